@@ -1,0 +1,258 @@
+"""Seeded synthetic inputs shared by the HIP path's tests/bench and the oracle's.
+
+This module holds no arithmetic of the method (no CV, bias or force); it only
+builds atom positions, external forces and hill centres from seeds, plus the
+parameter sets of the standard workloads.  Both sides read the same FP32
+positions; the oracle promotes them to FP64.
+
+Workloads (the GaN-like and Cu-like systems stand in for the paper's GaN NEP
+runs and benchmarks, whose datasets and trained potentials are not available):
+
+* ``fcc864``   fcc 6x6x6 cells, a = 3.615 A, jitter N(0, 0.1 A); coordination CV,
+               FP64; 1-D well-tempered bias from 1,000 hills.
+* ``wz96k``    wurtzite 40x40x15 hexagonal cells as a 40x20x15 orthohexagonal
+               grid (8 atoms each); lower z half crystal (jitter 0.05 A), upper
+               half random sequential addition at the same density with a
+               1.6 A minimum distance; q6 crystalline count, 10,000 hills.
+* ``wz1m``     the same recipe at 80x40x40 orthohexagonal cells, 1,024,000 atoms,
+               50,000 hills, external forces N(0, 1 eV/A).
+* ``wz2048``   8x4x8 slab, 2-D CV (coordination + q6 count), 5,000 hills.
+* ``wz262k``   64x32x16 orthohexagonal crystal slab, 2-D CV, timing size.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+
+# 1.2 kJ/mol expressed in eV, and k_B T at 300 K in kJ/mol and in eV.
+KJMOL_PER_EV = 96.48533212
+KB_EV = 8.617333262e-5
+KB_KJMOL = 0.0083144626
+
+
+def _cache_dir():
+    d = os.environ.get("GPUMETAD_CACHE", "/tmp/gpumetad_inputs")
+    os.makedirs(d, exist_ok=True)
+    return d
+
+
+def _cached(tag: str, spec: dict, fn):
+    key = hashlib.sha1(json.dumps(spec, sort_keys=True).encode()).hexdigest()[:16]
+    path = os.path.join(_cache_dir(), f"{tag}_{key}.npz")
+    if os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            return {k: z[k] for k in z.files}
+    out = fn()
+    tmp = path + ".tmp%d.npz" % os.getpid()
+    np.savez(tmp, **out)
+    os.replace(tmp, path)
+    return out
+
+
+def _wrap_f32(x: np.ndarray, box: np.ndarray) -> np.ndarray:
+    """Wrap into [0, L), round to FP32; a value that rounds up to L becomes 0."""
+    w = np.mod(x, box)
+    f = w.astype(np.float32)
+    for a in range(3):
+        col = f[:, a]
+        col[col.astype(np.float64) >= box[a]] = np.float32(0.0)
+        col[col < 0] = np.float32(0.0)
+    return f
+
+
+# --------------------------------------------------------------------------
+# Lattices
+# --------------------------------------------------------------------------
+def fcc_ideal(n: int, a: float):
+    """Ideal fcc positions (4 n^3 atoms) and the cubic box."""
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    g = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 3)
+    pos = (g[:, None, :] + basis[None, :, :]).reshape(-1, 3) * a
+    return pos, np.array([n * a] * 3, dtype=np.float64)
+
+
+def wurtzite_ortho_cell(a: float, c: float, u: float):
+    """8-atom orthohexagonal wurtzite cell (a, a*sqrt3, c); species 0 (Ga), 1 (N)."""
+    s3 = np.sqrt(3.0)
+    ga = np.array([[0.0, a * s3 / 3.0, 0.0],
+                   [a / 2.0, a * s3 / 6.0, c / 2.0],
+                   [a / 2.0, 5.0 * a * s3 / 6.0, 0.0],
+                   [0.0, 2.0 * a * s3 / 3.0, c / 2.0]])
+    n = ga + np.array([0.0, 0.0, u * c])
+    pos = np.concatenate([ga, n])
+    species = np.array([0] * 4 + [1] * 4, dtype=np.int32)
+    return pos, species, np.array([a, a * s3, c])
+
+
+def wurtzite_ideal(nx: int, ny: int, nz: int, a=3.19, c=5.19, u=0.377):
+    """Ideal wurtzite on an nx x ny x nz grid of orthohexagonal cells."""
+    cell, sp, L = wurtzite_ortho_cell(a, c, u)
+    g = np.stack(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"), -1).reshape(-1, 3)
+    pos = (g[:, None, :] * L[None, None, :] + cell[None, :, :]).reshape(-1, 3)
+    species = np.tile(sp, g.shape[0])
+    return pos, species, L * np.array([nx, ny, nz], dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# Random sequential addition
+# --------------------------------------------------------------------------
+def rsa_fill(fixed: np.ndarray, n_new: int, box: np.ndarray, zlo: float, zhi: float,
+             dmin: float, rng: np.random.Generator, batch: int = 60000) -> np.ndarray:
+    """Place n_new points uniformly in z in [zlo, zhi), one after another, each
+    accepted only if it is at least dmin (periodic) from every point already
+    placed, fixed points included.  Candidates are drawn in batches; inside a
+    batch they are accepted greedily in draw order, which is the sequential rule."""
+    from scipy.spatial import cKDTree
+
+    if n_new == 0:
+        return np.zeros((0, 3))
+    span = np.array([box[0], box[1], zhi - zlo])
+    lo = np.array([0.0, 0.0, zlo])
+    # Only fixed points within dmin of the slab (through periodic z) can interfere.
+    zf = np.mod(fixed[:, 2], box[2])
+    inside = (zf >= zlo) & (zf < zhi)
+    below = np.mod(zlo - zf, box[2]) < dmin
+    above = np.mod(zf - zhi, box[2]) < dmin
+    constraint = np.mod(fixed[inside | below | above], box)
+    placed = []
+    n_acc = 0
+    while n_acc < n_new:
+        pts = np.concatenate([constraint] + placed) if placed else constraint
+        tree = cKDTree(np.mod(pts, box), boxsize=box)
+        nb = int(min(batch, max(256, 2 * (n_new - n_acc))))
+        cand = lo + rng.random((nb, 3)) * span
+        cand[:, 2] = np.minimum(cand[:, 2], np.nextafter(zhi, zlo))
+        d, _ = tree.query(cand, k=1, distance_upper_bound=dmin)
+        surv = cand[~(d < dmin)]
+        if surv.shape[0] == 0:
+            continue
+        pairs = cKDTree(surv, boxsize=box).query_pairs(dmin, output_type="ndarray")
+        ok = np.ones(surv.shape[0], dtype=bool)
+        if pairs.size:
+            pairs = pairs[np.argsort(pairs[:, 1], kind="stable")]
+            for i, j in pairs:
+                if ok[i]:
+                    ok[j] = False
+        acc = surv[ok][: n_new - n_acc]
+        placed.append(acc)
+        n_acc += acc.shape[0]
+    return np.concatenate(placed)
+
+
+def wurtzite_slab(nx, ny, nz, a=3.19, c=5.19, u=0.377, jitter=0.05, dmin=1.6, seed=0,
+                  random_half=True):
+    """Wurtzite slab: atoms whose ideal z < Lz/2 keep the crystal sites plus
+    N(0, jitter) noise; the rest are replaced by random sequential addition in
+    [Lz/2, Lz) at the same count (so N and the density are unchanged)."""
+    spec = dict(kind="wz_slab", nx=nx, ny=ny, nz=nz, a=a, c=c, u=u, jitter=jitter, dmin=dmin,
+                seed=seed, random_half=random_half, v=3)
+
+    def make():
+        rng = np.random.default_rng(seed)
+        ideal, species, box = wurtzite_ideal(nx, ny, nz, a, c, u)
+        pos = ideal + rng.normal(0.0, jitter, ideal.shape)
+        if random_half:
+            crystal = ideal[:, 2] < box[2] / 2.0
+            n_rand = int((~crystal).sum())
+            keep = np.mod(pos[crystal], box)
+            rnd = rsa_fill(keep, n_rand, box, box[2] / 2.0, box[2], dmin, rng)
+            pos = np.concatenate([pos[crystal], rnd])
+            species = np.concatenate([species[crystal], species[~crystal]])
+            n_crystal = int(crystal.sum())
+        else:
+            n_crystal = pos.shape[0]
+        return dict(pos=_wrap_f32(pos, box), species=species.astype(np.int32), box=box,
+                    n_crystal=np.array(n_crystal))
+
+    return _cached("wz", spec, make)
+
+
+def fcc_jittered(n=6, a=3.615, jitter=0.1, seed=1):
+    spec = dict(kind="fcc", n=n, a=a, jitter=jitter, seed=seed, v=1)
+
+    def make():
+        rng = np.random.default_rng(seed)
+        ideal, box = fcc_ideal(n, a)
+        pos = ideal + rng.normal(0.0, jitter, ideal.shape)
+        return dict(pos=_wrap_f32(pos, box), species=np.zeros(pos.shape[0], np.int32), box=box,
+                    n_crystal=np.array(pos.shape[0]))
+
+    return _cached("fcc", spec, make)
+
+
+def as_float4(pos: np.ndarray, species: np.ndarray | None = None) -> np.ndarray:
+    """(N, 4) float32: x, y, z and the species id in the fourth lane."""
+    out = np.zeros((pos.shape[0], 4), np.float32)
+    out[:, :3] = pos[:, :3]
+    if species is not None:
+        out[:, 3] = species.astype(np.float32)
+    return out
+
+
+def external_forces(n: int, sigma: float = 1.0, seed: int = 4) -> np.ndarray:
+    """(N, 4) float32 forces from the interatomic potential stand-in: N(0, sigma)."""
+    rng = np.random.default_rng(seed)
+    f = np.zeros((n, 4), np.float32)
+    f[:, :3] = rng.normal(0.0, sigma, (n, 3)).astype(np.float32)
+    return f
+
+
+def hill_centres(k: int, lo, hi, seed: int) -> np.ndarray:
+    """(K, dims) float64 centres drawn uniformly in [lo, hi) per dimension, in
+    deposition order."""
+    lo = np.atleast_1d(np.asarray(lo, dtype=np.float64))
+    hi = np.atleast_1d(np.asarray(hi, dtype=np.float64))
+    rng = np.random.default_rng(seed)
+    return lo + rng.random((k, lo.shape[0])) * (hi - lo)
+
+
+# --------------------------------------------------------------------------
+# Standard workloads: geometry recipe + CV / bias parameters
+# --------------------------------------------------------------------------
+W0_EV = 1.2 / KJMOL_PER_EV
+KBT_EV = KB_EV * 300.0
+KBT_KJMOL = KB_KJMOL * 300.0
+
+Q6_CV = dict(r_c=3.6, skin=0.4, taper=0.2, bond_d0=0.7, bond_w=0.02, count_n0=5.5, count_w=0.25)
+
+WORKLOADS = {
+    "fcc864": dict(structure=dict(kind="fcc", n=6, a=3.615, jitter=0.1, seed=1),
+                   cv="coord", precision="fp64", r_c=6.0, skin=0.5, cn_r0=3.0, taper=0.0,
+                   hills=dict(k=1000, lo=[0.0], hi=[14.0], seed=11), sigma=[0.1],
+                   w0=1.2, gamma=10.0, kBT=KBT_KJMOL),
+    "wz96k": dict(structure=dict(kind="wz", nx=40, ny=20, nz=15, seed=2),
+                  cv="q6", precision="fp32", **Q6_CV, cn_r0=2.5,
+                  hills=dict(k=10000, lo=[0.0], hi=[96000.0], seed=12), sigma=[20.0],
+                  w0=W0_EV, gamma=10.0, kBT=KBT_EV),
+    "wz1m": dict(structure=dict(kind="wz", nx=80, ny=40, nz=40, seed=3),
+                 cv="q6", precision="fp32", **Q6_CV, cn_r0=2.5,
+                 hills=dict(k=50000, lo=[0.0], hi=[1.02e6], seed=13), sigma=[200.0],
+                 w0=W0_EV, gamma=10.0, kBT=KBT_EV, force_seed=4),
+    "wz2048": dict(structure=dict(kind="wz", nx=8, ny=4, nz=8, seed=5),
+                   cv="coord_q6", precision="fp32", **Q6_CV, cn_r0=2.5,
+                   hills=dict(k=5000, centre_rel=10.0, seed=15), sigma=[0.05, 20.0],
+                   w0=W0_EV, gamma=10.0, kBT=KBT_EV),
+    "wz262k": dict(structure=dict(kind="wz", nx=64, ny=32, nz=16, seed=6),
+                   cv="coord_q6", precision="fp32", **Q6_CV, cn_r0=2.5,
+                   hills=dict(k=5000, centre_rel=10.0, seed=16), sigma=[0.05, 20.0],
+                   w0=W0_EV, gamma=10.0, kBT=KBT_EV),
+}
+
+
+def structure(spec: dict):
+    """Positions (N,3) float32, species, box, n_crystal for a structure spec."""
+    s = dict(spec)
+    kind = s.pop("kind")
+    if kind == "fcc":
+        return fcc_jittered(**s)
+    if kind == "wz":
+        return wurtzite_slab(**s)
+    raise ValueError(kind)
+
+
+def small_wurtzite_slab(nx=4, ny=3, nz=6, seed=21, jitter=0.05):
+    """A small slab (a few hundred atoms) with crystal and random halves."""
+    return wurtzite_slab(nx, ny, nz, jitter=jitter, seed=seed)
