@@ -1,0 +1,255 @@
+"""Throughput of the per-step metadynamics bias pipeline on one MI355X.
+
+A bench step is one window of the hot path at 1,024,000 atoms (wurtzite
+GaN-like slab, q6 crystalline-count CV, 50,000 deposited hills, external
+forces N(0, 1 eV/A)):
+    1 x build_neighbors
+    10 x (cv_forward, bias_eval, cv_backward, apply_bias_forces)
+    1 x deposit_hill
+i.e. 10 MD steps = 10 N atom-steps.  Inputs are resident in HBM before the
+timed region.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--graph] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+MD_STEPS_PER_WINDOW = 10
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed FP32: 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="wz1m")
+    ap.add_argument("--graph", action="store_true", help="replay each window as a captured HIP graph")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def setup(wl_name):
+    import torch
+
+    import workloads as W
+    from paper_2510_06873_amd import FP32, FP64, Params, Pipeline
+
+    wl = W.WORKLOADS[wl_name]
+    d = W.structure(wl["structure"])
+    n = d["pos"].shape[0]
+    kind = {"coord": 1, "q6": 2, "coord_q6": 3}[wl["cv"]]
+    prm = Params(cv_kind=kind, precision=FP64 if wl["precision"] == "fp64" else FP32, r_c=wl["r_c"],
+                 skin=wl["skin"], taper=wl.get("taper") or 0.2, cn_r0=wl["cn_r0"], bond_d0=wl.get("bond_d0", 0.7),
+                 bond_w=wl.get("bond_w", 0.02), count_n0=wl.get("count_n0", 5.5), count_w=wl.get("count_w", 0.25),
+                 sigma=wl["sigma"], w0=wl["w0"], gamma=wl["gamma"], kBT=wl["kBT"],
+                 hill_capacity=wl["hills"]["k"] + 1024, max_neighbors=48)
+    stream = torch.cuda.Stream()
+    dev = torch.device("cuda", 0)
+    with torch.cuda.stream(stream):
+        pipe = Pipeline(n, prm, stream=stream)
+        pos4 = torch.from_numpy(W.as_float4(d["pos"], d["species"])).to(dev)
+        F_in = torch.from_numpy(W.external_forces(n, seed=wl.get("force_seed", 4))).to(dev)
+        if prm.precision == FP64:
+            F_in = F_in.double()
+        F = F_in.clone()
+        pipe.build_neighbors_checked(pos4, d["box"])
+        hp = wl["hills"]
+        if "lo" in hp:
+            cen = W.hill_centres(hp["k"], hp["lo"], hp["hi"], hp["seed"])
+        else:
+            s0 = pipe.cv_forward(pos4).cpu().numpy()
+            sig = np.array(wl["sigma"])
+            cen = W.hill_centres(hp["k"], s0 - hp["centre_rel"] * sig, s0 + hp["centre_rel"] * sig, hp["seed"])
+        cdev = torch.from_numpy(cen).to(dev)
+        t = time.time()
+        for k in range(cen.shape[0]):
+            pipe.deposit_hill(cdev[k])
+        stream.synchronize()
+        log(f"[bench] {wl_name}: N={n}, hills deposited: {cen.shape[0]} in {time.time() - t:.1f}s")
+        pipe.check()
+    return dict(wl=wl, d=d, n=n, pipe=pipe, pos4=pos4, F=F, stream=stream, cen=cen, box=d["box"])
+
+
+def window(S, ev=None):
+    """One window; ev collects (name, start, end) event pairs."""
+    import torch
+
+    pipe, pos4, F, box = S["pipe"], S["pos4"], S["F"], S["box"]
+
+    def timed(name, fn, *a):
+        if ev is None:
+            fn(*a)
+            return
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(S["stream"])
+        fn(*a)
+        e1.record(S["stream"])
+        ev.append((name, e0, e1))
+
+    timed("build_neighbors", pipe.build_neighbors, pos4, box)
+    for _ in range(MD_STEPS_PER_WINDOW):
+        timed("cv_forward", pipe.cv_forward, pos4)
+        timed("bias_eval", pipe.bias_eval)
+        timed("cv_backward", pipe.cv_backward, pos4)
+        timed("apply_bias_forces", pipe.apply_bias_forces, pos4, F)
+    timed("deposit_hill", pipe.deposit_hill)
+
+
+def neighbor_pairs(S):
+    """Total list entries and pairs inside r_c (for the per-launch work model)."""
+    pipe = S["pipe"]
+    _, total = pipe.neighbor_stats()
+    return total
+
+
+def cpu_baseline(wl_name="wz96k"):
+    """The oracle as it stands, single threaded, on the same recipe at 96,000
+    atoms: one neighbour build amortised over 10 steps plus one step of
+    forward, gradient, bias and force."""
+    import oracle as orc
+    import workloads as W
+
+    wl = W.WORKLOADS[wl_name]
+    d = W.structure(wl["structure"])
+    pos, box = d["pos"], d["box"]
+    n = pos.shape[0]
+    prm = orc.q6_params(wl["r_c"], wl["taper"], wl["bond_d0"], wl["bond_w"], wl["count_n0"], wl["count_w"])
+    hp = wl["hills"]
+    cen = W.hill_centres(min(hp["k"], 2000), hp["lo"], hp["hi"], hp["seed"])
+    hts = np.full(cen.shape[0], wl["w0"])
+    t_nl = t_step = 0.0
+    reps = 0
+    t_all = time.time()
+    while reps < 1 or time.time() - t_all < 10.0:
+        t0 = time.time()
+        nl = orc.neighbors(pos, box, wl["r_c"] + wl["skin"])
+        t1 = time.time()
+        s = orc.q6_forward(pos, box, nl, prm)["s"]
+        _, dv = orc.bias(cen, hts, wl["sigma"], [s])
+        g = orc.q6_gradient(pos, box, nl, prm)
+        orc.bias_forces(W.external_forces(n, seed=4), [g], dv)
+        t2 = time.time()
+        t_nl += t1 - t0
+        t_step += t2 - t1
+        reps += 1
+    per_step = (t_nl / MD_STEPS_PER_WINDOW + t_step) / reps
+    return {"value": n / per_step, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{wl_name}: {n} atoms (same slab recipe as the 1,024,000-atom workload), "
+                      f"{reps} x (neighbour build / 10 + q6 forward + q6 gradient + bias + forces), "
+                      f"FP64, single thread, {time.time() - t_all:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+
+    S = setup(args.workload)
+    n = S["n"]
+    stream = S["stream"]
+    graph = None
+    if args.graph:
+        # capture one window; the hill count lives on the device, so replays keep depositing
+        with torch.cuda.stream(stream):
+            window(S)
+            stream.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=stream):
+                window(S)
+        log("[bench] captured one window as a HIP graph")
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            graph.replay() if graph is not None else window(S)
+        stream.synchronize()
+        S["pipe"].check()
+        log(f"[bench] warmup done ({args.warmup} windows)")
+        ev = [] if graph is None else None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e_start = torch.cuda.Event(enable_timing=True)
+        e_stop = torch.cuda.Event(enable_timing=True)
+        e_start.record(stream)
+        for _ in range(args.steps):
+            if graph is not None:
+                graph.replay()
+            else:
+                window(S, ev)
+        e_stop.record(stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    S["pipe"].check()
+    gpu_ms = e_start.elapsed_time(e_stop)
+    ms_per_window = gpu_ms / args.steps
+    atom_steps = n * MD_STEPS_PER_WINDOW * args.steps
+    value = atom_steps / (gpu_ms / 1e3)
+    log(f"[bench] {args.steps} windows: {gpu_ms:.2f} ms GPU, {wall * 1e3:.2f} ms wall")
+
+    per_call = {}
+    if ev:
+        for name, e0, e1 in ev:
+            per_call.setdefault(name, []).append(e0.elapsed_time(e1))
+    per_call_us = {k: 1e3 * float(np.mean(v)) for k, v in per_call.items()}
+
+    total_entries = neighbor_pairs(S)
+    # apply_bias_forces is one launch of the force kernel (the dominant kernel).
+    # Algorithmic HBM bytes per atom for that launch: own position 16, own
+    # adjoint row 64, row length 4, permutation 4, force read+write 32, and its
+    # neighbour row 4 per entry (neighbour rows of q-hat/adjoint assumed cached).
+    force_bytes = n * (16 + 64 + 4 + 4 + 32) + 4 * total_entries
+    roofline = None
+    if "apply_bias_forces" in per_call_us:
+        t_us = per_call_us["apply_bias_forces"]
+        achieved = force_bytes / (t_us * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "k_q6_p4 (apply_bias_forces)", "avg_launch_us": round(t_us, 2),
+                    "bytes_per_launch": int(force_bytes)}
+    out = {
+        "metric": "atom-steps/s for q6-CV+bias+force at 1.02M atoms (%HBM roofline)",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_window,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 CV sum and hill sums)",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: wurtzite GaN-like slab, {n} atoms (half crystal, half RSA), "
+                               f"q6 crystalline-count CV, r_c 3.6 + skin 0.4, {S['cen'].shape[0]} hills, "
+                               f"window = 1 rebuild + 10 x (cv_forward, bias_eval, cv_backward, "
+                               f"apply_bias_forces) + 1 deposit",
+                   "atoms": n, "md_steps_per_step": MD_STEPS_PER_WINDOW, "graph": bool(args.graph),
+                   "neighbor_entries": int(total_entries)},
+        "per_call_us": {k: round(v, 2) for k, v in per_call_us.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        log("[bench] timing the oracle on the host cores ...")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * gpumetad -- the per-step metadynamics bias pipeline on one AMD MI355X (gfx950).
+ *
+ * What the pipeline computes (paper: Methods, "Metadynamics Method"):
+ *   the biased potential U_b = U_0 + V_b, with V_b a sum of Gaussian hills
+ *   deposited at visited CV values.  The interatomic potential U_0 is not
+ *   computed here: its forces arrive as an array, and the library adds the bias
+ *   forces -dV_b/dx to it, which is the job the paper's GPUMD interface does each
+ *   MD step (Results, "Frameworks of GPU-MetaD": the interface extracts the MD
+ *   state, computes CVs and bias-driven forces on the GPU, and returns them).
+ *
+ * One context (gm_ctx) holds one system of N atoms, its cell and neighbour
+ * lists, the per-atom intermediates of the collective variables, and the
+ * device-resident hill history.  A timed MD step is
+ *
+ *     gm_cv_forward -> gm_bias_eval -> gm_cv_backward -> gm_apply_bias_forces
+ *
+ * with gm_build_neighbors every few steps and gm_deposit_hill at the
+ * deposition pace.  Every call validates its arguments on the host, ENQUEUES
+ * its kernels on the context's HIP stream and returns; none synchronises except
+ * the calls marked "synchronous".  Scalars (s, V, dV/ds) stay in device memory,
+ * so a whole window of steps can be captured in a HIP graph.
+ *
+ * Pointer conventions
+ *   "dev"  : device memory (e.g. from hipMalloc), owned by the caller,
+ *            read or written only by the enqueued kernels, never kept past the call.
+ *   "host" : host memory, read or written before the call returns.
+ *   Positions are always float32 [N][4] (x, y, z, w; w is ignored), 16-byte
+ *   aligned, in the caller's atom order.  Force and gradient arrays are [N][4]
+ *   of float32 (GM_FP32) or float64 (GM_FP64); their fourth lane is untouched.
+ *   Lengths in Angstrom; energies in the unit of w0 and kBT (forces in
+ *   energy/Angstrom).  The box is orthorhombic and periodic.
+ *
+ * Errors: every call returns GM_OK (0) or a negative GM_ERR_* code and never
+ * throws.  Conditions only the device can see (neighbour overflow, a full hill
+ * buffer, a non-finite CV, bias or force) set a sticky device error word that
+ * gm_status() reads and clears.
+ *
+ * Threading: a context is not thread safe; use one context per stream.
+ */
+#ifndef GPUMETAD_H
+#define GPUMETAD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------- */
+#define GM_OK 0
+#define GM_ERR_INVALID_ARG (-1)       /* null or misaligned pointer, bad size or parameter */
+#define GM_ERR_OOM (-2)               /* a device allocation failed */
+#define GM_ERR_HIP (-3)               /* a HIP runtime call or launch failed */
+#define GM_ERR_BOX_TOO_SMALL (-4)     /* fewer than 3 cells of width >= r_c + skin on an axis */
+#define GM_ERR_NEIGHBOR_OVERFLOW (-5) /* sticky: an atom has more than max_neighbors neighbours */
+#define GM_ERR_HILL_CAPACITY (-6)     /* sticky: deposit into a full hill buffer */
+#define GM_ERR_NONFINITE (-7)         /* sticky: NaN/Inf position, CV, bias or force */
+#define GM_ERR_STATE (-8)             /* call order violated (see each call) */
+
+/* ---- collective variables ----------------------------------------------- */
+/* GM_CV_COORD   s = (1/N) sum_i sum_{j: r_ij < r_c} 1/(1 + (r_ij/r0)^6)
+ *               (the coordination number; paper, Results, GaN study).
+ * GM_CV_Q6COUNT s = sum_i c_i, the smooth count of crystalline atoms from
+ *               Steinhardt q6 (l = 6) bond order:
+ *                 Q_i  = sum_{j: r_ij < r_c} f(r_ij) Y_6(r_hat_ij)  (13 reals)
+ *                 d_ij = Q_i.Q_j / (|Q_i| |Q_j|)
+ *                 n_i  = sum_j f(r_ij) / (1 + exp(-(d_ij - bond_d0)/bond_w))
+ *                 c_i  = 1 / (1 + exp(-(n_i - count_n0)/count_w))
+ *               with f = 1 below r_c - taper and a cosine taper to 0 at r_c.
+ * GM_CV_COORD_Q6 the 2-D CV s = (s_COORD, s_Q6COUNT) over the same r_c.      */
+#define GM_CV_COORD 1
+#define GM_CV_Q6COUNT 2
+#define GM_CV_COORD_Q6 3
+
+#define GM_FP32 0
+#define GM_FP64 1
+
+typedef struct gm_params {
+  int32_t cv_kind;       /* GM_CV_*                                           */
+  int32_t precision;     /* GM_FP32 or GM_FP64 for the per-atom arithmetic;
+                            global CV sums and all hill arithmetic are FP64   */
+  double r_c;            /* CV cutoff, Angstrom                               */
+  double skin;           /* Verlet skin: neighbour lists hold r < r_c + skin  */
+  double taper;          /* q6 weight taper width (0 < taper <= r_c)          */
+  double cn_r0;          /* coordination switch length r0                     */
+  double bond_d0, bond_w;   /* bond sigmoid centre and width (q6 dot)         */
+  double count_n0, count_w; /* count sigmoid centre and width (bonds)         */
+  double sigma[2];       /* Gaussian hill widths per CV dimension             */
+  double w0;             /* initial hill height                               */
+  double gamma;          /* well-tempered bias factor (> 1); 0 = plain metad  */
+  double kBT;            /* k_B T in the energy unit of w0                    */
+  int64_t hill_capacity; /* maximum number of hills kept on the device        */
+  int32_t max_neighbors; /* neighbour-list row width (rounded up to 4)        */
+  int32_t reserved;      /* must be 0                                         */
+} gm_params;
+
+typedef struct gm_ctx gm_ctx;
+
+/* Create a context for n_atoms atoms whose kernels run on hip_stream
+ * (a HIP stream handle; NULL = the null stream).  Allocates every buffer the steps
+ * need (synchronous).  *out is set to NULL on failure. */
+int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_stream);
+
+/* Free everything the context owns (synchronous; waits for its stream). */
+int gm_destroy(gm_ctx* ctx);
+
+/* Re-bind the context to another stream (e.g. a capture stream). */
+int gm_set_stream(gm_ctx* ctx, void* hip_stream);
+
+/* Build the cell list (a stable counting sort of atoms by cell, cells of
+ * width >= r_c + skin) and the full neighbour lists
+ *   N(i) = { j != i : |mic(x_j - x_i)|^2 < (r_c + skin)^2 }
+ * with the distance test done in FP64 on the FP32 positions, no FMA.
+ * pos4: dev float32 [N][4].  box: host double[3] (Lx, Ly, Lz).
+ * Returns GM_ERR_BOX_TOO_SMALL if any axis holds fewer than 3 cells.
+ * Rows hold at most max_neighbors entries; a longer row sets the sticky
+ * GM_ERR_NEIGHBOR_OVERFLOW (grow with gm_reserve_neighbors and rebuild). */
+int gm_build_neighbors(gm_ctx* ctx, const float* pos4, const double* box);
+
+/* Evaluate the CV at pos4 (dev float32 [N][4], the same atoms as the last
+ * build, moved by less than skin/2).  s_dev: dev double[dims], written.
+ * GM_ERR_STATE before the first gm_build_neighbors. */
+int gm_cv_forward(gm_ctx* ctx, const float* pos4, double* s_dev);
+
+/* Bias and its CV gradient over the hills on the device
+ * (paper, Methods: V_b(s) = sum_tau w_tau exp(-(s - s_tau)^2 / (2 sigma^2)),
+ *  one Gaussian factor per CV dimension):
+ *   V = sum_k h_k exp(-sum_d (s_d - c_kd)^2 / (2 sigma_d^2))
+ *   dV/ds_d = -sum_k h_k exp(...) (s_d - c_kd) / sigma_d^2
+ * s_dev: dev double[dims] (read).  V_dev: dev double[1], dVds_dev: dev
+ * double[dims] (written; either may be NULL).  FP64 throughout; zero hills
+ * give V = 0. */
+int gm_bias_eval(gm_ctx* ctx, const double* s_dev, double* V_dev, double* dVds_dev);
+
+/* Adjoint of the last gm_cv_forward (same pos4).  Computes the per-atom
+ * adjoint state the force pass needs.  If grad4 != NULL it also writes
+ *   grad4[i] = sum_d seed_d ds_d/dx_i
+ * (dev [N][4] of the context precision, caller's atom order; lane 3 is left
+ * alone).  seed_dev: dev double[dims], read only when grad4 != NULL; NULL
+ * means seed 1 and is allowed with grad4 only when dims == 1.  GM_ERR_STATE
+ * if no gm_cv_forward since the last build. */
+int gm_cv_backward(gm_ctx* ctx, const float* pos4, const double* seed_dev, void* grad4);
+
+/* Add the bias force to force4 in place (dev [N][4] of the context precision,
+ * caller's atom order):
+ *   F_i <- F_i - sum_d dV/ds_d * ds_d/dx_i       (from U_b = U_0 + V_b)
+ * dVds_dev: dev double[dims], e.g. from gm_bias_eval.  GM_ERR_STATE unless
+ * gm_cv_backward ran since the last gm_cv_forward. */
+int gm_apply_bias_forces(gm_ctx* ctx, const float* pos4, const double* dVds_dev, void* force4);
+
+/* Deposit one hill at s_dev (dev double[dims]) with the well-tempered height
+ *   h = w0 exp(-V(s) / (kBT (gamma - 1)))     (gamma == 0: h = w0)
+ * where V(s) is the bias of the hills already deposited (Barducci, Bussi,
+ * Parrinello 2008; the paper names well-tempered metadynamics for its
+ * rutile study).  The hill count lives on the device, so the call can be
+ * replayed inside a graph; a full buffer sets the sticky GM_ERR_HILL_CAPACITY
+ * and deposits nothing. */
+int gm_deposit_hill(gm_ctx* ctx, const double* s_dev);
+
+/* Checkpoint the hill history (synchronous).  centres: host double[cap*dims],
+ * heights: host double[cap]; *k receives the hill count.  Either array may be
+ * NULL to query the count only.  GM_ERR_INVALID_ARG if cap < count. */
+int gm_hills_get(gm_ctx* ctx, double* centres, double* heights, int64_t cap, int64_t* k);
+
+/* Restore a hill history (synchronous).  centres: host double[k*dims],
+ * heights: host double[k], 0 <= k <= hill_capacity.  Bias sums run in hill
+ * index order, so a restored history reproduces V bit for bit. */
+int gm_hills_set(gm_ctx* ctx, const double* centres, const double* heights, int64_t k);
+
+/* Read and clear the sticky device error word.  sync != 0 waits for the
+ * stream first (synchronous); sync == 0 returns the code seen at the last
+ * synchronous check without touching the device. */
+int gm_status(gm_ctx* ctx, int sync);
+
+/* Text for a GM_* code (static storage). */
+const char* gm_strerror(int code);
+
+/* Largest row length and total entries of the last neighbour build
+ * (synchronous). */
+int gm_neighbor_stats(gm_ctx* ctx, int32_t* max_count, int64_t* total);
+
+/* Set the neighbour-list row width (rounded up to a multiple of 4) and
+ * reallocate; the lists must be rebuilt afterwards (synchronous). */
+int gm_reserve_neighbors(gm_ctx* ctx, int32_t max_neighbors);
+
+/* Copy the cell list of the last build (enqueued device-to-device copies):
+ * perm_dev: dev int32[N], the atom ids in sorted (cell, atom) order;
+ * cell_start_dev: dev int32[ncells + 1] (may be NULL); ncell: host int32[3]. */
+int gm_copy_cell_list(gm_ctx* ctx, int32_t* perm_dev, int32_t* cell_start_dev, int32_t* ncell);
+
+/* Copy the neighbour lists (enqueued): nbr_dev dev int32[N][row_width] whose
+ * row t lists the sorted positions (indices into perm) of the neighbours of
+ * the atom perm[t]; cnt_dev dev int32[N], the true row lengths;
+ * row_width: host int32. */
+int gm_copy_neighbors(gm_ctx* ctx, int32_t* nbr_dev, int32_t* cnt_dev, int32_t* row_width);
+
+/* Per-atom values of the last gm_cv_forward, caller's atom order, written as
+ * dev double[N] (enqueued):
+ *   GM_ATOM_Q6  Steinhardt q6_i = sqrt(4 pi/13) |Q_i| / sum_j f(r_ij)
+ *   GM_ATOM_NB  n_i, the weighted count of crystal-like bonds
+ *   GM_ATOM_C   c_i, the crystalline indicator
+ *   GM_ATOM_CN  sum_j 1/(1 + (r_ij/r0)^6), the per-atom coordination     */
+#define GM_ATOM_Q6 1
+#define GM_ATOM_NB 2
+#define GM_ATOM_C 3
+#define GM_ATOM_CN 4
+int gm_atom_values(gm_ctx* ctx, int what, double* dst_dev);
+
+/* Library version string. */
+const char* gm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPUMETAD_H */

@@ -1,0 +1,305 @@
+"""ctypes binding of libgpumetad (the C-ABI in include/gpumetad.h).
+
+Argument marshalling only: every step of the pipeline runs in the HIP library.
+Tensors are torch CUDA tensors (device memory and streams); their data
+pointers go straight to the C calls.  There is no CPU fallback: if the library
+is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgpumetad.so")
+
+GM_OK = 0
+ERRORS = {
+    -1: "GM_ERR_INVALID_ARG", -2: "GM_ERR_OOM", -3: "GM_ERR_HIP", -4: "GM_ERR_BOX_TOO_SMALL",
+    -5: "GM_ERR_NEIGHBOR_OVERFLOW", -6: "GM_ERR_HILL_CAPACITY", -7: "GM_ERR_NONFINITE", -8: "GM_ERR_STATE",
+}
+CV_COORD, CV_Q6COUNT, CV_COORD_Q6 = 1, 2, 3
+FP32, FP64 = 0, 1
+ATOM_Q6, ATOM_NB, ATOM_C, ATOM_CN = 1, 2, 3, 4
+
+# Every symbol include/gpumetad.h declares.
+EXPORTS = (
+    "gm_create", "gm_destroy", "gm_set_stream", "gm_build_neighbors", "gm_cv_forward", "gm_bias_eval",
+    "gm_cv_backward", "gm_apply_bias_forces", "gm_deposit_hill", "gm_hills_get", "gm_hills_set", "gm_status",
+    "gm_strerror", "gm_neighbor_stats", "gm_reserve_neighbors", "gm_copy_cell_list", "gm_copy_neighbors",
+    "gm_atom_values", "gm_version",
+)
+
+
+class GmError(RuntimeError):
+    def __init__(self, code: int, call: str):
+        self.code = code
+        msg = _lib.gm_strerror(code).decode() if _lib is not None else ""
+        super().__init__(f"{call}: {ERRORS.get(code, code)} ({msg})")
+
+
+class GmParams(C.Structure):
+    _fields_ = [
+        ("cv_kind", C.c_int32), ("precision", C.c_int32),
+        ("r_c", C.c_double), ("skin", C.c_double), ("taper", C.c_double), ("cn_r0", C.c_double),
+        ("bond_d0", C.c_double), ("bond_w", C.c_double), ("count_n0", C.c_double), ("count_w", C.c_double),
+        ("sigma", C.c_double * 2), ("w0", C.c_double), ("gamma", C.c_double), ("kBT", C.c_double),
+        ("hill_capacity", C.c_int64), ("max_neighbors", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_06873_amd.build` "
+                          "(hipcc, gfx950); there is no CPU fallback")
+    lib = C.CDLL(LIB_PATH)
+    vp, dp, ip32, ip64 = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    sig = {
+        "gm_create": ([C.POINTER(C.c_void_p), C.POINTER(GmParams), C.c_int64, vp], C.c_int),
+        "gm_destroy": ([vp], C.c_int),
+        "gm_set_stream": ([vp, vp], C.c_int),
+        "gm_build_neighbors": ([vp, vp, dp], C.c_int),
+        "gm_cv_forward": ([vp, vp, vp], C.c_int),
+        "gm_bias_eval": ([vp, vp, vp, vp], C.c_int),
+        "gm_cv_backward": ([vp, vp, vp, vp], C.c_int),
+        "gm_apply_bias_forces": ([vp, vp, vp, vp], C.c_int),
+        "gm_deposit_hill": ([vp, vp], C.c_int),
+        "gm_hills_get": ([vp, dp, dp, C.c_int64, ip64], C.c_int),
+        "gm_hills_set": ([vp, dp, dp, C.c_int64], C.c_int),
+        "gm_status": ([vp, C.c_int], C.c_int),
+        "gm_strerror": ([C.c_int], C.c_char_p),
+        "gm_neighbor_stats": ([vp, ip32, ip64], C.c_int),
+        "gm_reserve_neighbors": ([vp, C.c_int32], C.c_int),
+        "gm_copy_cell_list": ([vp, vp, vp, ip32], C.c_int),
+        "gm_copy_neighbors": ([vp, vp, vp, ip32], C.c_int),
+        "gm_atom_values": ([vp, C.c_int, vp], C.c_int),
+        "gm_version": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib: Optional[C.CDLL] = _load()
+
+
+def lib() -> C.CDLL:
+    return _lib
+
+
+def _check(rc: int, call: str):
+    if rc != GM_OK:
+        raise GmError(rc, call)
+
+
+def _ptr(t, numel: Optional[int] = None, dtype=None, name: str = "tensor") -> Optional[int]:
+    """Device pointer of a contiguous tensor, after checking its size and type."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name}: expected a device (CUDA/HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: expected at least {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+@dataclass
+class Params:
+    """Mirror of gm_params (see include/gpumetad.h)."""
+    cv_kind: int = CV_Q6COUNT
+    precision: int = FP32
+    r_c: float = 3.6
+    skin: float = 0.4
+    taper: float = 0.2
+    cn_r0: float = 2.5
+    bond_d0: float = 0.7
+    bond_w: float = 0.02
+    count_n0: float = 5.5
+    count_w: float = 0.25
+    sigma: Sequence[float] = field(default_factory=lambda: [20.0])
+    w0: float = 1.2
+    gamma: float = 10.0
+    kBT: float = 2.494
+    hill_capacity: int = 100000
+    max_neighbors: int = 64
+
+    @property
+    def dims(self) -> int:
+        return 2 if self.cv_kind == CV_COORD_Q6 else 1
+
+    def to_c(self) -> GmParams:
+        sig = list(self.sigma) + [0.0] * (2 - len(self.sigma))
+        return GmParams(self.cv_kind, self.precision, self.r_c, self.skin, self.taper, self.cn_r0,
+                        self.bond_d0, self.bond_w, self.count_n0, self.count_w, (C.c_double * 2)(*sig[:2]),
+                        self.w0, self.gamma, self.kBT, self.hill_capacity, self.max_neighbors, 0)
+
+
+class Pipeline:
+    """One gm_ctx: a system of n atoms, its lists, CV state and hill history."""
+
+    def __init__(self, n_atoms: int, params: Params, stream=None):
+        import torch
+
+        self.torch = torch
+        self.params = params
+        self.n = int(n_atoms)
+        self.dims = params.dims
+        self.fdtype = torch.float64 if params.precision == FP64 else torch.float32
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._cp = params.to_c()
+        h = C.c_void_p()
+        _check(_lib.gm_create(C.byref(h), C.byref(self._cp), self.n, C.c_void_p(self.stream.cuda_stream)),
+               "gm_create")
+        self.h = h
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.s = torch.zeros(self.dims, dtype=torch.float64, device=dev)
+        self.V = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.dVds = torch.zeros(self.dims, dtype=torch.float64, device=dev)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.gm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(_lib.gm_set_stream(self.h, C.c_void_p(stream.cuda_stream)), "gm_set_stream")
+
+    # ---- the six pipeline calls --------------------------------------------
+    def _pos(self, pos4):
+        return _ptr(pos4, 4 * self.n, self.torch.float32, "pos4")
+
+    def _vec(self, t, name):
+        return _ptr(t, self.dims, self.torch.float64, name)
+
+    def _arr4(self, t, name):
+        return _ptr(t, 4 * self.n, self.fdtype, name)
+
+    def build_neighbors(self, pos4, box):
+        box_c = (C.c_double * 3)(*[float(b) for b in box])
+        _check(_lib.gm_build_neighbors(self.h, self._pos(pos4), box_c), "gm_build_neighbors")
+
+    def cv_forward(self, pos4, s=None):
+        s = self.s if s is None else s
+        _check(_lib.gm_cv_forward(self.h, self._pos(pos4), self._vec(s, "s")), "gm_cv_forward")
+        return s
+
+    def bias_eval(self, s=None, V=None, dVds=None):
+        s = self.s if s is None else s
+        V = self.V if V is None else V
+        dVds = self.dVds if dVds is None else dVds
+        _check(_lib.gm_bias_eval(self.h, self._vec(s, "s"), _ptr(V, 1, self.torch.float64, "V"),
+                                 self._vec(dVds, "dVds")), "gm_bias_eval")
+        return V, dVds
+
+    def cv_backward(self, pos4, seed=None, grad4=None):
+        _check(_lib.gm_cv_backward(self.h, self._pos(pos4), self._vec(seed, "seed"), self._arr4(grad4, "grad4")),
+               "gm_cv_backward")
+        return grad4
+
+    def apply_bias_forces(self, pos4, force4, dVds=None):
+        dVds = self.dVds if dVds is None else dVds
+        _check(_lib.gm_apply_bias_forces(self.h, self._pos(pos4), self._vec(dVds, "dVds"),
+                                         self._arr4(force4, "force4")), "gm_apply_bias_forces")
+        return force4
+
+    def deposit_hill(self, s=None):
+        s = self.s if s is None else s
+        _check(_lib.gm_deposit_hill(self.h, self._vec(s, "s")), "gm_deposit_hill")
+
+    # ---- one MD step's bias pipeline ---------------------------------------
+    def step(self, pos4, force4):
+        self.cv_forward(pos4)
+        self.bias_eval()
+        self.cv_backward(pos4)
+        self.apply_bias_forces(pos4, force4)
+
+    # ---- state, checkpoint, inspection -------------------------------------
+    def status(self, sync: bool = True) -> int:
+        return _lib.gm_status(self.h, 1 if sync else 0)
+
+    def check(self):
+        _check(self.status(True), "gm_status")
+
+    def hills_get(self):
+        import numpy as np
+
+        k = C.c_int64()
+        _check(_lib.gm_hills_get(self.h, None, None, 0, C.byref(k)), "gm_hills_get")
+        K = k.value
+        cen = np.zeros((max(K, 1), self.dims))
+        hts = np.zeros(max(K, 1))
+        _check(_lib.gm_hills_get(self.h, cen.ctypes.data_as(C.POINTER(C.c_double)),
+                                 hts.ctypes.data_as(C.POINTER(C.c_double)), max(K, 1), C.byref(k)), "gm_hills_get")
+        return cen[:K], hts[:K]
+
+    def hills_set(self, centres, heights):
+        import numpy as np
+
+        cen = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, self.dims)
+        hts = np.ascontiguousarray(heights, dtype=np.float64)
+        _check(_lib.gm_hills_set(self.h, cen.ctypes.data_as(C.POINTER(C.c_double)),
+                                 hts.ctypes.data_as(C.POINTER(C.c_double)), hts.shape[0]), "gm_hills_set")
+
+    def neighbor_stats(self):
+        m = C.c_int32()
+        t = C.c_int64()
+        _check(_lib.gm_neighbor_stats(self.h, C.byref(m), C.byref(t)), "gm_neighbor_stats")
+        return m.value, t.value
+
+    def reserve_neighbors(self, kmax: int):
+        _check(_lib.gm_reserve_neighbors(self.h, int(kmax)), "gm_reserve_neighbors")
+
+    def build_neighbors_checked(self, pos4, box):
+        """Build; on a neighbour-list overflow grow the rows and rebuild (synchronises)."""
+        self.build_neighbors(pos4, box)
+        rc = self.status(True)
+        if rc == -5:
+            m, _ = self.neighbor_stats()
+            self.reserve_neighbors(m + 8)
+            self.build_neighbors(pos4, box)
+            rc = self.status(True)
+        _check(rc, "gm_build_neighbors")
+
+    def cell_list(self):
+        torch = self.torch
+        perm = torch.empty(self.n, dtype=torch.int32, device=self.s.device)
+        nc = (C.c_int32 * 3)()
+        _check(_lib.gm_copy_cell_list(self.h, _ptr(perm), None, nc), "gm_copy_cell_list")
+        ncells = nc[0] * nc[1] * nc[2]
+        start = torch.empty(ncells + 1, dtype=torch.int32, device=self.s.device)
+        _check(_lib.gm_copy_cell_list(self.h, _ptr(perm), _ptr(start), nc), "gm_copy_cell_list")
+        return (nc[0], nc[1], nc[2]), perm, start
+
+    def neighbor_lists(self):
+        torch = self.torch
+        w = C.c_int32()
+        _check(_lib.gm_copy_neighbors(self.h, None, None, C.byref(w)), "gm_copy_neighbors")
+        nbr = torch.empty((self.n, w.value), dtype=torch.int32, device=self.s.device)
+        cnt = torch.empty(self.n, dtype=torch.int32, device=self.s.device)
+        _check(_lib.gm_copy_neighbors(self.h, _ptr(nbr), _ptr(cnt), C.byref(w)), "gm_copy_neighbors")
+        return nbr, cnt
+
+    def atom_values(self, what: int):
+        out = self.torch.empty(self.n, dtype=self.torch.float64, device=self.s.device)
+        _check(_lib.gm_atom_values(self.h, int(what), _ptr(out, self.n, self.torch.float64, "out")),
+               "gm_atom_values")
+        return out
+
+
+def version() -> str:
+    return _lib.gm_version().decode()

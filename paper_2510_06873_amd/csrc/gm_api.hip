@@ -1,0 +1,540 @@
+// C-ABI of libgpumetad: context, argument validation, call-order state and
+// the enqueueing of the kernels in gm_kernels.hip.  No C++ exception crosses
+// the boundary; every entry point returns a GM_* code.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "gm_internal.h"
+
+using namespace gm;
+
+struct gm_ctx {
+  gm_params p;
+  int64_t n = 0;
+  hipStream_t stream = nullptr;
+  int dims = 1;
+  bool fp64 = false;
+  bool has_q6 = false, has_cn = false;
+  double r_list = 0.0;
+  double box[3] = {0, 0, 0};
+  CellGeom geom;
+  int64_t ncells = 0, ncells_cap = 0;
+  int32_t kmax = 0;
+  int64_t blocks = 0;
+  int bias_blocks = 0;
+
+  int32_t *cell = nullptr, *count = nullptr, *start = nullptr, *fill = nullptr, *perm = nullptr;
+  int32_t *nbr = nullptr, *cnt = nullptr, *err = nullptr, *stats = nullptr;
+  void *pos_s = nullptr, *qrow = nullptr, *grow = nullptr, *nb = nullptr, *cn_atom = nullptr;
+  double *part_a = nullptr, *part_b = nullptr, *s_int = nullptr;
+  unsigned* tickets = nullptr;
+  double *centres = nullptr, *heights = nullptr, *bias_part = nullptr;
+  int64_t* hill_count = nullptr;
+
+  bool built = false, fwd = false, bwd = false;
+  int last_status = GM_OK;
+  YCoef<float> ycf;
+  YCoef<double> ycd;
+};
+
+namespace {
+
+template <typename P>
+int dalloc(P** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return GM_ERR_OOM;
+  }
+  *p = reinterpret_cast<P*>(q);
+  return GM_OK;
+}
+
+template <typename P>
+void dfree(P*& p) {
+  if (p) (void)hipFree(reinterpret_cast<void*>(p));
+  p = nullptr;
+}
+
+int hip_rc(hipError_t e) { return e == hipSuccess ? GM_OK : GM_ERR_HIP; }
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+double fact(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; i++) f *= i;
+  return f;
+}
+
+// Real l = 6 harmonics in polynomial form.  With z = cos(theta) and
+// P_6(z) = (231 z^6 - 315 z^4 + 105 z^2 - 5)/16, the m-th derivatives are
+//   D1 = (1386 z^5 - 1260 z^3 + 210 z)/16     D2 = (6930 z^4 - 3780 z^2 + 210)/16
+//   D3 = (27720 z^3 - 7560 z)/16              D4 = (83160 z^2 - 7560)/16
+//   D5 = 166320 z/16                          D6 = 166320/16
+// and Y_6m = K_m (-1)^m D_m(z) (x + i y)^m with K_m = sqrt(13/(4 pi) (6-m)!/(6+m)!)
+// (Condon-Shortley phase).  The real basis scales m > 0 by sqrt(2).
+template <typename T>
+void make_ycoef(YCoef<T>& c) {
+  const double D0[4] = {-5, 105, -315, 231}, D1[3] = {210, -1260, 1386}, D2[3] = {210, -3780, 6930};
+  const double D3[2] = {-7560, 27720}, D4[2] = {-7560, 83160}, D5 = 166320, D6 = 166320;
+  double A[7];
+  for (int m = 0; m <= 6; m++) {
+    double K = sqrt(13.0 / (4.0 * M_PI) * fact(6 - m) / fact(6 + m));
+    A[m] = m == 0 ? K : sqrt(2.0) * ((m & 1) ? -K : K);
+  }
+  for (int k = 0; k < 4; k++) c.e0[k] = (T)(A[0] * D0[k] / 16.0);
+  for (int k = 0; k < 3; k++) c.e1[k] = (T)(A[1] * D1[k] / 16.0);
+  for (int k = 0; k < 3; k++) c.e2[k] = (T)(A[2] * D2[k] / 16.0);
+  for (int k = 0; k < 2; k++) c.e3[k] = (T)(A[3] * D3[k] / 16.0);
+  for (int k = 0; k < 2; k++) c.e4[k] = (T)(A[4] * D4[k] / 16.0);
+  c.e5 = (T)(A[5] * D5 / 16.0);
+  c.e6 = (T)(A[6] * D6 / 16.0);
+  for (int m = 0; m < 6; m++) c.rat[m] = (T)(A[m] / A[m + 1]);
+}
+
+int validate(const gm_params* p, int64_t n) {
+  if (!p || n < 1 || n > (int64_t)INT32_MAX / 2) return GM_ERR_INVALID_ARG;
+  if (p->cv_kind < GM_CV_COORD || p->cv_kind > GM_CV_COORD_Q6) return GM_ERR_INVALID_ARG;
+  if (p->precision != GM_FP32 && p->precision != GM_FP64) return GM_ERR_INVALID_ARG;
+  if (!(p->r_c > 0.0) || !(p->skin >= 0.0) || !isfinite(p->r_c + p->skin)) return GM_ERR_INVALID_ARG;
+  const bool q6 = p->cv_kind != GM_CV_COORD, cn = p->cv_kind != GM_CV_Q6COUNT;
+  if (q6 && (!(p->taper > 0.0) || p->taper > p->r_c || !(p->bond_w > 0.0) || !(p->count_w > 0.0)))
+    return GM_ERR_INVALID_ARG;
+  if (cn && !(p->cn_r0 > 0.0)) return GM_ERR_INVALID_ARG;
+  const int dims = p->cv_kind == GM_CV_COORD_Q6 ? 2 : 1;
+  for (int d = 0; d < dims; d++)
+    if (!(p->sigma[d] > 0.0)) return GM_ERR_INVALID_ARG;
+  if (!(p->w0 >= 0.0) || !(p->gamma == 0.0 || p->gamma > 1.0)) return GM_ERR_INVALID_ARG;
+  if (p->gamma > 1.0 && !(p->kBT > 0.0)) return GM_ERR_INVALID_ARG;
+  if (p->hill_capacity < 0 || p->max_neighbors < 0 || p->max_neighbors > 4096 || p->reserved != 0)
+    return GM_ERR_INVALID_ARG;
+  return GM_OK;
+}
+
+template <typename T>
+CvArgs<T> make_args(gm_ctx* c) {
+  CvArgs<T> a;
+  memset(&a, 0, sizeof(a));
+  a.pos_s = reinterpret_cast<const vec4_t<T>*>(c->pos_s);
+  a.nbr = c->nbr;
+  a.cnt = c->cnt;
+  a.perm = c->perm;
+  a.n = c->n;
+  a.kmax = c->kmax;
+  a.dims = c->dims;
+  for (int d = 0; d < 3; d++) {
+    const T L = (T)c->box[d];
+    a.L[d] = L;
+    a.invL[d] = (T)(1.0 / c->box[d]);
+    a.Llo[d] = (T)(c->box[d] - (double)L);
+  }
+  const double rc = c->p.r_c, D = c->p.taper > 0 ? c->p.taper : 1.0;
+  a.rc2 = (T)(rc * rc);
+  a.taper_lo = (T)(rc - c->p.taper);
+  a.pi_over_D = (T)(M_PI / D);
+  a.half_pi_over_D = (T)(0.5 * M_PI / D);
+  a.bond_d0 = (T)c->p.bond_d0;
+  a.inv_bond_w = (T)(c->p.bond_w > 0 ? 1.0 / c->p.bond_w : 0.0);
+  a.count_n0 = (T)c->p.count_n0;
+  a.inv_count_w = (T)(c->p.count_w > 0 ? 1.0 / c->p.count_w : 0.0);
+  a.cn_r0inv = (T)(c->p.cn_r0 > 0 ? 1.0 / c->p.cn_r0 : 0.0);
+  a.inv_n = 1.0 / (double)c->n;
+  if constexpr (sizeof(T) == 4)
+    a.yc = c->ycf;
+  else
+    a.yc = c->ycd;
+  a.qrow = reinterpret_cast<T*>(c->qrow);
+  a.grow = reinterpret_cast<T*>(c->grow);
+  a.nb = reinterpret_cast<T*>(c->nb);
+  a.cn_atom = reinterpret_cast<T*>(c->cn_atom);
+  a.part_a = c->part_a;
+  a.part_b = c->part_b;
+  a.ticket = c->tickets;
+  a.s_int = c->s_int;
+  a.err = c->err;
+  return a;
+}
+
+BiasArgs make_bias(gm_ctx* c, const double* s, int deposit) {
+  BiasArgs b;
+  memset(&b, 0, sizeof(b));
+  b.s = s;
+  b.centres = c->centres;
+  b.heights = c->heights;
+  b.count = c->hill_count;
+  b.capacity = c->p.hill_capacity;
+  b.dims = c->dims;
+  b.deposit = deposit;
+  for (int d = 0; d < c->dims; d++) {
+    b.inv2s2[d] = 1.0 / (2.0 * c->p.sigma[d] * c->p.sigma[d]);
+    b.invs2[d] = 1.0 / (c->p.sigma[d] * c->p.sigma[d]);
+  }
+  b.w0 = c->p.w0;
+  b.wt_scale = c->p.gamma == 0.0 ? 0.0 : 1.0 / (c->p.kBT * (c->p.gamma - 1.0));
+  b.part = c->bias_part;
+  b.ticket = c->tickets + 1;
+  b.err = c->err;
+  return b;
+}
+
+void free_all(gm_ctx* c) {
+  dfree(c->cell);
+  dfree(c->count);
+  dfree(c->start);
+  dfree(c->fill);
+  dfree(c->perm);
+  dfree(c->nbr);
+  dfree(c->cnt);
+  dfree(c->err);
+  dfree(c->stats);
+  dfree(c->pos_s);
+  dfree(c->qrow);
+  dfree(c->grow);
+  dfree(c->nb);
+  dfree(c->cn_atom);
+  dfree(c->part_a);
+  dfree(c->part_b);
+  dfree(c->s_int);
+  dfree(c->tickets);
+  dfree(c->centres);
+  dfree(c->heights);
+  dfree(c->bias_part);
+  dfree(c->hill_count);
+}
+
+int status_from_bits(int32_t bits) {
+  if (bits & kErrOverflow) return GM_ERR_NEIGHBOR_OVERFLOW;
+  if (bits & kErrNonFinite) return GM_ERR_NONFINITE;
+  if (bits & kErrCapacity) return GM_ERR_HILL_CAPACITY;
+  return GM_OK;
+}
+
+#define GM_TRY(x)               \
+  do {                          \
+    int _rc = (x);              \
+    if (_rc != GM_OK) return _rc; \
+  } while (0)
+
+}  // namespace
+
+template <typename T>
+static int cv_forward_t(gm_ctx* c, const float* pos4, double* s_dev) {
+  hipStream_t st = c->stream;
+  auto* ps = reinterpret_cast<vec4_t<T>*>(c->pos_s);
+  GM_TRY(hip_rc(launch_gather<T>(reinterpret_cast<const float4*>(pos4), c->perm, c->n, ps, c->err, st)));
+  CvArgs<T> a = make_args<T>(c);
+  a.s_out = s_dev;
+  if (c->has_q6) return hip_rc(launch_q6_forward<T>(a, c->has_cn, st));
+  return hip_rc(launch_cn_forward<T>(a, st));
+}
+
+template <typename T>
+static int force_pass(gm_ctx* c, const double* seed, void* out4, int mode) {
+  CvArgs<T> a = make_args<T>(c);
+  a.seed = seed;
+  a.mode = mode;
+  a.out4 = out4;
+  if (c->has_q6) return hip_rc(launch_q6_force<T>(a, c->has_cn, c->stream));
+  return hip_rc(launch_cn_force<T>(a, c->stream));
+}
+
+extern "C" {
+
+const char* gm_version(void) { return "gpumetad 0.1 (gfx950)"; }
+
+const char* gm_strerror(int code) {
+  switch (code) {
+    case GM_OK: return "ok";
+    case GM_ERR_INVALID_ARG: return "invalid argument";
+    case GM_ERR_OOM: return "device out of memory";
+    case GM_ERR_HIP: return "HIP runtime error";
+    case GM_ERR_BOX_TOO_SMALL: return "box too small: fewer than 3 cells of width r_c + skin on an axis";
+    case GM_ERR_NEIGHBOR_OVERFLOW: return "neighbour list overflow: raise max_neighbors and rebuild";
+    case GM_ERR_HILL_CAPACITY: return "hill buffer full";
+    case GM_ERR_NONFINITE: return "non-finite position, CV, bias or force";
+    case GM_ERR_STATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_stream) {
+  if (!out) return GM_ERR_INVALID_ARG;
+  *out = nullptr;
+  GM_TRY(validate(params, n_atoms));
+  gm_ctx* c = new (std::nothrow) gm_ctx();
+  if (!c) return GM_ERR_OOM;
+  c->p = *params;
+  c->n = n_atoms;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->dims = params->cv_kind == GM_CV_COORD_Q6 ? 2 : 1;
+  c->fp64 = params->precision == GM_FP64;
+  c->has_q6 = params->cv_kind != GM_CV_COORD;
+  c->has_cn = params->cv_kind != GM_CV_Q6COUNT;
+  c->r_list = params->r_c + params->skin;
+  int32_t km = params->max_neighbors > 0 ? params->max_neighbors : 64;
+  c->kmax = (km + 3) / 4 * 4;
+  c->blocks = atom_blocks(n_atoms);
+  int64_t hb = (params->hill_capacity + kBlock - 1) / kBlock;
+  c->bias_blocks = (int)(hb < 1 ? 1 : (hb > 1024 ? 1024 : hb));
+  make_ycoef(c->ycf);
+  make_ycoef(c->ycd);
+
+  const size_t n = (size_t)n_atoms, T = c->fp64 ? 8 : 4;
+  const size_t cap = (size_t)(params->hill_capacity > 0 ? params->hill_capacity : 1);
+  int rc = GM_OK;
+  if (rc == GM_OK) rc = dalloc(&c->cell, n * 4);
+  if (rc == GM_OK) rc = dalloc(&c->perm, n * 4);
+  if (rc == GM_OK) rc = dalloc(&c->cnt, n * 4);
+  if (rc == GM_OK) rc = dalloc(&c->nbr, n * (size_t)c->kmax * 4);
+  if (rc == GM_OK) rc = dalloc(&c->pos_s, n * 4 * T);
+  if (rc == GM_OK && c->has_q6) rc = dalloc(&c->qrow, n * 16 * T);
+  if (rc == GM_OK && c->has_q6) rc = dalloc(&c->grow, n * 16 * T);
+  if (rc == GM_OK) rc = dalloc(&c->nb, n * T);
+  if (rc == GM_OK) rc = dalloc(&c->cn_atom, n * T);
+  if (rc == GM_OK) rc = dalloc(&c->part_a, (size_t)c->blocks * 8);
+  if (rc == GM_OK) rc = dalloc(&c->part_b, (size_t)c->blocks * 8);
+  if (rc == GM_OK) rc = dalloc(&c->s_int, 16);
+  if (rc == GM_OK) rc = dalloc(&c->tickets, 16);
+  if (rc == GM_OK) rc = dalloc(&c->err, 16);
+  if (rc == GM_OK) rc = dalloc(&c->stats, 16);
+  if (rc == GM_OK) rc = dalloc(&c->centres, cap * c->dims * 8);
+  if (rc == GM_OK) rc = dalloc(&c->heights, cap * 8);
+  if (rc == GM_OK) rc = dalloc(&c->hill_count, 16);
+  if (rc == GM_OK) rc = dalloc(&c->bias_part, (size_t)c->bias_blocks * 3 * 8);
+  if (rc == GM_OK) {
+    bool ok = hipMemset(c->tickets, 0, 16) == hipSuccess && hipMemset(c->err, 0, 16) == hipSuccess &&
+              hipMemset(c->hill_count, 0, 16) == hipSuccess && hipMemset(c->stats, 0, 16) == hipSuccess &&
+              hipMemset(c->s_int, 0, 16) == hipSuccess && hipMemset(c->cn_atom, 0, n * T) == hipSuccess &&
+              hipMemset(c->nb, 0, n * T) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    if (!ok) rc = GM_ERR_HIP;
+  }
+  if (rc != GM_OK) {
+    free_all(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return GM_OK;
+}
+
+int gm_destroy(gm_ctx* c) {
+  if (!c) return GM_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+  return GM_OK;
+}
+
+int gm_set_stream(gm_ctx* c, void* hip_stream) {
+  if (!c) return GM_ERR_INVALID_ARG;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return GM_OK;
+}
+
+int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
+  if (!c || !pos4 || !box || !aligned(pos4, 16)) return GM_ERR_INVALID_ARG;
+  int32_t nc[3];
+  for (int a = 0; a < 3; a++) {
+    if (!(box[a] > 0.0) || !isfinite(box[a])) return GM_ERR_INVALID_ARG;
+    double k = floor(box[a] / c->r_list);
+    if (k < 3.0) return GM_ERR_BOX_TOO_SMALL;
+    if (k > 4096.0) return GM_ERR_INVALID_ARG;
+    nc[a] = (int32_t)k;
+  }
+  const int64_t ncells = (int64_t)nc[0] * nc[1] * nc[2];
+  if (ncells > c->ncells_cap) {
+    (void)hipStreamSynchronize(c->stream);
+    dfree(c->count);
+    dfree(c->start);
+    dfree(c->fill);
+    c->ncells_cap = 0;
+    GM_TRY(dalloc(&c->count, (size_t)ncells * 4));
+    GM_TRY(dalloc(&c->start, (size_t)(ncells + 1) * 4));
+    GM_TRY(dalloc(&c->fill, (size_t)ncells * 4));
+    c->ncells_cap = ncells;
+  }
+  c->ncells = ncells;
+  for (int a = 0; a < 3; a++) {
+    c->box[a] = box[a];
+    c->geom.L[a] = box[a];
+    c->geom.inv[a] = (double)nc[a] / box[a];
+    c->geom.invL[a] = 1.0 / box[a];
+    c->geom.nc[a] = nc[a];
+  }
+  hipStream_t st = c->stream;
+  const float4* p4 = reinterpret_cast<const float4*>(pos4);
+  c->built = c->fwd = c->bwd = false;
+  GM_TRY(hip_rc(launch_fill_i32(c->count, 0, ncells, st)));
+  GM_TRY(hip_rc(launch_fill_i32(c->stats, 0, 4, st)));
+  GM_TRY(hip_rc(launch_cell_ids(p4, c->n, c->geom, c->cell, c->count, c->err, st)));
+  GM_TRY(hip_rc(launch_scan_cells(c->count, ncells, c->start, c->fill, st)));
+  GM_TRY(hip_rc(launch_scatter(c->cell, c->n, c->start, c->fill, c->perm, st)));
+  GM_TRY(hip_rc(launch_sort_cells(c->start, ncells, c->perm, st)));
+  unsigned long long* total = reinterpret_cast<unsigned long long*>(c->stats + 2);
+  const double rl2 = c->r_list * c->r_list;
+  if (c->fp64) {
+    auto* ps = reinterpret_cast<double4*>(c->pos_s);
+    GM_TRY(hip_rc(launch_gather<double>(p4, c->perm, c->n, ps, c->err, st)));
+    GM_TRY(hip_rc(launch_build_nbr<double>(ps, c->n, c->geom, rl2, c->start, c->nbr, c->kmax, c->cnt, c->err,
+                                           c->stats, total, st)));
+  } else {
+    auto* ps = reinterpret_cast<float4*>(c->pos_s);
+    GM_TRY(hip_rc(launch_gather<float>(p4, c->perm, c->n, ps, c->err, st)));
+    GM_TRY(hip_rc(launch_build_nbr<float>(ps, c->n, c->geom, rl2, c->start, c->nbr, c->kmax, c->cnt, c->err,
+                                          c->stats, total, st)));
+  }
+  c->built = true;
+  return GM_OK;
+}
+
+int gm_cv_forward(gm_ctx* c, const float* pos4, double* s_dev) {
+  if (!c || !pos4 || !aligned(pos4, 16) || (s_dev && !aligned(s_dev, 8))) return GM_ERR_INVALID_ARG;
+  if (!c->built) return GM_ERR_STATE;
+  c->fwd = c->bwd = false;
+  GM_TRY(c->fp64 ? cv_forward_t<double>(c, pos4, s_dev) : cv_forward_t<float>(c, pos4, s_dev));
+  c->fwd = true;
+  return GM_OK;
+}
+
+int gm_bias_eval(gm_ctx* c, const double* s_dev, double* V_dev, double* dVds_dev) {
+  if (!c || !s_dev) return GM_ERR_INVALID_ARG;
+  BiasArgs b = make_bias(c, s_dev, 0);
+  b.V_out = V_dev;
+  b.dV_out = dVds_dev;
+  return hip_rc(launch_bias(b, c->bias_blocks, c->stream));
+}
+
+int gm_deposit_hill(gm_ctx* c, const double* s_dev) {
+  if (!c || !s_dev) return GM_ERR_INVALID_ARG;
+  BiasArgs b = make_bias(c, s_dev, 1);
+  return hip_rc(launch_bias(b, c->bias_blocks, c->stream));
+}
+
+int gm_cv_backward(gm_ctx* c, const float* pos4, const double* seed_dev, void* grad4) {
+  if (!c || !pos4) return GM_ERR_INVALID_ARG;
+  if (!seed_dev && c->dims > 1 && grad4) return GM_ERR_INVALID_ARG;
+  const size_t vs = c->fp64 ? 32 : 16;
+  if (grad4 && !aligned(grad4, vs)) return GM_ERR_INVALID_ARG;
+  if (!c->fwd) return GM_ERR_STATE;
+  if (c->has_q6) {
+    if (c->fp64)
+      GM_TRY(hip_rc(launch_q6_adjoint<double>(make_args<double>(c), c->stream)));
+    else
+      GM_TRY(hip_rc(launch_q6_adjoint<float>(make_args<float>(c), c->stream)));
+  }
+  c->bwd = true;
+  if (grad4) return c->fp64 ? force_pass<double>(c, seed_dev, grad4, 1) : force_pass<float>(c, seed_dev, grad4, 1);
+  return GM_OK;
+}
+
+int gm_apply_bias_forces(gm_ctx* c, const float* pos4, const double* dVds_dev, void* force4) {
+  if (!c || !pos4 || !dVds_dev || !force4) return GM_ERR_INVALID_ARG;
+  const size_t vs = c->fp64 ? 32 : 16;
+  if (!aligned(force4, vs)) return GM_ERR_INVALID_ARG;
+  if (!c->bwd) return GM_ERR_STATE;
+  return c->fp64 ? force_pass<double>(c, dVds_dev, force4, 0) : force_pass<float>(c, dVds_dev, force4, 0);
+}
+
+int gm_hills_get(gm_ctx* c, double* centres, double* heights, int64_t cap, int64_t* k) {
+  if (!c || !k) return GM_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
+  int64_t K = 0;
+  if (hipMemcpy(&K, c->hill_count, 8, hipMemcpyDeviceToHost) != hipSuccess) return GM_ERR_HIP;
+  *k = K;
+  if (centres || heights) {
+    if (cap < K) return GM_ERR_INVALID_ARG;
+    if (centres && K && hipMemcpy(centres, c->centres, (size_t)K * c->dims * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return GM_ERR_HIP;
+    if (heights && K && hipMemcpy(heights, c->heights, (size_t)K * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return GM_ERR_HIP;
+  }
+  return GM_OK;
+}
+
+int gm_hills_set(gm_ctx* c, const double* centres, const double* heights, int64_t k) {
+  if (!c || k < 0 || k > c->p.hill_capacity) return GM_ERR_INVALID_ARG;
+  if (k > 0 && (!centres || !heights)) return GM_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
+  if (k && hipMemcpy(c->centres, centres, (size_t)k * c->dims * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return GM_ERR_HIP;
+  if (k && hipMemcpy(c->heights, heights, (size_t)k * 8, hipMemcpyHostToDevice) != hipSuccess) return GM_ERR_HIP;
+  if (hipMemcpy(c->hill_count, &k, 8, hipMemcpyHostToDevice) != hipSuccess) return GM_ERR_HIP;
+  return GM_OK;
+}
+
+int gm_status(gm_ctx* c, int sync) {
+  if (!c) return GM_ERR_INVALID_ARG;
+  if (!sync) return c->last_status;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
+  int32_t bits = 0;
+  if (hipMemcpy(&bits, c->err, 4, hipMemcpyDeviceToHost) != hipSuccess) return GM_ERR_HIP;
+  if (bits) {
+    const int32_t zero = 0;
+    if (hipMemcpy(c->err, &zero, 4, hipMemcpyHostToDevice) != hipSuccess) return GM_ERR_HIP;
+  }
+  c->last_status = status_from_bits(bits);
+  return c->last_status;
+}
+
+int gm_neighbor_stats(gm_ctx* c, int32_t* max_count, int64_t* total) {
+  if (!c) return GM_ERR_INVALID_ARG;
+  if (!c->built) return GM_ERR_STATE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
+  int32_t s[4];
+  if (hipMemcpy(s, c->stats, 16, hipMemcpyDeviceToHost) != hipSuccess) return GM_ERR_HIP;
+  if (max_count) *max_count = s[0];
+  if (total) {
+    unsigned long long t;
+    memcpy(&t, &s[2], 8);
+    *total = (int64_t)t;
+  }
+  return GM_OK;
+}
+
+int gm_reserve_neighbors(gm_ctx* c, int32_t max_neighbors) {
+  if (!c || max_neighbors < 1 || max_neighbors > 4096) return GM_ERR_INVALID_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
+  dfree(c->nbr);
+  c->kmax = (max_neighbors + 3) / 4 * 4;
+  c->built = c->fwd = c->bwd = false;
+  return dalloc(&c->nbr, (size_t)c->n * c->kmax * 4);
+}
+
+int gm_copy_cell_list(gm_ctx* c, int32_t* perm_dev, int32_t* cell_start_dev, int32_t* ncell) {
+  if (!c || !perm_dev) return GM_ERR_INVALID_ARG;
+  if (!c->built) return GM_ERR_STATE;
+  if (hipMemcpyAsync(perm_dev, c->perm, (size_t)c->n * 4, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return GM_ERR_HIP;
+  if (cell_start_dev && hipMemcpyAsync(cell_start_dev, c->start, (size_t)(c->ncells + 1) * 4,
+                                       hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return GM_ERR_HIP;
+  if (ncell)
+    for (int a = 0; a < 3; a++) ncell[a] = c->geom.nc[a];
+  return GM_OK;
+}
+
+int gm_copy_neighbors(gm_ctx* c, int32_t* nbr_dev, int32_t* cnt_dev, int32_t* row_width) {
+  if (!c) return GM_ERR_INVALID_ARG;
+  if (!c->built) return GM_ERR_STATE;
+  if (nbr_dev && hipMemcpyAsync(nbr_dev, c->nbr, (size_t)c->n * c->kmax * 4, hipMemcpyDeviceToDevice,
+                                c->stream) != hipSuccess)
+    return GM_ERR_HIP;
+  if (cnt_dev && hipMemcpyAsync(cnt_dev, c->cnt, (size_t)c->n * 4, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return GM_ERR_HIP;
+  if (row_width) *row_width = c->kmax;
+  return GM_OK;
+}
+
+int gm_atom_values(gm_ctx* c, int what, double* dst_dev) {
+  if (!c || !dst_dev || what < GM_ATOM_Q6 || what > GM_ATOM_CN) return GM_ERR_INVALID_ARG;
+  if (!c->fwd) return GM_ERR_STATE;
+  if ((what != GM_ATOM_CN && !c->has_q6) || (what == GM_ATOM_CN && !c->has_cn)) return GM_ERR_INVALID_ARG;
+  if (c->fp64) return hip_rc(launch_atom_values<double>(make_args<double>(c), what, c->p.cv_kind, dst_dev, c->stream));
+  return hip_rc(launch_atom_values<float>(make_args<float>(c), what, c->p.cv_kind, dst_dev, c->stream));
+}
+
+}  // extern "C"

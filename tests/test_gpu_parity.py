@@ -1,0 +1,297 @@
+"""HIP path against the FP64 oracle, stage by stage, on the same seeded inputs.
+
+Bars (written here, derived in the design notes):
+  * cell permutation, cell starts and neighbour sets: bit-exact;
+  * CV: |s_gpu - s_ref| <= 1e-5 |s_ref| in FP32 (1e-10 in FP64);
+  * bias forces (F_out - F_in), seeded with the same dV/ds on both sides:
+    max_i |dF_i| / max_i |F_ref_i| <= 1e-4 in FP32 (1e-10 in FP64);
+  * V, dV/ds and hill heights at the same s: 1e-12 relative (FP64 both sides).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.helpers import oracle_cvs, params_for, rel_force_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+Q6CV = dict(cv="q6", precision="fp32", r_c=3.6, skin=0.4, taper=0.2, cn_r0=2.5, bond_d0=0.7, bond_w=0.02,
+            count_n0=5.5, count_w=0.25, sigma=[20.0], w0=W.W0_EV, gamma=10.0, kBT=W.KBT_EV,
+            hills=dict(k=64))
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def to_dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=dev(), dtype=dtype).contiguous()
+
+
+def make_pipe(wl, n, **kw):
+    from paper_2510_06873_amd import Pipeline
+
+    return Pipeline(n, params_for(wl, **kw))
+
+
+def gpu_neighbor_sets(pipe):
+    """Rows of the GPU neighbour lists mapped back to atom ids, as sorted arrays."""
+    _, perm, _ = pipe.cell_list()
+    nbr, cnt = pipe.neighbor_lists()
+    perm = perm.cpu().numpy()
+    nbr = nbr.cpu().numpy()
+    cnt = cnt.cpu().numpy()
+    rows = {}
+    for t in range(len(perm)):
+        rows[int(perm[t])] = np.sort(perm[nbr[t, :cnt[t]]])
+    return rows
+
+
+# ---------------------------------------------------------------------------
+# Cell list and neighbour sets: bit-exact
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("spec", [dict(nx=4, ny=3, nz=6, seed=21), dict(nx=7, ny=5, nz=5, seed=22),
+                                  dict(nx=40, ny=20, nz=15, seed=2)])
+def test_cell_list_and_neighbors_bit_exact(orc, spec):
+    d = W.wurtzite_slab(**spec)
+    pos, box = d["pos"], d["box"]
+    n = len(pos)
+    pipe = make_pipe(Q6CV, n)
+    p4 = to_dev(W.as_float4(pos, d["species"]))
+    pipe.build_neighbors(p4, box)
+    assert pipe.status(True) == 0
+    nc, perm, start = pipe.cell_list()
+    onc, ocell, operm, ostart = orc.cell_list(pos, box, 4.0)
+    assert tuple(onc.tolist()) == nc
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    assert np.array_equal(start.cpu().numpy(), ostart)
+    off, nb = orc.neighbors(pos, box, 4.0)
+    rows = gpu_neighbor_sets(pipe)
+    for i in range(n):
+        assert np.array_equal(rows[i], nb[off[i]:off[i + 1]]), i
+    mx, tot = pipe.neighbor_stats()
+    assert tot == len(nb) and mx == int(np.diff(off).max())
+
+
+def test_neighbors_random_boxes_edge(orc):
+    """Uniform random atoms in boxes just above 3 cells per axis, skin 0."""
+    from paper_2510_06873_amd import Params, Pipeline
+
+    rng = np.random.default_rng(3)
+    for L in ((12.0, 12.3, 12.9), (12.0000001, 13.7, 16.2)):
+        box = np.array(L)
+        pos = (rng.random((700, 3)) * box).astype(np.float32)
+        pipe = Pipeline(700, Params(cv_kind=2, r_c=4.0, skin=0.0, sigma=[1.0], hill_capacity=4, max_neighbors=200))
+        pipe.build_neighbors(to_dev(W.as_float4(pos)), box)
+        assert pipe.status(True) == 0
+        off, nb = orc.neighbors(pos, box, 4.0, method="brute")
+        rows = gpu_neighbor_sets(pipe)
+        for i in range(700):
+            assert np.array_equal(rows[i], nb[off[i]:off[i + 1]])
+
+
+# ---------------------------------------------------------------------------
+# q6 count: CV, per-atom values, gradient and forces
+# ---------------------------------------------------------------------------
+def run_step(pipe, pos, species, box, F_in, seed_dv):
+    p4 = to_dev(W.as_float4(pos, species))
+    pipe.build_neighbors_checked(p4, box)
+    s = pipe.cv_forward(p4).clone()
+    pipe.cv_backward(p4)
+    F = to_dev(F_in, pipe.fdtype)
+    dv = torch.tensor(seed_dv, dtype=torch.float64, device=dev())
+    pipe.apply_bias_forces(p4, F, dv)
+    torch.cuda.synchronize()
+    assert pipe.status(True) == 0
+    return s.cpu().numpy(), F.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("precision,tol_s,tol_f", [("fp32", 1e-5, 1e-4), ("fp64", 1e-10, 1e-10)])
+@pytest.mark.parametrize("spec", [dict(nx=4, ny=3, nz=6, seed=21), dict(nx=8, ny=4, nz=8, seed=5)])
+def test_q6_cv_and_forces(orc, spec, precision, tol_s, tol_f):
+    d = W.wurtzite_slab(**spec)
+    pos, box, sp = d["pos"], d["box"], d["species"]
+    n = len(pos)
+    wl = dict(Q6CV, precision=precision)
+    pipe = make_pipe(wl, n)
+    F_in = W.external_forces(n, seed=9)
+    dv = [0.37]
+    s, F = run_step(pipe, pos, sp, box, F_in, dv)
+    s_ref, g_ref, nl = oracle_cvs(orc, pos, box, wl)
+    assert abs(s[0] - s_ref[0]) <= tol_s * abs(s_ref[0])
+    F_ref_bias = -dv[0] * g_ref[0]
+    assert rel_force_err(F[:, :3] - F_in[:, :3].astype(np.float64), F_ref_bias) <= tol_f
+    assert np.array_equal(F[:, 3], F_in[:, 3])
+    # per-atom Steinhardt q6 and bond counts
+    prm = orc.q6_params(3.6, 0.2, 0.7, 0.02, 5.5, 0.25)
+    o = orc.q6_forward(pos, box, nl, prm)
+    from paper_2510_06873_amd import ATOM_C, ATOM_NB, ATOM_Q6
+
+    tol_a = 1e-4 if precision == "fp32" else 1e-10
+    assert np.max(np.abs(pipe.atom_values(ATOM_Q6).cpu().numpy() - o["q6"])) <= tol_a
+    assert np.max(np.abs(pipe.atom_values(ATOM_NB).cpu().numpy() - o["nb"])) <= 50 * tol_a
+    assert np.max(np.abs(pipe.atom_values(ATOM_C).cpu().numpy() - o["c"])) <= 50 * tol_a
+
+
+def test_q6_backward_gradient_output(orc):
+    d = W.wurtzite_slab(5, 3, 5, seed=23)
+    pos, box = d["pos"], d["box"]
+    n = len(pos)
+    pipe = make_pipe(Q6CV, n)
+    p4 = to_dev(W.as_float4(pos))
+    pipe.build_neighbors(p4, box)
+    pipe.cv_forward(p4)
+    g = torch.full((n, 4), 7.0, dtype=torch.float32, device=dev())
+    pipe.cv_backward(p4, None, g)
+    torch.cuda.synchronize()
+    _, g_ref, _ = oracle_cvs(orc, pos, box, Q6CV)
+    g = g.cpu().numpy().astype(np.float64)
+    assert rel_force_err(g[:, :3], g_ref[0]) <= 1e-4
+    assert np.all(g[:, 3] == 7.0)
+    # zero net gradient (translation invariance), FP32 bound
+    gmax = np.linalg.norm(g[:, :3], axis=1).max()
+    assert np.linalg.norm(g[:, :3].sum(0)) <= 1e-5 * np.sqrt(n) * gmax
+
+
+# ---------------------------------------------------------------------------
+# 2-D CV (coordination + q6 count) and coordination alone (FP64)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision,tol_s,tol_f", [("fp32", 1e-5, 1e-4), ("fp64", 1e-10, 1e-10)])
+def test_coord_q6_2d(orc, precision, tol_s, tol_f):
+    wl = dict(W.WORKLOADS["wz2048"], precision=precision)
+    d = W.structure(wl["structure"])
+    pos, box = d["pos"], d["box"]
+    n = len(pos)
+    pipe = make_pipe(wl, n)
+    F_in = W.external_forces(n, seed=10)
+    dv = [0.11, -0.023]
+    s, F = run_step(pipe, pos, d["species"], box, F_in, dv)
+    s_ref, g_ref, _ = oracle_cvs(orc, pos, box, wl)
+    assert np.all(np.abs(s - s_ref) <= tol_s * np.abs(s_ref))
+    F_ref_bias = -(dv[0] * g_ref[0] + dv[1] * g_ref[1])
+    assert rel_force_err(F[:, :3] - F_in[:, :3].astype(np.float64), F_ref_bias) <= tol_f
+
+
+def test_fcc864_coordination_fp64(orc):
+    wl = W.WORKLOADS["fcc864"]
+    d = W.structure(wl["structure"])
+    pos, box = d["pos"], d["box"]
+    n = len(pos)
+    pipe = make_pipe(wl, n)
+    F_in = np.zeros((n, 4))
+    F_in[:, :3] = W.external_forces(n, seed=11)[:, :3]
+    dv = [-3.3]
+    s, F = run_step(pipe, pos, None, box, F_in, dv)
+    s_ref, g_ref, _ = oracle_cvs(orc, pos, box, wl)
+    assert abs(s[0] - s_ref[0]) <= 1e-10 * abs(s_ref[0])
+    assert rel_force_err(F[:, :3] - F_in[:, :3], -dv[0] * g_ref[0]) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Hills: deposition replay, bias evaluation, checkpoint
+# ---------------------------------------------------------------------------
+def test_deposit_replay_and_bias_fcc864(orc):
+    wl = W.WORKLOADS["fcc864"]
+    hp = wl["hills"]
+    cen = W.hill_centres(hp["k"], hp["lo"], hp["hi"], hp["seed"])
+    pipe = make_pipe(wl, 864)
+    cdev = to_dev(cen, torch.float64)
+    for k in range(len(cen)):
+        pipe.deposit_hill(cdev[k])
+    gc, gh = pipe.hills_get()
+    h_ref = orc.deposit_sequence(cen, wl["sigma"], wl["w0"], wl["gamma"], wl["kBT"])
+    assert np.array_equal(gc, cen)
+    assert np.max(np.abs(gh - h_ref) / h_ref) <= 1e-12
+    for sval in (13.2, 0.0, 7.77, 20.0):
+        s = torch.tensor([sval], dtype=torch.float64, device=dev())
+        V, dV = pipe.bias_eval(s)
+        Vr, dVr = orc.bias(cen, h_ref, wl["sigma"], [sval])
+        assert abs(V.item() - Vr) <= 1e-12 * max(Vr, 1e-300)
+        assert abs(dV.item() - dVr[0]) <= 1e-12 * (abs(dVr[0]) + Vr / wl["sigma"][0])
+
+
+def test_bias_2d_and_checkpoint_roundtrip(orc):
+    wl = W.WORKLOADS["wz2048"]
+    pipe = make_pipe(wl, 100)
+    cen = W.hill_centres(3000, [5.0, 900.0], [6.0, 1100.0], seed=3)
+    hts = np.random.default_rng(1).random(3000) * 0.01
+    pipe.hills_set(cen, hts)
+    s = torch.tensor([5.5, 1000.0], dtype=torch.float64, device=dev())
+    V, dV = pipe.bias_eval(s)
+    V1, dV1 = V.item(), dV.cpu().numpy().copy()
+    Vr, dVr = orc.bias(cen, hts, wl["sigma"], [5.5, 1000.0])
+    assert abs(V1 - Vr) <= 1e-12 * Vr
+    assert np.all(np.abs(dV1 - dVr) <= 1e-12 * (np.abs(dVr) + Vr / np.array(wl["sigma"])))
+    c2, h2 = pipe.hills_get()
+    pipe2 = make_pipe(wl, 100)
+    pipe2.hills_set(c2, h2)
+    V2, dV2 = pipe2.bias_eval(s)
+    assert V2.item() == V1 and np.array_equal(dV2.cpu().numpy(), dV1)
+
+
+def test_deposit_sampled_heights_wz1m_hills(orc):
+    """50,000 deposits (the 1.02M-atom workload's history); every 997th height
+    is recomputed by the oracle from the GPU's own earlier hills."""
+    wl = W.WORKLOADS["wz1m"]
+    hp = wl["hills"]
+    cen = W.hill_centres(hp["k"], hp["lo"], hp["hi"], hp["seed"])
+    pipe = make_pipe(wl, 1000)
+    cdev = to_dev(cen, torch.float64)
+    for k in range(len(cen)):
+        pipe.deposit_hill(cdev[k])
+    gc, gh = pipe.hills_get()
+    assert len(gh) == hp["k"] and gh[0] == wl["w0"]
+    for k in range(1, hp["k"], 997):
+        V, _ = orc.bias(gc[:k], gh[:k], wl["sigma"], gc[k])
+        assert abs(gh[k] - orc.wt_height(wl["w0"], wl["gamma"], wl["kBT"], V)) <= 1e-12 * gh[k]
+
+
+# ---------------------------------------------------------------------------
+# Determinism, call order and the sticky errors
+# ---------------------------------------------------------------------------
+def test_bitwise_determinism():
+    d = W.wurtzite_slab(8, 4, 8, seed=5)
+    n = len(d["pos"])
+    p4 = to_dev(W.as_float4(d["pos"]))
+    outs = []
+    for _ in range(2):
+        pipe = make_pipe(Q6CV, n)
+        pipe.hills_set([[float(n) * 0.4]], [0.01])
+        pipe.build_neighbors(p4, d["box"])
+        F = torch.zeros((n, 4), dtype=torch.float32, device=dev())
+        pipe.step(p4, F)
+        torch.cuda.synchronize()
+        outs.append((pipe.s.cpu().numpy().copy(), F.cpu().numpy().copy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_errors_and_call_order():
+    from paper_2510_06873_amd import GmError
+
+    d = W.wurtzite_slab(4, 3, 6, seed=21)
+    n = len(d["pos"])
+    p4 = to_dev(W.as_float4(d["pos"]))
+    pipe = make_pipe(Q6CV, n, max_neighbors=8)
+    with pytest.raises(GmError, match="STATE"):
+        pipe.cv_forward(p4)
+    with pytest.raises(GmError, match="BOX_TOO_SMALL"):
+        pipe.build_neighbors(p4, [11.9, 30.0, 30.0])
+    pipe.build_neighbors(p4, d["box"])
+    assert pipe.status(True) == -5  # rows of ~26 > 8
+    assert pipe.status(True) == 0   # cleared
+    pipe.build_neighbors_checked(p4, d["box"])
+    pipe.cv_forward(p4)
+    F = torch.zeros((n, 4), dtype=torch.float32, device=dev())
+    with pytest.raises(GmError, match="STATE"):
+        pipe.apply_bias_forces(p4, F)
+    bad = p4.clone()
+    bad[3, 1] = float("nan")
+    pipe.cv_forward(bad)
+    assert pipe.status(True) == -7
+    small = make_pipe(dict(Q6CV, hills=dict(k=0)), n, hill_capacity=2)
+    s = torch.tensor([1.0], dtype=torch.float64, device=dev())
+    for _ in range(3):
+        small.deposit_hill(s)
+    assert small.status(True) == -6
+    assert len(small.hills_get()[1]) == 2
