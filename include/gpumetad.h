@@ -176,9 +176,10 @@ int gm_status(gm_ctx* ctx, int sync);
 /* Text for a GM_* code (static storage). */
 const char* gm_strerror(int code);
 
-/* Largest row length and total entries of the last neighbour build
- * (synchronous). */
-int gm_neighbor_stats(gm_ctx* ctx, int32_t* max_count, int64_t* total);
+/* Largest row length and total entries of the last neighbour build, and the
+ * number of ordered pairs inside r_c at the last gm_cv_forward (0 before the
+ * first one).  Any output pointer may be NULL (synchronous). */
+int gm_neighbor_stats(gm_ctx* ctx, int32_t* max_count, int64_t* total, int64_t* cutoff_pairs);
 
 /* Set the neighbour-list row width (rounded up to a multiple of 4) and
  * reallocate; the lists must be rebuilt afterwards (synchronous). */
@@ -206,6 +207,37 @@ int gm_copy_neighbors(gm_ctx* ctx, int32_t* nbr_dev, int32_t* cnt_dev, int32_t* 
 #define GM_ATOM_C 3
 #define GM_ATOM_CN 4
 int gm_atom_values(gm_ctx* ctx, int what, double* dst_dev);
+
+/* ---- batches of walkers --------------------------------------------------
+ * Many independent systems ("walkers", one context each, uneven sizes, any CV
+ * kind) advanced together: every pass of the step is ONE launch for all
+ * walkers of a CV kind, driven by a device table of per-walker arguments.
+ * Each walker keeps its own lists, hills, tickets and partial sums, so its
+ * results are bitwise the same as when it is stepped alone.  Walkers must
+ * share the precision.  The batch re-binds every walker to its stream. */
+typedef struct gm_batch gm_batch;
+
+/* walkers: host array of count contexts; pos4 / force4: host arrays of count
+ * device pointers (float32 [N_w][4] positions, [N_w][4] forces of the context
+ * precision) that stay valid while the batch exists. */
+int gm_batch_create(gm_batch** out, gm_ctx* const* walkers, int32_t count, const float* const* pos4,
+                    void* const* force4, void* hip_stream);
+int gm_batch_destroy(gm_batch* batch);
+
+/* Rebuild every walker's cell and neighbour lists; boxes: host double[count][3]. */
+int gm_batch_build(gm_batch* batch, const double* boxes);
+
+/* One MD step of the bias pipeline for every walker: CV forward, bias,
+ * adjoint and F -= dV/ds ds/dx, each pass one launch per CV kind.  V and dV/ds
+ * stay in the walker's context.  GM_ERR_STATE if a walker was never built. */
+int gm_batch_step(gm_batch* batch);
+
+/* Deposit one well-tempered hill per walker at its current CV value. */
+int gm_batch_deposit(gm_batch* batch);
+
+/* Copy each walker's CV and bias (enqueued): s_dev dev double[count][2]
+ * (second column 0 for 1-D CVs), V_dev dev double[count]; either may be NULL. */
+int gm_batch_values(gm_batch* batch, double* s_dev, double* V_dev);
 
 /* Library version string. */
 const char* gm_version(void);

@@ -3,8 +3,10 @@
 The compute lives in ``libgpumetad.so`` (hand-written HIP for gfx950, C-ABI in
 ``include/gpumetad.h``); ``binding`` marshals torch tensors into it.
 """
-from .binding import (ATOM_C, ATOM_CN, ATOM_NB, ATOM_Q6, CV_COORD, CV_COORD_Q6, CV_Q6COUNT, EXPORTS, FP32,
+from .binding import (Batch, ATOM_C, ATOM_CN, ATOM_NB, ATOM_Q6, CV_COORD, CV_COORD_Q6, CV_Q6COUNT, EXPORTS, FP32,
                       FP64, GmError, Params, Pipeline, lib, version)
 
-__all__ = ["Pipeline", "Params", "GmError", "lib", "version", "EXPORTS", "CV_COORD", "CV_Q6COUNT",
+from . import autograd  # noqa: E402
+
+__all__ = ["autograd", "Batch", "Pipeline", "Params", "GmError", "lib", "version", "EXPORTS", "CV_COORD", "CV_Q6COUNT",
            "CV_COORD_Q6", "FP32", "FP64", "ATOM_Q6", "ATOM_NB", "ATOM_C", "ATOM_CN"]

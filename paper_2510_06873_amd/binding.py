@@ -29,7 +29,8 @@ EXPORTS = (
     "gm_create", "gm_destroy", "gm_set_stream", "gm_build_neighbors", "gm_cv_forward", "gm_bias_eval",
     "gm_cv_backward", "gm_apply_bias_forces", "gm_deposit_hill", "gm_hills_get", "gm_hills_set", "gm_status",
     "gm_strerror", "gm_neighbor_stats", "gm_reserve_neighbors", "gm_copy_cell_list", "gm_copy_neighbors",
-    "gm_atom_values", "gm_version",
+    "gm_atom_values", "gm_version", "gm_batch_create", "gm_batch_destroy", "gm_batch_build", "gm_batch_step",
+    "gm_batch_deposit", "gm_batch_values",
 )
 
 
@@ -70,12 +71,19 @@ def _load() -> C.CDLL:
         "gm_hills_set": ([vp, dp, dp, C.c_int64], C.c_int),
         "gm_status": ([vp, C.c_int], C.c_int),
         "gm_strerror": ([C.c_int], C.c_char_p),
-        "gm_neighbor_stats": ([vp, ip32, ip64], C.c_int),
+        "gm_neighbor_stats": ([vp, ip32, ip64, ip64], C.c_int),
         "gm_reserve_neighbors": ([vp, C.c_int32], C.c_int),
         "gm_copy_cell_list": ([vp, vp, vp, ip32], C.c_int),
         "gm_copy_neighbors": ([vp, vp, vp, ip32], C.c_int),
         "gm_atom_values": ([vp, C.c_int, vp], C.c_int),
         "gm_version": ([], C.c_char_p),
+        "gm_batch_create": ([C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p),
+                             C.POINTER(C.c_void_p), vp], C.c_int),
+        "gm_batch_destroy": ([vp], C.c_int),
+        "gm_batch_build": ([vp, dp], C.c_int),
+        "gm_batch_step": ([vp], C.c_int),
+        "gm_batch_deposit": ([vp], C.c_int),
+        "gm_batch_values": ([vp, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -163,6 +171,7 @@ class Pipeline:
         self.s = torch.zeros(self.dims, dtype=torch.float64, device=dev)
         self.V = torch.zeros(1, dtype=torch.float64, device=dev)
         self.dVds = torch.zeros(self.dims, dtype=torch.float64, device=dev)
+        self.generation = 0  # number of cv_forward calls (autograd checks it)
 
     def close(self):
         if getattr(self, "h", None):
@@ -196,6 +205,7 @@ class Pipeline:
     def cv_forward(self, pos4, s=None):
         s = self.s if s is None else s
         _check(_lib.gm_cv_forward(self.h, self._pos(pos4), self._vec(s, "s")), "gm_cv_forward")
+        self.generation += 1
         return s
 
     def bias_eval(self, s=None, V=None, dVds=None):
@@ -255,11 +265,14 @@ class Pipeline:
         _check(_lib.gm_hills_set(self.h, cen.ctypes.data_as(C.POINTER(C.c_double)),
                                  hts.ctypes.data_as(C.POINTER(C.c_double)), hts.shape[0]), "gm_hills_set")
 
-    def neighbor_stats(self):
+    def neighbor_stats(self, cutoff_pairs: bool = False):
+        """(max row length, total list entries[, ordered pairs inside r_c])."""
         m = C.c_int32()
         t = C.c_int64()
-        _check(_lib.gm_neighbor_stats(self.h, C.byref(m), C.byref(t)), "gm_neighbor_stats")
-        return m.value, t.value
+        cp = C.c_int64()
+        _check(_lib.gm_neighbor_stats(self.h, C.byref(m), C.byref(t), C.byref(cp) if cutoff_pairs else None),
+               "gm_neighbor_stats")
+        return (m.value, t.value, cp.value) if cutoff_pairs else (m.value, t.value)
 
     def reserve_neighbors(self, kmax: int):
         _check(_lib.gm_reserve_neighbors(self.h, int(kmax)), "gm_reserve_neighbors")
@@ -299,6 +312,68 @@ class Pipeline:
         _check(_lib.gm_atom_values(self.h, int(what), _ptr(out, self.n, self.torch.float64, "out")),
                "gm_atom_values")
         return out
+
+
+class Batch:
+    """Many walkers (Pipelines) stepped together: one launch per pass for all
+    walkers of a CV kind (gm_batch_*).  pos4[w] / force4[w] are the walkers'
+    resident device arrays; they must outlive the batch."""
+
+    def __init__(self, pipes, pos4, force4, stream=None):
+        import torch
+
+        self.torch = torch
+        self.pipes = list(pipes)
+        self.pos4 = list(pos4)
+        self.force4 = list(force4)
+        w = len(self.pipes)
+        if not (len(self.pos4) == len(self.force4) == w) or w == 0:
+            raise ValueError("one position and one force array per walker")
+        for p, x, f in zip(self.pipes, self.pos4, self.force4):
+            p._pos(x)
+            p._arr4(f, "force4")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        hs = (C.c_void_p * w)(*[p.h.value for p in self.pipes])
+        xs = (C.c_void_p * w)(*[x.data_ptr() for x in self.pos4])
+        fs = (C.c_void_p * w)(*[f.data_ptr() for f in self.force4])
+        h = C.c_void_p()
+        _check(_lib.gm_batch_create(C.byref(h), hs, w, xs, fs, C.c_void_p(self.stream.cuda_stream)), "gm_batch_create")
+        self.h = h
+        for p in self.pipes:
+            p.stream = self.stream
+        dev = self.pos4[0].device
+        self.s = torch.zeros((w, 2), dtype=torch.float64, device=dev)
+        self.V = torch.zeros(w, dtype=torch.float64, device=dev)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.gm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build(self, boxes):
+        import numpy as np
+
+        b = np.ascontiguousarray(boxes, dtype=np.float64).reshape(len(self.pipes), 3)
+        _check(_lib.gm_batch_build(self.h, b.ctypes.data_as(C.POINTER(C.c_double))), "gm_batch_build")
+
+    def step(self):
+        _check(_lib.gm_batch_step(self.h), "gm_batch_step")
+        for p in self.pipes:
+            p.generation += 1
+
+    def deposit(self):
+        _check(_lib.gm_batch_deposit(self.h), "gm_batch_deposit")
+
+    def values(self):
+        """(s[W, 2], V[W]) device tensors, enqueued on the batch stream."""
+        _check(_lib.gm_batch_values(self.h, self.s.data_ptr(), self.V.data_ptr()), "gm_batch_values")
+        return self.s, self.V
 
 
 def version() -> str:

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "gm_internal.h"
 
@@ -20,21 +21,29 @@ struct gm_ctx {
   double r_list = 0.0;
   double box[3] = {0, 0, 0};
   CellGeom geom;
+  BrickGeom bg;
   int64_t ncells = 0, ncells_cap = 0;
+  int64_t nbricks_cap = 0, halo_cap = 0, blocks_cap = 0;
   int32_t kmax = 0;
-  int64_t blocks = 0;
   int bias_blocks = 0;
 
+  // cell list (canonical sorted order)
   int32_t *cell = nullptr, *count = nullptr, *start = nullptr, *fill = nullptr, *perm = nullptr;
-  int32_t *nbr = nullptr, *cnt = nullptr, *err = nullptr, *stats = nullptr;
-  void *pos_s = nullptr, *qrow = nullptr, *grow = nullptr, *nb = nullptr, *cn_atom = nullptr;
-  double *part_a = nullptr, *part_b = nullptr, *s_int = nullptr;
+  // bricks
+  int32_t *brick_H = nullptr, *brick_O = nullptr, *brick_hb = nullptr, *brick_ob = nullptr, *brick_hp = nullptr;
+  int32_t *halo_rank = nullptr, *owned_slot = nullptr, *owned_rank = nullptr, *owned_hcell = nullptr;
+  // neighbour rows and the per-step in-cutoff rows (16-bit halo slots)
+  uint16_t *nbr = nullptr, *cut = nullptr;
+  int32_t *cnt = nullptr, *ccnt = nullptr, *err = nullptr, *stats = nullptr;
+  void *pos_s = nullptr, *qrow = nullptr, *grow = nullptr, *frad = nullptr, *nb = nullptr, *cn_atom = nullptr;
+  double *part_a = nullptr, *part_b = nullptr, *s_int = nullptr, *V_int = nullptr, *dV_int = nullptr;
   unsigned* tickets = nullptr;
   double *centres = nullptr, *heights = nullptr, *bias_part = nullptr;
   int64_t* hill_count = nullptr;
 
   bool built = false, fwd = false, bwd = false;
   int last_status = GM_OK;
+  int64_t version = 0;  // bumped whenever the kernel arguments may change
   YCoef<float> ycf;
   YCoef<double> ycd;
 };
@@ -115,6 +124,18 @@ int validate(const gm_params* p, int64_t n) {
   return GM_OK;
 }
 
+BrickIndex brick_index(gm_ctx* c) {
+  BrickIndex bi;
+  bi.hb = c->brick_hb;
+  bi.ob = c->brick_ob;
+  bi.hp = c->brick_hp;
+  bi.halo_rank = c->halo_rank;
+  bi.owned_slot = c->owned_slot;
+  bi.owned_rank = c->owned_rank;
+  bi.owned_hcell = c->owned_hcell;
+  return bi;
+}
+
 template <typename T>
 CvArgs<T> make_args(gm_ctx* c) {
   CvArgs<T> a;
@@ -122,7 +143,11 @@ CvArgs<T> make_args(gm_ctx* c) {
   a.pos_s = reinterpret_cast<const vec4_t<T>*>(c->pos_s);
   a.nbr = c->nbr;
   a.cnt = c->cnt;
+  a.cut = c->cut;
+  a.ccnt = c->ccnt;
   a.perm = c->perm;
+  a.bg = c->bg;
+  a.bi = brick_index(c);
   a.n = c->n;
   a.kmax = c->kmax;
   a.dims = c->dims;
@@ -149,6 +174,7 @@ CvArgs<T> make_args(gm_ctx* c) {
     a.yc = c->ycd;
   a.qrow = reinterpret_cast<T*>(c->qrow);
   a.grow = reinterpret_cast<T*>(c->grow);
+  a.frad = reinterpret_cast<vec4_t<T>*>(c->frad);
   a.nb = reinterpret_cast<T*>(c->nb);
   a.cn_atom = reinterpret_cast<T*>(c->cn_atom);
   a.part_a = c->part_a;
@@ -157,6 +183,60 @@ CvArgs<T> make_args(gm_ctx* c) {
   a.s_int = c->s_int;
   a.err = c->err;
   return a;
+}
+
+// Brick size: the most cells per brick whose expected halo (atoms of the
+// (b+2)^3 cells around it, with a 15% margin) fits the LDS staging budget and
+// whose expected owned atoms fit one pass of a 256-thread workgroup.
+void choose_bricks(gm_ctx* c, const int32_t nc[3]) {
+  const int rec = c->fp64 ? slot_bytes<double>(c->has_q6) : slot_bytes<float>(c->has_q6);
+  const int cap = kLdsBudget / rec;
+  const double rho = (double)c->n / ((double)nc[0] * nc[1] * nc[2]);
+  int best[3] = {1, 1, 1};
+  double best_own = -1.0, best_ratio = 1e30;
+  for (int bx = 1; bx <= kMaxBrick && bx <= nc[0]; bx++)
+    for (int by = 1; by <= kMaxBrick && by <= nc[1]; by++)
+      for (int bz = 1; bz <= kMaxBrick && bz <= nc[2]; bz++) {
+        const double halo = (double)(bx + 2) * (by + 2) * (bz + 2) * rho * 1.15;
+        const double own = (double)bx * by * bz * rho;
+        if (halo > cap || own > 0.95 * kBlock) continue;
+        const double ratio = halo / own;
+        if (own > best_own * 1.0001 || (own > best_own * 0.9999 && ratio < best_ratio)) {
+          best_own = own;
+          best_ratio = ratio;
+          best[0] = bx;
+          best[1] = by;
+          best[2] = bz;
+        }
+      }
+  BrickGeom& g = c->bg;
+  for (int a = 0; a < 3; a++) {
+    g.nc[a] = nc[a];
+    g.b[a] = best[a];
+    g.nb[a] = (nc[a] + best[a] - 1) / best[a];
+  }
+  g.nbricks = g.nb[0] * g.nb[1] * g.nb[2];
+  g.cap = cap;
+  g.blocks = (g.nbricks + kXcd - 1) / kXcd * kXcd;
+}
+
+// Upper bound of the total halo slots: each cell is counted once per brick
+// whose halo covers it (duplicates included when the halo wraps onto itself).
+int64_t halo_bound(const gm_ctx* c) {
+  int64_t m = 1;
+  for (int a = 0; a < 3; a++) {
+    const int n = c->bg.nc[a], b = c->bg.b[a];
+    int best = 0;
+    int* mult = new int[n]();
+    for (int o = 0; o < n; o += b) {
+      const int e = b < n - o ? b : n - o;
+      for (int p = -1; p <= e; p++) mult[((o + p) % n + n) % n]++;
+    }
+    for (int i = 0; i < n; i++) best = mult[i] > best ? mult[i] : best;
+    delete[] mult;
+    m *= best;
+  }
+  return m * c->n;
 }
 
 BiasArgs make_bias(gm_ctx* c, const double* s, int deposit) {
@@ -187,18 +267,32 @@ void free_all(gm_ctx* c) {
   dfree(c->start);
   dfree(c->fill);
   dfree(c->perm);
+  dfree(c->brick_H);
+  dfree(c->brick_O);
+  dfree(c->brick_hb);
+  dfree(c->brick_ob);
+  dfree(c->brick_hp);
+  dfree(c->halo_rank);
+  dfree(c->owned_slot);
+  dfree(c->owned_rank);
+  dfree(c->owned_hcell);
   dfree(c->nbr);
+  dfree(c->cut);
   dfree(c->cnt);
+  dfree(c->ccnt);
   dfree(c->err);
   dfree(c->stats);
   dfree(c->pos_s);
   dfree(c->qrow);
   dfree(c->grow);
+  dfree(c->frad);
   dfree(c->nb);
   dfree(c->cn_atom);
   dfree(c->part_a);
   dfree(c->part_b);
   dfree(c->s_int);
+  dfree(c->V_int);
+  dfree(c->dV_int);
   dfree(c->tickets);
   dfree(c->centres);
   dfree(c->heights);
@@ -277,7 +371,6 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   c->r_list = params->r_c + params->skin;
   int32_t km = params->max_neighbors > 0 ? params->max_neighbors : 64;
   c->kmax = (km + 3) / 4 * 4;
-  c->blocks = atom_blocks(n_atoms);
   int64_t hb = (params->hill_capacity + kBlock - 1) / kBlock;
   c->bias_blocks = (int)(hb < 1 ? 1 : (hb > 1024 ? 1024 : hb));
   make_ycoef(c->ycf);
@@ -288,27 +381,34 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   int rc = GM_OK;
   if (rc == GM_OK) rc = dalloc(&c->cell, n * 4);
   if (rc == GM_OK) rc = dalloc(&c->perm, n * 4);
+  if (rc == GM_OK) rc = dalloc(&c->owned_slot, n * 4);
+  if (rc == GM_OK) rc = dalloc(&c->owned_rank, n * 4);
+  if (rc == GM_OK) rc = dalloc(&c->owned_hcell, n * 4);
   if (rc == GM_OK) rc = dalloc(&c->cnt, n * 4);
-  if (rc == GM_OK) rc = dalloc(&c->nbr, n * (size_t)c->kmax * 4);
+  if (rc == GM_OK) rc = dalloc(&c->ccnt, n * 4);
+  if (rc == GM_OK) rc = dalloc(&c->nbr, n * (size_t)c->kmax * 2);
+  if (rc == GM_OK) rc = dalloc(&c->cut, n * (size_t)c->kmax * 2);
   if (rc == GM_OK) rc = dalloc(&c->pos_s, n * 4 * T);
   if (rc == GM_OK && c->has_q6) rc = dalloc(&c->qrow, n * 16 * T);
   if (rc == GM_OK && c->has_q6) rc = dalloc(&c->grow, n * 16 * T);
+  if (rc == GM_OK && c->has_q6) rc = dalloc(&c->frad, n * 4 * T);
   if (rc == GM_OK) rc = dalloc(&c->nb, n * T);
   if (rc == GM_OK) rc = dalloc(&c->cn_atom, n * T);
-  if (rc == GM_OK) rc = dalloc(&c->part_a, (size_t)c->blocks * 8);
-  if (rc == GM_OK) rc = dalloc(&c->part_b, (size_t)c->blocks * 8);
   if (rc == GM_OK) rc = dalloc(&c->s_int, 16);
+  if (rc == GM_OK) rc = dalloc(&c->V_int, 16);
+  if (rc == GM_OK) rc = dalloc(&c->dV_int, 16);
   if (rc == GM_OK) rc = dalloc(&c->tickets, 16);
   if (rc == GM_OK) rc = dalloc(&c->err, 16);
-  if (rc == GM_OK) rc = dalloc(&c->stats, 16);
+  if (rc == GM_OK) rc = dalloc(&c->stats, 32);
   if (rc == GM_OK) rc = dalloc(&c->centres, cap * c->dims * 8);
   if (rc == GM_OK) rc = dalloc(&c->heights, cap * 8);
   if (rc == GM_OK) rc = dalloc(&c->hill_count, 16);
   if (rc == GM_OK) rc = dalloc(&c->bias_part, (size_t)c->bias_blocks * 3 * 8);
   if (rc == GM_OK) {
     bool ok = hipMemset(c->tickets, 0, 16) == hipSuccess && hipMemset(c->err, 0, 16) == hipSuccess &&
-              hipMemset(c->hill_count, 0, 16) == hipSuccess && hipMemset(c->stats, 0, 16) == hipSuccess &&
-              hipMemset(c->s_int, 0, 16) == hipSuccess && hipMemset(c->cn_atom, 0, n * T) == hipSuccess &&
+              hipMemset(c->hill_count, 0, 16) == hipSuccess && hipMemset(c->stats, 0, 32) == hipSuccess &&
+              hipMemset(c->s_int, 0, 16) == hipSuccess && hipMemset(c->V_int, 0, 16) == hipSuccess &&
+              hipMemset(c->dV_int, 0, 16) == hipSuccess && hipMemset(c->cn_atom, 0, n * T) == hipSuccess &&
               hipMemset(c->nb, 0, n * T) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
     if (!ok) rc = GM_ERR_HIP;
   }
@@ -332,6 +432,44 @@ int gm_destroy(gm_ctx* c) {
 int gm_set_stream(gm_ctx* c, void* hip_stream) {
   if (!c) return GM_ERR_INVALID_ARG;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->version++;
+  return GM_OK;
+}
+
+// (Re)allocate the brick tables for the current brick geometry.
+static int reserve_bricks(gm_ctx* c) {
+  const int64_t nbk = c->bg.nbricks, blocks = c->bg.blocks, hbound = halo_bound(c);
+  const bool grow_b = nbk > c->nbricks_cap, grow_h = hbound > c->halo_cap, grow_p = blocks > c->blocks_cap;
+  if (!(grow_b || grow_h || grow_p)) return GM_OK;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
+  if (grow_b) {
+    dfree(c->brick_H);
+    dfree(c->brick_O);
+    dfree(c->brick_hb);
+    dfree(c->brick_ob);
+    dfree(c->brick_hp);
+    c->nbricks_cap = 0;
+    GM_TRY(dalloc(&c->brick_H, (size_t)nbk * 4));
+    GM_TRY(dalloc(&c->brick_O, (size_t)nbk * 4));
+    GM_TRY(dalloc(&c->brick_hb, (size_t)(nbk + 1) * 4));
+    GM_TRY(dalloc(&c->brick_ob, (size_t)(nbk + 1) * 4));
+    GM_TRY(dalloc(&c->brick_hp, (size_t)nbk * (kHaloCells + 1) * 4));
+    c->nbricks_cap = nbk;
+  }
+  if (grow_h) {
+    dfree(c->halo_rank);
+    c->halo_cap = 0;
+    GM_TRY(dalloc(&c->halo_rank, (size_t)hbound * 4));
+    c->halo_cap = hbound;
+  }
+  if (grow_p) {
+    dfree(c->part_a);
+    dfree(c->part_b);
+    c->blocks_cap = 0;
+    GM_TRY(dalloc(&c->part_a, (size_t)blocks * 8));
+    GM_TRY(dalloc(&c->part_b, (size_t)blocks * 8));
+    c->blocks_cap = blocks;
+  }
   return GM_OK;
 }
 
@@ -365,29 +503,39 @@ int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
     c->geom.invL[a] = 1.0 / box[a];
     c->geom.nc[a] = nc[a];
   }
+  choose_bricks(c, nc);
+  GM_TRY(reserve_bricks(c));
   hipStream_t st = c->stream;
   const float4* p4 = reinterpret_cast<const float4*>(pos4);
   c->built = c->fwd = c->bwd = false;
+  // canonical cell list: counts, scan, scatter, per-cell sort by atom id
   GM_TRY(hip_rc(launch_fill_i32(c->count, 0, ncells, st)));
   GM_TRY(hip_rc(launch_fill_i32(c->stats, 0, 4, st)));
   GM_TRY(hip_rc(launch_cell_ids(p4, c->n, c->geom, c->cell, c->count, c->err, st)));
-  GM_TRY(hip_rc(launch_scan_cells(c->count, ncells, c->start, c->fill, st)));
+  GM_TRY(hip_rc(launch_scan(c->count, ncells, c->start, c->fill, st)));
   GM_TRY(hip_rc(launch_scatter(c->cell, c->n, c->start, c->fill, c->perm, st)));
   GM_TRY(hip_rc(launch_sort_cells(c->start, ncells, c->perm, st)));
-  unsigned long long* total = reinterpret_cast<unsigned long long*>(c->stats + 2);
+  // bricks: halo and owned sizes, their prefix sums, the slot tables
+  GM_TRY(hip_rc(launch_brick_count(c->start, c->bg, c->brick_H, c->brick_O, st)));
+  GM_TRY(hip_rc(launch_scan(c->brick_H, c->bg.nbricks, c->brick_hb, nullptr, st)));
+  GM_TRY(hip_rc(launch_scan(c->brick_O, c->bg.nbricks, c->brick_ob, nullptr, st)));
+  const BrickIndex bi = brick_index(c);
+  GM_TRY(hip_rc(launch_brick_fill(c->start, c->bg, bi, c->brick_hp, c->halo_rank, c->owned_slot, c->owned_rank,
+                                  c->owned_hcell, c->err, st)));
   const double rl2 = c->r_list * c->r_list;
   if (c->fp64) {
     auto* ps = reinterpret_cast<double4*>(c->pos_s);
     GM_TRY(hip_rc(launch_gather<double>(p4, c->perm, c->n, ps, c->err, st)));
-    GM_TRY(hip_rc(launch_build_nbr<double>(ps, c->n, c->geom, rl2, c->start, c->nbr, c->kmax, c->cnt, c->err,
-                                           c->stats, total, st)));
+    GM_TRY(hip_rc(launch_build_nbr<double>(ps, c->geom, c->bg, bi, rl2, c->nbr, c->kmax, c->cnt, c->err, c->stats,
+                                           st)));
   } else {
     auto* ps = reinterpret_cast<float4*>(c->pos_s);
     GM_TRY(hip_rc(launch_gather<float>(p4, c->perm, c->n, ps, c->err, st)));
-    GM_TRY(hip_rc(launch_build_nbr<float>(ps, c->n, c->geom, rl2, c->start, c->nbr, c->kmax, c->cnt, c->err,
-                                          c->stats, total, st)));
+    GM_TRY(hip_rc(launch_build_nbr<float>(ps, c->geom, c->bg, bi, rl2, c->nbr, c->kmax, c->cnt, c->err, c->stats,
+                                          st)));
   }
   c->built = true;
+  c->version++;
   return GM_OK;
 }
 
@@ -480,17 +628,25 @@ int gm_status(gm_ctx* c, int sync) {
   return c->last_status;
 }
 
-int gm_neighbor_stats(gm_ctx* c, int32_t* max_count, int64_t* total) {
+int gm_neighbor_stats(gm_ctx* c, int32_t* max_count, int64_t* total, int64_t* cutoff_pairs) {
   if (!c) return GM_ERR_INVALID_ARG;
   if (!c->built) return GM_ERR_STATE;
+  if (cutoff_pairs) {
+    GM_TRY(hip_rc(launch_fill_i32(c->stats + 4, 0, 2, c->stream)));
+    if (c->fwd) GM_TRY(hip_rc(launch_sum_i32(c->ccnt, c->n, reinterpret_cast<unsigned long long*>(c->stats + 4), c->stream)));
+  }
   if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
-  int32_t s[4];
-  if (hipMemcpy(s, c->stats, 16, hipMemcpyDeviceToHost) != hipSuccess) return GM_ERR_HIP;
+  int32_t s[8];
+  if (hipMemcpy(s, c->stats, 32, hipMemcpyDeviceToHost) != hipSuccess) return GM_ERR_HIP;
   if (max_count) *max_count = s[0];
+  unsigned long long t;
   if (total) {
-    unsigned long long t;
     memcpy(&t, &s[2], 8);
     *total = (int64_t)t;
+  }
+  if (cutoff_pairs) {
+    memcpy(&t, &s[4], 8);
+    *cutoff_pairs = (int64_t)t;
   }
   return GM_OK;
 }
@@ -499,9 +655,12 @@ int gm_reserve_neighbors(gm_ctx* c, int32_t max_neighbors) {
   if (!c || max_neighbors < 1 || max_neighbors > 4096) return GM_ERR_INVALID_ARG;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
   dfree(c->nbr);
+  dfree(c->cut);
   c->kmax = (max_neighbors + 3) / 4 * 4;
   c->built = c->fwd = c->bwd = false;
-  return dalloc(&c->nbr, (size_t)c->n * c->kmax * 4);
+  c->version++;
+  GM_TRY(dalloc(&c->nbr, (size_t)c->n * c->kmax * 2));
+  return dalloc(&c->cut, (size_t)c->n * c->kmax * 2);
 }
 
 int gm_copy_cell_list(gm_ctx* c, int32_t* perm_dev, int32_t* cell_start_dev, int32_t* ncell) {
@@ -520,13 +679,10 @@ int gm_copy_cell_list(gm_ctx* c, int32_t* perm_dev, int32_t* cell_start_dev, int
 int gm_copy_neighbors(gm_ctx* c, int32_t* nbr_dev, int32_t* cnt_dev, int32_t* row_width) {
   if (!c) return GM_ERR_INVALID_ARG;
   if (!c->built) return GM_ERR_STATE;
-  if (nbr_dev && hipMemcpyAsync(nbr_dev, c->nbr, (size_t)c->n * c->kmax * 4, hipMemcpyDeviceToDevice,
-                                c->stream) != hipSuccess)
-    return GM_ERR_HIP;
-  if (cnt_dev && hipMemcpyAsync(cnt_dev, c->cnt, (size_t)c->n * 4, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
-    return GM_ERR_HIP;
   if (row_width) *row_width = c->kmax;
-  return GM_OK;
+  if (!nbr_dev && !cnt_dev) return GM_OK;
+  if (!nbr_dev || !cnt_dev) return GM_ERR_INVALID_ARG;
+  return hip_rc(launch_neighbor_ranks(c->nbr, c->cnt, c->bg, brick_index(c), c->kmax, nbr_dev, cnt_dev, c->stream));
 }
 
 int gm_atom_values(gm_ctx* c, int what, double* dst_dev) {
@@ -535,6 +691,230 @@ int gm_atom_values(gm_ctx* c, int what, double* dst_dev) {
   if ((what != GM_ATOM_CN && !c->has_q6) || (what == GM_ATOM_CN && !c->has_cn)) return GM_ERR_INVALID_ARG;
   if (c->fp64) return hip_rc(launch_atom_values<double>(make_args<double>(c), what, c->p.cv_kind, dst_dev, c->stream));
   return hip_rc(launch_atom_values<float>(make_args<float>(c), what, c->p.cv_kind, dst_dev, c->stream));
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------------------
+// Batches of walkers
+// --------------------------------------------------------------------------
+struct gm_batch {
+  hipStream_t stream = nullptr;
+  std::vector<gm_ctx*> walkers;
+  std::vector<const float*> pos;
+  std::vector<void*> force;
+  struct Group {
+    int kind = 0;                 // GM_CV_*
+    std::vector<int> members;     // indices into walkers
+    std::vector<int64_t> versions;
+    std::vector<unsigned char> h_cv, h_gather, h_bias, h_dep;  // host images of the tables
+    void *d_cv = nullptr, *d_gather = nullptr, *d_bias = nullptr, *d_dep = nullptr;
+    int32_t *d_blk_cv = nullptr, *d_blk_gather = nullptr, *d_blk_bias = nullptr;
+    int32_t blocks_cv = 0, blocks_gather = 0, blocks_bias = 0, cap = 0;
+  };
+  std::vector<Group> groups;
+  bool fp64 = false;
+};
+
+namespace {
+
+template <typename T>
+void append(std::vector<unsigned char>& v, const T& x) {
+  const unsigned char* p = reinterpret_cast<const unsigned char*>(&x);
+  v.insert(v.end(), p, p + sizeof(T));
+}
+
+int upload(std::vector<unsigned char>& host, void** dev, hipStream_t st) {
+  dfree(*dev);
+  GM_TRY(dalloc(dev, host.size()));
+  if (hipMemcpyAsync(*dev, host.data(), host.size(), hipMemcpyHostToDevice, st) != hipSuccess) return GM_ERR_HIP;
+  return hipStreamSynchronize(st) == hipSuccess ? GM_OK : GM_ERR_HIP;
+}
+
+int upload_i32(const std::vector<int32_t>& v, int32_t** dev, hipStream_t st) {
+  std::vector<unsigned char> h(reinterpret_cast<const unsigned char*>(v.data()),
+                               reinterpret_cast<const unsigned char*>(v.data()) + v.size() * 4);
+  void* d = *dev;
+  int rc = upload(h, &d, st);
+  *dev = reinterpret_cast<int32_t*>(d);
+  return rc;
+}
+
+// Rebuild the device tables of a group if any walker changed since the last time.
+template <typename T>
+int refresh_group(gm_batch* B, gm_batch::Group& g, bool force) {
+  bool stale = force || g.versions.size() != g.members.size();
+  for (size_t i = 0; !stale && i < g.members.size(); i++) stale = g.versions[i] != B->walkers[g.members[i]]->version;
+  if (!stale) return GM_OK;
+  std::vector<unsigned char> cv, ga, bi, de;
+  std::vector<int32_t> bcv{0}, bga{0}, bbi{0};
+  g.versions.clear();
+  g.cap = 0;
+  for (int m : g.members) {
+    gm_ctx* c = B->walkers[m];
+    if (!c->built) return GM_ERR_STATE;
+    CvArgs<T> a = make_args<T>(c);
+    a.s_out = nullptr;
+    a.seed = c->dV_int;
+    a.mode = 0;
+    a.out4 = B->force[m];
+    append(cv, a);
+    GatherArgs gth{reinterpret_cast<const float4*>(B->pos[m]), c->perm, c->n, c->pos_s, c->err};
+    append(ga, gth);
+    BiasArgs ev = make_bias(c, c->s_int, 0);
+    ev.V_out = c->V_int;
+    ev.dV_out = c->dV_int;
+    append(bi, ev);
+    append(de, make_bias(c, c->s_int, 1));
+    bcv.push_back(bcv.back() + c->bg.blocks);
+    bga.push_back(bga.back() + (int32_t)((c->n + kBlock - 1) / kBlock));
+    bbi.push_back(bbi.back() + c->bias_blocks);
+    g.cap = c->bg.cap > g.cap ? c->bg.cap : g.cap;
+    g.versions.push_back(c->version);
+  }
+  g.blocks_cv = bcv.back();
+  g.blocks_gather = bga.back();
+  g.blocks_bias = bbi.back();
+  if (force || cv != g.h_cv) GM_TRY(upload(cv, &g.d_cv, B->stream));
+  if (force || ga != g.h_gather) GM_TRY(upload(ga, &g.d_gather, B->stream));
+  if (force || bi != g.h_bias) GM_TRY(upload(bi, &g.d_bias, B->stream));
+  if (force || de != g.h_dep) GM_TRY(upload(de, &g.d_dep, B->stream));
+  GM_TRY(upload_i32(bcv, &g.d_blk_cv, B->stream));
+  GM_TRY(upload_i32(bga, &g.d_blk_gather, B->stream));
+  GM_TRY(upload_i32(bbi, &g.d_blk_bias, B->stream));
+  g.h_cv.swap(cv);
+  g.h_gather.swap(ga);
+  g.h_bias.swap(bi);
+  g.h_dep.swap(de);
+  return GM_OK;
+}
+
+template <typename T>
+int batch_step_t(gm_batch* B) {
+  for (auto& g : B->groups) {
+    GM_TRY(refresh_group<T>(B, g, false));
+    const int32_t W = (int32_t)g.members.size();
+    auto* tab = reinterpret_cast<const CvArgs<T>*>(g.d_cv);
+    const bool q6 = g.kind != GM_CV_COORD, cn = g.kind != GM_CV_Q6COUNT;
+    hipStream_t st = B->stream;
+    GM_TRY(hip_rc(launch_gather_batch<T>(reinterpret_cast<const GatherArgs*>(g.d_gather), g.d_blk_gather, W,
+                                         g.blocks_gather, st)));
+    if (q6) {
+      GM_TRY(hip_rc(launch_pass_batch<T>(1, cn, true, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
+      GM_TRY(hip_rc(launch_pass_batch<T>(2, cn, true, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
+    } else {
+      GM_TRY(hip_rc(launch_pass_batch<T>(5, true, false, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
+    }
+    GM_TRY(hip_rc(launch_bias_batch(reinterpret_cast<const BiasArgs*>(g.d_bias), g.d_blk_bias, W, g.blocks_bias, st)));
+    if (q6) {
+      GM_TRY(hip_rc(launch_pass_batch<T>(3, cn, true, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
+      GM_TRY(hip_rc(launch_pass_batch<T>(4, cn, true, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
+    } else {
+      GM_TRY(hip_rc(launch_pass_batch<T>(6, true, false, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
+    }
+    for (int m : g.members) B->walkers[m]->fwd = B->walkers[m]->bwd = true;
+  }
+  return GM_OK;
+}
+
+void free_batch(gm_batch* B) {
+  for (auto& g : B->groups) {
+    dfree(g.d_cv);
+    dfree(g.d_gather);
+    dfree(g.d_bias);
+    dfree(g.d_dep);
+    dfree(g.d_blk_cv);
+    dfree(g.d_blk_gather);
+    dfree(g.d_blk_bias);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int gm_batch_create(gm_batch** out, gm_ctx* const* walkers, int32_t count, const float* const* pos4,
+                    void* const* force4, void* hip_stream) {
+  if (!out) return GM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!walkers || !pos4 || !force4 || count < 1) return GM_ERR_INVALID_ARG;
+  gm_batch* B = new (std::nothrow) gm_batch();
+  if (!B) return GM_ERR_OOM;
+  B->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  B->fp64 = walkers[0] && walkers[0]->fp64;
+  for (int32_t i = 0; i < count; i++) {
+    gm_ctx* c = walkers[i];
+    const size_t vs = B->fp64 ? 32 : 16;
+    if (!c || !pos4[i] || !force4[i] || c->fp64 != B->fp64 || !aligned(pos4[i], 16) || !aligned(force4[i], vs)) {
+      delete B;
+      return GM_ERR_INVALID_ARG;
+    }
+    for (int32_t j = 0; j < i; j++)
+      if (walkers[j] == c) {
+        delete B;
+        return GM_ERR_INVALID_ARG;
+      }
+    B->walkers.push_back(c);
+    B->pos.push_back(pos4[i]);
+    B->force.push_back(force4[i]);
+  }
+  for (int kind = GM_CV_COORD; kind <= GM_CV_COORD_Q6; kind++) {
+    gm_batch::Group g;
+    g.kind = kind;
+    for (int32_t i = 0; i < count; i++)
+      if (walkers[i]->p.cv_kind == kind) g.members.push_back(i);
+    if (!g.members.empty()) B->groups.push_back(std::move(g));
+  }
+  for (gm_ctx* c : B->walkers) {
+    c->stream = B->stream;
+    c->version++;
+  }
+  *out = B;
+  return GM_OK;
+}
+
+int gm_batch_destroy(gm_batch* B) {
+  if (!B) return GM_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(B->stream);
+  free_batch(B);
+  delete B;
+  return GM_OK;
+}
+
+int gm_batch_build(gm_batch* B, const double* boxes) {
+  if (!B || !boxes) return GM_ERR_INVALID_ARG;
+  for (size_t i = 0; i < B->walkers.size(); i++)
+    GM_TRY(gm_build_neighbors(B->walkers[i], B->pos[i], boxes + 3 * i));
+  return GM_OK;
+}
+
+int gm_batch_step(gm_batch* B) {
+  if (!B) return GM_ERR_INVALID_ARG;
+  for (gm_ctx* c : B->walkers)
+    if (!c->built) return GM_ERR_STATE;
+  return B->fp64 ? batch_step_t<double>(B) : batch_step_t<float>(B);
+}
+
+int gm_batch_deposit(gm_batch* B) {
+  if (!B) return GM_ERR_INVALID_ARG;
+  for (auto& g : B->groups) {
+    GM_TRY(B->fp64 ? refresh_group<double>(B, g, false) : refresh_group<float>(B, g, false));
+    GM_TRY(hip_rc(launch_bias_batch(reinterpret_cast<const BiasArgs*>(g.d_dep), g.d_blk_bias,
+                                    (int32_t)g.members.size(), g.blocks_bias, B->stream)));
+  }
+  return GM_OK;
+}
+
+int gm_batch_values(gm_batch* B, double* s_dev, double* V_dev) {
+  if (!B) return GM_ERR_INVALID_ARG;
+  for (size_t i = 0; i < B->walkers.size(); i++) {
+    gm_ctx* c = B->walkers[i];
+    if (s_dev && hipMemcpyAsync(s_dev + 2 * i, c->s_int, 16, hipMemcpyDeviceToDevice, B->stream) != hipSuccess)
+      return GM_ERR_HIP;
+    if (V_dev && hipMemcpyAsync(V_dev + i, c->V_int, 8, hipMemcpyDeviceToDevice, B->stream) != hipSuccess)
+      return GM_ERR_HIP;
+  }
+  return GM_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,97 @@
+// Gaussian-hill bias on the device, FP64: evaluation of V and dV/ds, and the
+// deposition of one well-tempered hill.  Fixed-order sums (thread -> wave ->
+// block -> last block over the block partials), so results are reproducible.
+#include "gm_device.h"
+
+namespace gm {
+
+// --------------------------------------------------------------------------
+// Gaussian-hill bias (FP64): evaluation, or deposition of one hill.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void bias_body(const BiasArgs& a, int32_t blk, int32_t nblk) {
+  __shared__ double red[kBlock / 64];
+  const int64_t K = *a.count;
+  double s[2] = {a.s[0], a.dims > 1 ? a.s[1] : 0.0};
+  double v = 0.0, g0 = 0.0, g1 = 0.0;
+  const int64_t stride = (int64_t)nblk * blockDim.x;
+  for (int64_t k = (int64_t)blk * blockDim.x + threadIdx.x; k < K; k += stride) {
+    const double x0 = s[0] - a.centres[k * a.dims];
+    double arg = x0 * x0 * a.inv2s2[0];
+    double x1 = 0.0;
+    if (a.dims > 1) {
+      x1 = s[1] - a.centres[k * a.dims + 1];
+      arg += x1 * x1 * a.inv2s2[1];
+    }
+    const double e = a.heights[k] * exp(-arg);
+    v += e;
+    g0 -= e * x0 * a.invs2[0];
+    g1 -= e * x1 * a.invs2[1];
+  }
+  v = block_sum(v, red);
+  g0 = block_sum(g0, red);
+  if (a.dims > 1) g1 = block_sum(g1, red);
+  if (threadIdx.x == 0) {
+    store_agent(&a.part[blk * 3 + 0], v);
+    store_agent(&a.part[blk * 3 + 1], g0);
+    store_agent(&a.part[blk * 3 + 2], g1);
+  }
+  if (last_block_done(a.ticket, nblk)) {
+    double V = 0.0, G0 = 0.0, G1 = 0.0;
+    for (int64_t i = threadIdx.x; i < (int64_t)nblk; i += blockDim.x) {
+      V += load_agent(&a.part[i * 3 + 0]);
+      G0 += load_agent(&a.part[i * 3 + 1]);
+      G1 += load_agent(&a.part[i * 3 + 2]);
+    }
+    V = block_sum(V, red);
+    G0 = block_sum(G0, red);
+    if (a.dims > 1) G1 = block_sum(G1, red);
+    if (threadIdx.x == 0) {
+      if (!isfinite(V)) atomicOr(a.err, kErrNonFinite);
+      if (a.deposit) {
+        const double h = a.wt_scale == 0.0 ? a.w0 : a.w0 * exp(-V * a.wt_scale);
+        if (K < a.capacity) {
+          for (int d = 0; d < a.dims; d++) a.centres[K * a.dims + d] = s[d];
+          a.heights[K] = h;
+          *a.count = K + 1;
+        } else {
+          atomicOr(a.err, kErrCapacity);
+        }
+      } else {
+        if (a.V_out) a.V_out[0] = V;
+        if (a.dV_out) {
+          a.dV_out[0] = G0;
+          if (a.dims > 1) a.dV_out[1] = G1;
+        }
+      }
+    }
+    release_ticket(a.ticket);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bias(BiasArgs a) { bias_body(a, blockIdx.x, gridDim.x); }
+
+// One launch for many walkers: workgroup g serves walker w with
+// blk_start[w] <= g < blk_start[w+1].
+__global__ __launch_bounds__(kBlock) void k_bias_batch(const BiasArgs* __restrict__ tab,
+                                                       const int32_t* __restrict__ blk_start, int32_t W) {
+  const int64_t g = blockIdx.x;
+  int32_t lo = 0, hi = W;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (blk_start[mid] <= g) lo = mid; else hi = mid;
+  }
+  bias_body(tab[lo], (int32_t)(g - blk_start[lo]), blk_start[lo + 1] - blk_start[lo]);
+}
+
+hipError_t launch_bias_batch(const BiasArgs* tab, const int32_t* blk_start, int32_t W, int32_t blocks,
+                             hipStream_t st) {
+  k_bias_batch<<<(unsigned)blocks, kBlock, 0, st>>>(tab, blk_start, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias(const BiasArgs& a, int blocks, hipStream_t st) {
+  k_bias<<<(unsigned)blocks, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace gm

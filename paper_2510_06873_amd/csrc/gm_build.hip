@@ -1,0 +1,445 @@
+// Cell list, brick tables and neighbour list of libgpumetad (every rebuild).
+//
+// The cell list is a stable counting sort of atoms by cell id (counts ->
+// exclusive scan -> atomic scatter -> per-cell sort by atom id), bit-exact
+// against a plain sequential sort.  The cell grid is then cut into bricks
+// that one workgroup each handles; a brick's atoms and its one-cell halo are
+// addressed by "slots" in halo-cell order, which is also how the neighbour
+// rows refer to neighbours (16-bit entries).
+#include "gm_device.h"
+
+namespace gm {
+
+// --------------------------------------------------------------------------
+// Cell list and neighbour list (every rebuild)
+// --------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+// Cell coordinates of one position, FP64 with no contraction so that the
+// ids match a plain IEEE evaluation of w = x - L floor(x/L),
+// c = clamp(floor(w * n/L), 0, n-1).
+__device__ __forceinline__ bool cell_coords(float4 p, const CellGeom& g, int32_t c[3]) {
+#pragma clang fp contract(off)
+  const double x[3] = {(double)p.x, (double)p.y, (double)p.z};
+  bool ok = true;
+  for (int a = 0; a < 3; a++) {
+    if (!isfinite(x[a])) {
+      ok = false;
+      c[a] = 0;
+      continue;
+    }
+    double w = x[a] - g.L[a] * floor(x[a] / g.L[a]);
+    double f = floor(w * g.inv[a]);
+    f = f < 0.0 ? 0.0 : f;
+    f = f > (double)(g.nc[a] - 1) ? (double)(g.nc[a] - 1) : f;
+    c[a] = (int32_t)f;
+  }
+  return ok;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_ids(const float4* __restrict__ pos, int64_t n,
+                                                     CellGeom g, int32_t* __restrict__ cell,
+                                                     int32_t* __restrict__ count, int32_t* err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t c[3];
+  if (!cell_coords(pos[i], g, c)) atomicOr(err, kErrNonFinite);
+  int32_t id = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
+  cell[i] = id;
+  atomicAdd(&count[id], 1);
+}
+
+// Exclusive prefix sum of n int32 values in one block of 1024 threads: each
+// thread sums a contiguous chunk, the chunk sums are scanned in LDS, then each
+// thread writes its chunk; out[n] receives the total.  If zero != NULL it is
+// cleared alongside (the scatter cursors of the cell sort).
+__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ in, int64_t n,
+                                               int32_t* __restrict__ out, int32_t* __restrict__ zero) {
+  __shared__ int32_t sums[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b = tid * per;
+  const int64_t e = b + per < n ? b + per : n;
+  int32_t s = 0;
+  for (int64_t i = b; i < e; i++) s += in[i];
+  sums[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int32_t v = tid >= off ? sums[tid - off] : 0;
+    __syncthreads();
+    sums[tid] += v;
+    __syncthreads();
+  }
+  int32_t run = sums[tid] - s;
+  for (int64_t i = b; i < e; i++) {
+    const int32_t c = in[i];
+    out[i] = run;
+    run += c;
+    if (zero) zero[i] = 0;
+  }
+  if (tid == 1023) out[n] = sums[1023];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ cell, int64_t n,
+                                                    const int32_t* __restrict__ start,
+                                                    int32_t* __restrict__ fill, int32_t* __restrict__ perm) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t c = cell[i];
+  int32_t slot = atomicAdd(&fill[c], 1);
+  perm[start[c] + slot] = (int32_t)i;
+}
+
+// The atomic scatter leaves each cell's atoms in arbitrary order; sorting each
+// (short) segment by atom id makes the permutation the unique stable order.
+__global__ __launch_bounds__(kBlock) void k_sort_cells(const int32_t* __restrict__ start, int64_t ncells,
+                                                       int32_t* __restrict__ perm) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  const int32_t b = start[c], e = start[c + 1];
+  for (int32_t i = b + 1; i < e; i++) {
+    int32_t v = perm[i];
+    int32_t k = i - 1;
+    while (k >= b && perm[k] > v) {
+      perm[k + 1] = perm[k];
+      k--;
+    }
+    perm[k + 1] = v;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void gather_body(const float4* __restrict__ pos, const int32_t* __restrict__ perm, int64_t n,
+                                            vec4_t<T>* __restrict__ pos_s, int32_t* err, int64_t t) {
+  if (t >= n) return;
+  float4 p = pos[perm[t]];
+  if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z))) atomicOr(err, kErrNonFinite);
+  vec4_t<T> q;
+  q.x = (T)p.x;
+  q.y = (T)p.y;
+  q.z = (T)p.z;
+  q.w = (T)p.w;
+  pos_s[t] = q;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather(const float4* __restrict__ pos, const int32_t* __restrict__ perm,
+                                                   int64_t n, vec4_t<T>* __restrict__ pos_s, int32_t* err) {
+  gather_body<T>(pos, perm, n, pos_s, err, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_batch(const GatherArgs* __restrict__ tab,
+                                                         const int32_t* __restrict__ blk_start, int32_t W) {
+  const int64_t g = blockIdx.x;
+  int32_t lo = 0, hi = W;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (blk_start[mid] <= g) lo = mid; else hi = mid;
+  }
+  const GatherArgs& a = tab[lo];
+  gather_body<T>(a.pos, a.perm, a.n, reinterpret_cast<vec4_t<T>*>(a.pos_s), a.err,
+                 (g - blk_start[lo]) * blockDim.x + threadIdx.x);
+}
+
+// --------------------------------------------------------------------------
+// Bricks: halo sizes, halo slot tables, owned atoms (every rebuild)
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_brick_count(const int32_t* __restrict__ start, BrickGeom g,
+                                                        int32_t* __restrict__ H, int32_t* __restrict__ O) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= g.nbricks) return;
+  const BrickShape s = brick_shape(b, g);
+  int32_t h = 0, own = 0;
+  for (int hz = 0; hz < s.h[2]; hz++)
+    for (int hy = 0; hy < s.h[1]; hy++)
+      for (int hx = 0; hx < s.h[0]; hx++) {
+        const int32_t c = halo_cell_id(s, g, hx, hy, hz);
+        const int32_t k = start[c + 1] - start[c];
+        h += k;
+        if (hx >= 1 && hx <= s.e[0] && hy >= 1 && hy <= s.e[1] && hz >= 1 && hz <= s.e[2]) own += k;
+      }
+  H[b] = h;
+  O[b] = own;
+}
+
+// One workgroup per brick: slot prefix over the halo cells, the sorted
+// position of every halo slot, and for every owned atom its slot, sorted
+// position and own halo cell.
+__global__ __launch_bounds__(kBlock) void k_brick_fill(const int32_t* __restrict__ start, BrickGeom g, BrickIndex bi,
+                                                       int32_t* __restrict__ hp_out, int32_t* __restrict__ halo_rank,
+                                                       int32_t* __restrict__ owned_slot, int32_t* __restrict__ owned_rank,
+                                                       int32_t* __restrict__ owned_hcell, int32_t* err) {
+  __shared__ int32_t hcell[kHaloCells], hpre[kHaloCells + 1];
+  __shared__ int32_t oh[kOwnCells], opre[kOwnCells + 1];
+  const int64_t b = blockIdx.x;
+  const BrickShape s = brick_shape(b, g);
+  const int nh = s.h[0] * s.h[1] * s.h[2];
+  const int no = s.e[0] * s.e[1] * s.e[2];
+  for (int h = threadIdx.x; h < nh; h += blockDim.x) {
+    const int hx = h % s.h[0], hy = (h / s.h[0]) % s.h[1], hz = h / (s.h[0] * s.h[1]);
+    const int32_t c = halo_cell_id(s, g, hx, hy, hz);
+    hcell[h] = c;
+    hpre[h + 1] = start[c + 1] - start[c];
+  }
+  for (int k = threadIdx.x; k < no; k += blockDim.x) {
+    const int ox = k % s.e[0], oy = (k / s.e[0]) % s.e[1], oz = k / (s.e[0] * s.e[1]);
+    oh[k] = ((oz + 1) * s.h[1] + (oy + 1)) * s.h[0] + (ox + 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    hpre[0] = 0;
+    for (int h = 0; h < nh; h++) hpre[h + 1] += hpre[h];
+    opre[0] = 0;
+    for (int k = 0; k < no; k++) opre[k + 1] = opre[k] + (hpre[oh[k] + 1] - hpre[oh[k]]);
+    if (hpre[nh] > 65535) atomicOr(err, kErrOverflow);  // slots must fit 16 bits
+  }
+  __syncthreads();
+  int32_t* hp = hp_out + b * (kHaloCells + 1);
+  for (int h = threadIdx.x; h <= nh; h += blockDim.x) hp[h] = hpre[h];
+  const int32_t hb = bi.hb[b], H = bi.hb[b + 1] - hb;
+  for (int32_t sl = threadIdx.x; sl < H; sl += blockDim.x) {
+    int lo = 0, hi = nh;  // find h with hpre[h] <= sl < hpre[h+1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (hpre[mid] <= sl) lo = mid; else hi = mid;
+    }
+    halo_rank[hb + sl] = start[hcell[lo]] + (sl - hpre[lo]);
+  }
+  const int32_t ob = bi.ob[b], O = bi.ob[b + 1] - ob;
+  for (int32_t k = threadIdx.x; k < O; k += blockDim.x) {
+    int lo = 0, hi = no;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (opre[mid] <= k) lo = mid; else hi = mid;
+    }
+    const int h = oh[lo];
+    const int32_t idx = k - opre[lo];
+    owned_slot[ob + k] = hpre[h] + idx;
+    owned_rank[ob + k] = start[hcell[h]] + idx;
+    owned_hcell[ob + k] = h;
+  }
+}
+
+// Full neighbour rows as halo slots.  The pair test is FP64 on the FP32
+// coordinates, no contraction: d = x_j - x_i, d -= L rint(d/L),
+// r^2 = (dx dx + dy dy) + dz dz < r_list^2.  (rint(d * (1/L)) picks the same
+// image as rint(d / L) for every pair that can pass the test, since such pairs
+// have |d/L| far from a half integer.)  Candidates are the atoms of the 27
+// cells around the atom's own cell, visited in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_build_nbr(const vec4_t<T>* __restrict__ pos_s, CellGeom cg, BrickGeom g,
+                                                      BrickIndex bi, double rl2, uint16_t* __restrict__ nbr,
+                                                      int32_t kmax, int32_t* __restrict__ cnt, int32_t* err,
+                                                      int32_t* stats) {
+#pragma clang fp contract(off)
+  extern __shared__ __align__(16) unsigned char smem[];
+  float4* hpos = reinterpret_cast<float4*>(smem);
+  __shared__ int32_t hp[kHaloCells + 1];
+  __shared__ double red[kBlock / 64];
+  __shared__ int32_t wmax[kBlock / 64];
+  const int64_t b = logical_brick(g);
+  const bool live = b < g.nbricks;
+  int32_t hb = 0, H = 0, ob = 0, O = 0, hx = 0, hxy = 0;
+  if (live) {
+    const BrickShape s = brick_shape(b, g);
+    hx = s.h[0];
+    hxy = s.h[0] * s.h[1];
+    hb = bi.hb[b];
+    H = bi.hb[b + 1] - hb;
+    ob = bi.ob[b];
+    O = bi.ob[b + 1] - ob;
+    const int nh = s.h[0] * s.h[1] * s.h[2];
+    for (int h = threadIdx.x; h <= nh; h += blockDim.x) hp[h] = bi.hp[b * (kHaloCells + 1) + h];
+    const int32_t ns = H < g.cap ? H : g.cap;
+    for (int32_t sl = threadIdx.x; sl < ns; sl += blockDim.x) {
+      const vec4_t<T> p = pos_s[bi.halo_rank[hb + sl]];
+      hpos[sl] = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
+    }
+  }
+  __syncthreads();
+  int32_t mymax = 0;
+  double mysum = 0.0;
+  for (int32_t k = threadIdx.x; k < O; k += blockDim.x) {
+    const int32_t si = bi.owned_slot[ob + k];
+    const int32_t hc = bi.owned_hcell[ob + k];
+    float4 pi;
+    if (si < g.cap) {
+      pi = hpos[si];
+    } else {
+      const vec4_t<T> p = pos_s[bi.halo_rank[hb + si]];
+      pi = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
+    }
+    const double xi = (double)pi.x, yi = (double)pi.y, zi = (double)pi.z;
+    uint16_t* row = nbr + (int64_t)ob * kmax + k;
+    int32_t count = 0;
+    for (int dz = -1; dz <= 1; dz++)
+      for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++) {
+          const int h = hc + dz * hxy + dy * hx + dx;
+          const int32_t se = hp[h + 1];
+          for (int32_t sl = hp[h]; sl < se; sl++) {
+            if (sl == si) continue;
+            float4 pj;
+            if (sl < g.cap) {
+              pj = hpos[sl];
+            } else {
+              const vec4_t<T> p = pos_s[bi.halo_rank[hb + sl]];
+              pj = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
+            }
+            double d0 = (double)pj.x - xi;
+            double d1 = (double)pj.y - yi;
+            double d2 = (double)pj.z - zi;
+            d0 = d0 - cg.L[0] * rint(d0 * cg.invL[0]);
+            d1 = d1 - cg.L[1] * rint(d1 * cg.invL[1]);
+            d2 = d2 - cg.L[2] * rint(d2 * cg.invL[2]);
+            const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            if (r2 < rl2) {
+              if (count < kmax) row[(int64_t)count * O] = (uint16_t)sl;
+              count++;
+            }
+          }
+        }
+    cnt[ob + k] = count;
+    if (count > kmax) atomicOr(err, kErrOverflow);
+    mymax = count > mymax ? count : mymax;
+    mysum += (double)count;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int32_t v = __shfl_down(mymax, o, 64);
+    mymax = v > mymax ? v : mymax;
+  }
+  const double bsum = block_sum(mysum, red);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mymax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t bm = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); i++) bm = wmax[i] > bm ? wmax[i] : bm;
+    atomicMax(&stats[0], bm);
+    atomicAdd(reinterpret_cast<unsigned long long*>(stats + 2), (unsigned long long)bsum);
+  }
+}
+
+// Neighbour rows as sorted positions (for inspection and tests).
+__global__ __launch_bounds__(kBlock) void k_neighbor_ranks(const uint16_t* __restrict__ nbr,
+                                                           const int32_t* __restrict__ cnt, BrickGeom g, BrickIndex bi,
+                                                           int32_t kmax, int32_t* __restrict__ nbr_out,
+                                                           int32_t* __restrict__ cnt_out) {
+  const int64_t b = blockIdx.x;
+  const int32_t hb = bi.hb[b], ob = bi.ob[b], O = bi.ob[b + 1] - ob;
+  for (int32_t k = threadIdx.x; k < O; k += blockDim.x) {
+    const int32_t r = bi.owned_rank[ob + k];
+    const int32_t c = cnt[ob + k];
+    const int32_t m = c < kmax ? c : kmax;
+    for (int32_t e = 0; e < m; e++) nbr_out[(int64_t)r * kmax + e] = bi.halo_rank[hb + nbr[(int64_t)ob * kmax + (int64_t)e * O + k]];
+    cnt_out[r] = c;
+  }
+}
+
+// Sum of n int32 values into a 64-bit counter (block sums, one atomic each).
+__global__ __launch_bounds__(kBlock) void k_sum_i32(const int32_t* __restrict__ v, int64_t n,
+                                                    unsigned long long* out) {
+  __shared__ double red[kBlock / 64];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)v[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) atomicAdd(out, (unsigned long long)s);
+}
+
+// --------------------------------------------------------------------------
+// Launchers
+// --------------------------------------------------------------------------
+hipError_t launch_sum_i32(const int32_t* v, int64_t n, unsigned long long* out, hipStream_t st) {
+  k_sum_i32<<<256, kBlock, 0, st>>>(v, n, out);
+  return hipGetLastError();
+}
+
+static inline unsigned grid_of(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = grid_of(n, kBlock);
+  if (g > 4096) g = 4096;
+  k_fill_i32<<<(unsigned)g, kBlock, 0, st>>>(p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_ids(const float4* pos, int64_t n, const CellGeom& g, int32_t* cell, int32_t* count,
+                           int32_t* err, hipStream_t st) {
+  k_cell_ids<<<grid_of(n, kBlock), kBlock, 0, st>>>(pos, n, g, cell, count, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* zero, hipStream_t st) {
+  k_scan<<<1, 1024, 0, st>>>(in, n, out, zero);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const int32_t* cell, int64_t n, const int32_t* start, int32_t* fill, int32_t* perm,
+                          hipStream_t st) {
+  k_scatter<<<grid_of(n, kBlock), kBlock, 0, st>>>(cell, n, start, fill, perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_cells(const int32_t* start, int64_t ncells, int32_t* perm, hipStream_t st) {
+  k_sort_cells<<<grid_of(ncells, kBlock), kBlock, 0, st>>>(start, ncells, perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_brick_count(const int32_t* start, const BrickGeom& g, int32_t* H, int32_t* O, hipStream_t st) {
+  k_brick_count<<<grid_of(g.nbricks, kBlock), kBlock, 0, st>>>(start, g, H, O);
+  return hipGetLastError();
+}
+
+hipError_t launch_brick_fill(const int32_t* start, const BrickGeom& g, const BrickIndex& bi, int32_t* hp,
+                             int32_t* halo_rank, int32_t* owned_slot, int32_t* owned_rank, int32_t* owned_hcell,
+                             int32_t* err, hipStream_t st) {
+  k_brick_fill<<<(unsigned)g.nbricks, kBlock, 0, st>>>(start, g, bi, hp, halo_rank, owned_slot, owned_rank,
+                                                       owned_hcell, err);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather(const float4* pos, const int32_t* perm, int64_t n, vec4_t<T>* pos_s, int32_t* err,
+                         hipStream_t st) {
+  k_gather<T><<<grid_of(n, kBlock), kBlock, 0, st>>>(pos, perm, n, pos_s, err);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_build_nbr(const vec4_t<T>* pos_s, const CellGeom& cg, const BrickGeom& g, const BrickIndex& bi,
+                            double rl2, uint16_t* nbr, int32_t kmax, int32_t* cnt, int32_t* err, int32_t* stats,
+                            hipStream_t st) {
+  const size_t lds = (size_t)g.cap * sizeof(float4);
+  k_build_nbr<T><<<(unsigned)g.blocks, kBlock, lds, st>>>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_neighbor_ranks(const uint16_t* nbr, const int32_t* cnt, const BrickGeom& g, const BrickIndex& bi,
+                                 int32_t kmax, int32_t* nbr_out, int32_t* cnt_out, hipStream_t st) {
+  k_neighbor_ranks<<<(unsigned)g.nbricks, kBlock, 0, st>>>(nbr, cnt, g, bi, kmax, nbr_out, cnt_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather_batch(const GatherArgs* tab, const int32_t* blk_start, int32_t W, int32_t blocks,
+                               hipStream_t st) {
+  k_gather_batch<T><<<(unsigned)blocks, kBlock, 0, st>>>(tab, blk_start, W);
+  return hipGetLastError();
+}
+template hipError_t launch_gather_batch<float>(const GatherArgs*, const int32_t*, int32_t, int32_t, hipStream_t);
+template hipError_t launch_gather_batch<double>(const GatherArgs*, const int32_t*, int32_t, int32_t, hipStream_t);
+template hipError_t launch_gather<float>(const float4*, const int32_t*, int64_t, float4*, int32_t*, hipStream_t);
+template hipError_t launch_gather<double>(const float4*, const int32_t*, int64_t, double4*, int32_t*, hipStream_t);
+template hipError_t launch_build_nbr<float>(const float4*, const CellGeom&, const BrickGeom&, const BrickIndex&,
+                                            double, uint16_t*, int32_t, int32_t*, int32_t*, int32_t*, hipStream_t);
+template hipError_t launch_build_nbr<double>(const double4*, const CellGeom&, const BrickGeom&, const BrickIndex&,
+                                             double, uint16_t*, int32_t, int32_t*, int32_t*, int32_t*, hipStream_t);
+
+}  // namespace gm

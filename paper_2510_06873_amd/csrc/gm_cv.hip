@@ -1,0 +1,601 @@
+// Collective-variable kernels of libgpumetad, one workgroup per brick.
+//
+// Each pass stages the brick's halo (positions, plus the 16-wide per-atom row
+// the pass needs) in LDS with coalesced loads, then every thread walks the
+// neighbour slots of one owned atom reading LDS only.  Pass 1 also writes the
+// slots inside r_c for this step, so passes 2-4 skip the skin pairs.
+//
+//   pass 1  Q_i = sum_j f(r_ij) v(r_hat_ij), qhat_i = Q_i/|Q_i|; coordination sums
+//   pass 2  n_i = sum_j f b(qhat_i.qhat_j), c_i, c'_i; s = sum_i c_i (FP64)
+//   pass 3  g_i = ds/dQ_i and the taper radial term of ds/dx_i
+//   pass 4  ds/dx_i = -sum_j [ (du/dr)(r_ij)^T (g_i + g_j) + radial ],
+//           F_i -= sum_d dV/ds_d ds_d/dx_i  (or the gradient alone)
+#include "gm_device.h"
+
+namespace gm {
+
+struct Brick {
+  int64_t b;
+  int32_t hb, H, ob, O, ns;
+};
+
+template <typename T>
+__device__ __forceinline__ Brick brick_begin(const CvArgs<T>& a, int64_t brick) {
+  Brick k;
+  k.b = brick;
+  k.hb = k.H = k.ob = k.O = k.ns = 0;
+  if (k.b < a.bg.nbricks) {
+    k.hb = a.bi.hb[k.b];
+    k.H = a.bi.hb[k.b + 1] - k.hb;
+    k.ob = a.bi.ob[k.b];
+    k.O = a.bi.ob[k.b + 1] - k.ob;
+    k.ns = k.H < a.bg.cap ? k.H : a.bg.cap;
+  }
+  return k;
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_pos(const CvArgs<T>& a, const Brick& k, vec4_t<T>* lp) {
+  for (int32_t s = threadIdx.x; s < k.ns; s += blockDim.x) lp[s] = a.pos_s[a.bi.halo_rank[k.hb + s]];
+}
+
+// LDS record of a slot: position, then the 16-wide row (4 vectors).
+template <typename T>
+__device__ __forceinline__ void stage_rows(const CvArgs<T>& a, const Brick& k, const T* rows, vec4_t<T>* lr) {
+  for (int32_t s = threadIdx.x; s < k.ns; s += blockDim.x) {
+    const int32_t r = a.bi.halo_rank[k.hb + s];
+    const vec4_t<T>* src = reinterpret_cast<const vec4_t<T>*>(rows + (int64_t)r * 16);
+    vec4_t<T>* dst = lr + 5 * s;
+    dst[0] = a.pos_s[r];
+    dst[1] = src[0];
+    dst[2] = src[1];
+    dst[3] = src[2];
+    dst[4] = src[3];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ vec4_t<T> fetch_pos(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lp, int32_t s) {
+  if (s < a.bg.cap) return lp[s];
+  return a.pos_s[a.bi.halo_rank[k.hb + s]];
+}
+
+template <typename T>
+__device__ __forceinline__ void fetch_rec(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr, const T* rows,
+                                          int32_t s, vec4_t<T>& p, T v[16]) {
+  if (s < a.bg.cap) {
+    const vec4_t<T>* src = lr + 5 * s;
+    p = src[0];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const vec4_t<T> x = src[1 + q];
+      v[4 * q + 0] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
+    }
+  } else {
+    const int32_t r = a.bi.halo_rank[k.hb + s];
+    p = a.pos_s[r];
+    load_row16(rows + (int64_t)r * 16, v);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void write_out(const CvArgs<T>& a, int32_t rank, T gx, T gy, T gz) {
+  const int32_t id = a.perm[rank];
+  vec4_t<T>* out = reinterpret_cast<vec4_t<T>*>(a.out4) + id;
+  vec4_t<T> v = *out;
+  if (a.mode == 0) {
+    v.x -= gx;
+    v.y -= gy;
+    v.z -= gz;
+  } else {
+    v.x = gx;
+    v.y = gy;
+    v.z = gz;
+  }
+  *out = v;
+  if (!(isfinite(v.x) && isfinite(v.y) && isfinite(v.z))) atomicOr(a.err, kErrNonFinite);
+}
+
+// Sum of the per-workgroup partials by the last workgroup to finish; writes s.
+// TWO: part_b holds the coordination (scaled by 1/N), part_a the q6 count.
+// SCALE: one CV held in part_a that is scaled by 1/N (the coordination alone).
+template <typename T, bool TWO, bool SCALE>
+__device__ __forceinline__ void finish_sum(const CvArgs<T>& a, double* red, int32_t nblk) {
+  if (last_block_done(a.ticket, nblk)) {
+    double sa = 0.0, sb = 0.0;
+    for (int64_t i = threadIdx.x; i < (int64_t)nblk; i += blockDim.x) {
+      sa += load_agent(&a.part_a[i]);
+      if (TWO) sb += load_agent(&a.part_b[i]);
+    }
+    sa = block_sum(sa, red);
+    if (TWO) sb = block_sum(sb, red);
+    if (threadIdx.x == 0) {
+      const double s0 = TWO ? sb * a.inv_n : (SCALE ? sa * a.inv_n : sa);
+      const double s1 = TWO ? sa : 0.0;
+      a.s_int[0] = s0;
+      if (a.s_out) a.s_out[0] = s0;
+      if (TWO) {
+        a.s_int[1] = s1;
+        if (a.s_out) a.s_out[1] = s1;
+      }
+      if (!isfinite(s0) || !isfinite(s1)) atomicOr(a.err, kErrNonFinite);
+    }
+    release_ticket(a.ticket);
+  }
+}
+
+// --------------------------------------------------------------------------
+// Pass 1
+// --------------------------------------------------------------------------
+template <typename T, bool CN, bool Q6>
+__device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  vec4_t<T>* lp = reinterpret_cast<vec4_t<T>*>(smem);
+  __shared__ double red[kBlock / 64];
+  const Brick k = brick_begin(a, brick);
+  stage_pos(a, k, lp);
+  __syncthreads();
+  double cn_part = 0.0;
+  for (int32_t o = threadIdx.x; o < k.O; o += blockDim.x) {
+    const int32_t si = a.bi.owned_slot[k.ob + o];
+    const int32_t ri = a.bi.owned_rank[k.ob + o];
+    const vec4_t<T> pi = fetch_pos(a, k, lp, si);
+    const int32_t c = min(a.cnt[k.ob + o], a.kmax);
+    const uint16_t* row = a.nbr + (int64_t)k.ob * a.kmax + o;
+    uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
+    T Q[13];
+#pragma unroll
+    for (int m = 0; m < 13; m++) Q[m] = T(0);
+    T fsum = T(0), cnsum = T(0);
+    int32_t nc = 0;
+    for (int32_t e = 0; e < c; e++) {
+      const int32_t s = row[(int64_t)e * k.O];
+      const vec4_t<T> pj = fetch_pos(a, k, lp, s);
+      T dx, dy, dz;
+      const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
+      if (r2 < a.rc2) {
+        crow[(int64_t)nc * k.O] = (uint16_t)s;
+        nc++;
+        const T rinv = g_rsqrt(r2);
+        const T r = r2 * rinv;
+        if (Q6) {
+          T df;
+          const T f = taper_w(r, a, df);
+          accumulate_y(a.yc, dx * rinv, dy * rinv, dz * rinv, f, Q);
+          fsum += f;
+        }
+        if (CN) {
+          const T x = r * a.cn_r0inv;
+          const T x2 = x * x;
+          cnsum += g_rcp(T(1) + x2 * x2 * x2);
+        }
+      }
+    }
+    a.ccnt[k.ob + o] = nc;
+    if (Q6) {
+      T qq = T(0);
+#pragma unroll
+      for (int m = 0; m < 13; m++) qq += Q[m] * Q[m];
+      const T qn = g_sqrt(qq);
+      const T inv = qn >= T(1e-12) ? T(1) / qn : T(0);
+      T rowv[16];
+#pragma unroll
+      for (int m = 0; m < 13; m++) rowv[m] = Q[m] * inv;
+      rowv[13] = qn;
+      rowv[14] = T(0);
+      rowv[15] = fsum;
+      store_row16(a.qrow + (int64_t)ri * 16, rowv);
+    }
+    if (CN) {
+      a.cn_atom[ri] = cnsum;
+      cn_part += (double)cnsum;
+    }
+  }
+  if (CN) {
+    const double b = block_sum(cn_part, red);
+    if (threadIdx.x == 0) store_agent(Q6 ? &a.part_b[blk] : &a.part_a[blk], b);
+    if (!Q6) finish_sum<T, false, true>(a, red, nblk);
+  }
+}
+
+// --------------------------------------------------------------------------
+// Pass 2
+// --------------------------------------------------------------------------
+template <typename T, bool CN>
+__device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
+  __shared__ double red[kBlock / 64];
+  const Brick k = brick_begin(a, brick);
+  stage_rows(a, k, a.qrow, lr);
+  __syncthreads();
+  double c_part = 0.0;
+  for (int32_t o = threadIdx.x; o < k.O; o += blockDim.x) {
+    const int32_t si = a.bi.owned_slot[k.ob + o];
+    const int32_t ri = a.bi.owned_rank[k.ob + o];
+    vec4_t<T> pi;
+    T qi[16];
+    fetch_rec(a, k, lr, a.qrow, si, pi, qi);
+    const int32_t nc = a.ccnt[k.ob + o];
+    const uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
+    T nbond = T(0);
+    for (int32_t e = 0; e < nc; e++) {
+      const int32_t s = crow[(int64_t)e * k.O];
+      vec4_t<T> pj;
+      T qj[16];
+      fetch_rec(a, k, lr, a.qrow, s, pj, qj);
+      T dx, dy, dz;
+      const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
+      const T r = g_sqrt(r2);
+      T df;
+      const T f = taper_w(r, a, df);
+      T d = T(0);
+#pragma unroll
+      for (int m = 0; m < 13; m++) d += qi[m] * qj[m];
+      nbond += f * logistic((d - a.bond_d0) * a.inv_bond_w);
+    }
+    const T cc = logistic((nbond - a.count_n0) * a.inv_count_w);
+    const T dc = cc * (T(1) - cc) * a.inv_count_w;
+    a.qrow[(int64_t)ri * 16 + 14] = dc;
+    a.nb[ri] = nbond;
+    c_part += (double)cc;
+  }
+  const double b = block_sum(c_part, red);
+  if (threadIdx.x == 0) store_agent(&a.part_a[blk], b);
+  finish_sum<T, CN, false>(a, red, nblk);
+}
+
+// --------------------------------------------------------------------------
+// Pass 3
+// --------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void pass3_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
+  const Brick k = brick_begin(a, brick);
+  stage_rows(a, k, a.qrow, lr);
+  __syncthreads();
+  for (int32_t o = threadIdx.x; o < k.O; o += blockDim.x) {
+    const int32_t si = a.bi.owned_slot[k.ob + o];
+    const int32_t ri = a.bi.owned_rank[k.ob + o];
+    vec4_t<T> pi;
+    T qi[16];
+    fetch_rec(a, k, lr, a.qrow, si, pi, qi);
+    const T dci = qi[14];
+    const int32_t nc = a.ccnt[k.ob + o];
+    const uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
+    T h[13];
+#pragma unroll
+    for (int m = 0; m < 13; m++) h[m] = T(0);
+    T rx = T(0), ry = T(0), rz = T(0);
+    for (int32_t e = 0; e < nc; e++) {
+      const int32_t s = crow[(int64_t)e * k.O];
+      vec4_t<T> pj;
+      T qj[16];
+      fetch_rec(a, k, lr, a.qrow, s, pj, qj);
+      T dx, dy, dz;
+      const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
+      const T rinv = g_rsqrt(r2);
+      const T r = r2 * rinv;
+      T df;
+      const T f = taper_w(r, a, df);
+      T d = T(0);
+#pragma unroll
+      for (int m = 0; m < 13; m++) d += qi[m] * qj[m];
+      const T b = logistic((d - a.bond_d0) * a.inv_bond_w);
+      const T cs = dci + qj[14];
+      const T coef = f * b * (T(1) - b) * a.inv_bond_w * cs;
+#pragma unroll
+      for (int m = 0; m < 13; m++) h[m] += coef * qj[m];
+      if (df != T(0)) {
+        const T rad = cs * b * df * rinv;
+        rx += rad * dx;
+        ry += rad * dy;
+        rz += rad * dz;
+      }
+    }
+    T proj = T(0);
+#pragma unroll
+    for (int m = 0; m < 13; m++) proj += qi[m] * h[m];
+    const T inv = qi[13] >= T(1e-12) ? T(1) / qi[13] : T(0);
+    T g[16];
+#pragma unroll
+    for (int m = 0; m < 13; m++) g[m] = (h[m] - proj * qi[m]) * inv;
+    g[13] = dci;
+    g[14] = T(0);
+    g[15] = T(0);
+    store_row16(a.grow + (int64_t)ri * 16, g);
+    vec4_t<T> fr;
+    fr.x = rx;
+    fr.y = ry;
+    fr.z = rz;
+    fr.w = T(0);
+    a.frad[ri] = fr;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Pass 4: chain rule onto positions (u(r) = f(r) v(r_hat) is even in r, so
+// both ends of a pair reuse one Jacobian with g_i + g_j).
+// --------------------------------------------------------------------------
+template <typename T, bool CN>
+__device__ __forceinline__ void pass4_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
+  const Brick k = brick_begin(a, brick);
+  stage_rows(a, k, a.grow, lr);
+  __syncthreads();
+  const T seed_q = a.seed ? (T)a.seed[a.dims - 1] : T(1);
+  const T seed_cn = (CN && a.seed) ? (T)(a.seed[0] * 2.0 * a.inv_n) : T(0);
+  for (int32_t o = threadIdx.x; o < k.O; o += blockDim.x) {
+    const int32_t si = a.bi.owned_slot[k.ob + o];
+    const int32_t ri = a.bi.owned_rank[k.ob + o];
+    vec4_t<T> pi;
+    T gi[16];
+    fetch_rec(a, k, lr, a.grow, si, pi, gi);
+    const int32_t nc = a.ccnt[k.ob + o];
+    const uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
+    T ax = T(0), ay = T(0), az = T(0);
+    T cx = T(0), cy = T(0), cz = T(0);
+    for (int32_t e = 0; e < nc; e++) {
+      const int32_t s = crow[(int64_t)e * k.O];
+      vec4_t<T> pj;
+      T gj[16];
+      fetch_rec(a, k, lr, a.grow, s, pj, gj);
+      T dx, dy, dz;
+      const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
+      const T rinv = g_rsqrt(r2);
+      const T r = r2 * rinv;
+      const T ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+      T df;
+      const T f = taper_w(r, a, df);
+      T w[13];
+#pragma unroll
+      for (int m = 0; m < 13; m++) w[m] = gi[m] + gj[m];
+      T S, Sx, Sy, Sz;
+      grad_s(a.yc, ux, uy, uz, w, S, Sx, Sy, Sz);
+      const T ud = ux * Sx + uy * Sy + uz * Sz;
+      const T fr = f * rinv;
+      T px = fr * (Sx - ud * ux);
+      T py = fr * (Sy - ud * uy);
+      T pz = fr * (Sz - ud * uz);
+      if (df != T(0)) {
+        px += df * S * ux;
+        py += df * S * uy;
+        pz += df * S * uz;
+      }
+      ax += px;
+      ay += py;
+      az += pz;
+      if (CN) {
+        const T x = r * a.cn_r0inv;
+        const T x2 = x * x;
+        const T x5 = x2 * x2 * x;
+        const T den = T(1) + x5 * x;
+        const T swp = T(-6) * x5 * a.cn_r0inv * g_rcp(den * den);
+        cx += swp * ux;
+        cy += swp * uy;
+        cz += swp * uz;
+      }
+    }
+    const vec4_t<T> fr = a.frad[ri];
+    ax += fr.x;
+    ay += fr.y;
+    az += fr.z;
+    write_out(a, ri, -(seed_q * ax + seed_cn * cx), -(seed_q * ay + seed_cn * cy), -(seed_q * az + seed_cn * cz));
+  }
+}
+
+// --------------------------------------------------------------------------
+// Coordination number alone: forces over the in-cutoff slots of pass 1.
+// --------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void cn_force_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  vec4_t<T>* lp = reinterpret_cast<vec4_t<T>*>(smem);
+  const Brick k = brick_begin(a, brick);
+  stage_pos(a, k, lp);
+  __syncthreads();
+  const T seed = (T)((a.seed ? a.seed[0] : 1.0) * 2.0 * a.inv_n);
+  for (int32_t o = threadIdx.x; o < k.O; o += blockDim.x) {
+    const int32_t si = a.bi.owned_slot[k.ob + o];
+    const int32_t ri = a.bi.owned_rank[k.ob + o];
+    const vec4_t<T> pi = fetch_pos(a, k, lp, si);
+    const int32_t nc = a.ccnt[k.ob + o];
+    const uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
+    T cx = T(0), cy = T(0), cz = T(0);
+    for (int32_t e = 0; e < nc; e++) {
+      const vec4_t<T> pj = fetch_pos(a, k, lp, crow[(int64_t)e * k.O]);
+      T dx, dy, dz;
+      const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
+      const T rinv = g_rsqrt(r2);
+      const T x = r2 * rinv * a.cn_r0inv;
+      const T x2 = x * x;
+      const T x5 = x2 * x2 * x;
+      const T den = T(1) + x5 * x;
+      const T swp = T(-6) * x5 * a.cn_r0inv * g_rcp(den * den) * rinv;
+      cx += swp * dx;
+      cy += swp * dy;
+      cz += swp * dz;
+    }
+    write_out(a, ri, -seed * cx, -seed * cy, -seed * cz);
+  }
+}
+
+
+// --------------------------------------------------------------------------
+// Kernels: one context (its bricks remapped per XCD), or a batch of contexts
+// ("walkers") in one launch.  In a batch, workgroup g (after the same XCD
+// remap over the whole grid) belongs to the walker w with
+// blk_start[w] <= g < blk_start[w+1] and handles that walker's brick
+// g - blk_start[w]; every walker keeps its own tickets and partial sums, so
+// its results are bitwise the same alone and in a batch.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int32_t find_walker(const int32_t* __restrict__ blk_start, int32_t W, int64_t g) {
+  int32_t lo = 0, hi = W;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (blk_start[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int64_t xcd_remap() {
+  const int64_t b = blockIdx.x;
+  const int64_t per = gridDim.x / kXcd;
+  return (b % kXcd) * per + b / kXcd;
+}
+
+#define GM_PASS_KERNELS(NAME, BODY, TMPL, TARGS)                                                      \
+  TMPL __global__ __launch_bounds__(kBlock) void NAME(CvArgs<T> a) {                                  \
+    const int64_t g = logical_brick(a.bg);                                                            \
+    BODY TARGS(a, g, (int32_t)g, (int32_t)gridDim.x);                                                 \
+  }                                                                                                   \
+  TMPL __global__ __launch_bounds__(kBlock) void NAME##_batch(const CvArgs<T>* __restrict__ tab,      \
+                                                              const int32_t* __restrict__ blk_start,  \
+                                                              int32_t W) {                            \
+    const int64_t g = xcd_remap();                                                                    \
+    const int32_t w = find_walker(blk_start, W, g);                                                   \
+    const int32_t local = (int32_t)(g - blk_start[w]);                                                \
+    BODY TARGS(tab[w], local, local, blk_start[w + 1] - blk_start[w]);                                \
+  }
+
+#define GM_COMMA ,
+GM_PASS_KERNELS(k_pass1, pass1_body, template <typename T GM_COMMA bool CN GM_COMMA bool Q6>, <T GM_COMMA CN GM_COMMA Q6>)
+GM_PASS_KERNELS(k_pass2, pass2_body, template <typename T GM_COMMA bool CN>, <T GM_COMMA CN>)
+GM_PASS_KERNELS(k_pass3, pass3_body, template <typename T>, <T>)
+GM_PASS_KERNELS(k_pass4, pass4_body, template <typename T GM_COMMA bool CN>, <T GM_COMMA CN>)
+GM_PASS_KERNELS(k_cn_force, cn_force_body, template <typename T>, <T>)
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_atom_values(CvArgs<T> a, int what, int cv_kind, double* dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.n) return;
+  double v = 0.0;
+  if (what == GM_ATOM_CN) {
+    v = (double)a.cn_atom[t];
+  } else if (cv_kind != GM_CV_COORD) {
+    if (what == GM_ATOM_Q6) {
+      const double fs = (double)a.qrow[t * 16 + 15];
+      v = fs > 0.0 ? sqrt(4.0 * M_PI / 13.0) * (double)a.qrow[t * 16 + 13] / fs : 0.0;
+    } else if (what == GM_ATOM_NB) {
+      v = (double)a.nb[t];
+    } else if (what == GM_ATOM_C) {
+      v = (double)logistic((a.nb[t] - a.count_n0) * a.inv_count_w);
+    }
+  }
+  dst[a.perm[t]] = v;
+}
+
+// --------------------------------------------------------------------------
+// Launchers
+// --------------------------------------------------------------------------
+template <typename T>
+static size_t lds_bytes(const CvArgs<T>& a, bool rows) {
+  return (size_t)a.bg.cap * (size_t)slot_bytes<T>(rows);
+}
+
+template <typename T>
+hipError_t launch_q6_forward(const CvArgs<T>& a, bool with_cn, hipStream_t st) {
+  const unsigned g = (unsigned)a.bg.blocks;
+  if (with_cn) {
+    k_pass1<T, true, true><<<g, kBlock, lds_bytes(a, false), st>>>(a);
+    k_pass2<T, true><<<g, kBlock, lds_bytes(a, true), st>>>(a);
+  } else {
+    k_pass1<T, false, true><<<g, kBlock, lds_bytes(a, false), st>>>(a);
+    k_pass2<T, false><<<g, kBlock, lds_bytes(a, true), st>>>(a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_q6_adjoint(const CvArgs<T>& a, hipStream_t st) {
+  k_pass3<T><<<(unsigned)a.bg.blocks, kBlock, lds_bytes(a, true), st>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_q6_force(const CvArgs<T>& a, bool with_cn, hipStream_t st) {
+  const unsigned g = (unsigned)a.bg.blocks;
+  if (with_cn)
+    k_pass4<T, true><<<g, kBlock, lds_bytes(a, true), st>>>(a);
+  else
+    k_pass4<T, false><<<g, kBlock, lds_bytes(a, true), st>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cn_forward(const CvArgs<T>& a, hipStream_t st) {
+  k_pass1<T, true, false><<<(unsigned)a.bg.blocks, kBlock, lds_bytes(a, false), st>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cn_force(const CvArgs<T>& a, hipStream_t st) {
+  k_cn_force<T><<<(unsigned)a.bg.blocks, kBlock, lds_bytes(a, false), st>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_atom_values(const CvArgs<T>& a, int what, int cv_kind, double* dst, hipStream_t st) {
+  k_atom_values<T><<<(unsigned)((a.n + kBlock - 1) / kBlock), kBlock, 0, st>>>(a, what, cv_kind, dst);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pass_batch(int pass, bool with_cn, bool fp_rows, const CvArgs<T>* tab, const int32_t* blk_start,
+                             int32_t W, int32_t blocks, int32_t cap, hipStream_t st) {
+  const size_t lds_pos = (size_t)cap * slot_bytes<T>(false), lds_rows = (size_t)cap * slot_bytes<T>(true);
+  (void)fp_rows;
+  const unsigned g = (unsigned)blocks;
+  switch (pass) {
+    case 1:
+      if (with_cn)
+        k_pass1_batch<T, true, true><<<g, kBlock, lds_pos, st>>>(tab, blk_start, W);
+      else
+        k_pass1_batch<T, false, true><<<g, kBlock, lds_pos, st>>>(tab, blk_start, W);
+      break;
+    case 2:
+      if (with_cn)
+        k_pass2_batch<T, true><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
+      else
+        k_pass2_batch<T, false><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
+      break;
+    case 3:
+      k_pass3_batch<T><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
+      break;
+    case 4:
+      if (with_cn)
+        k_pass4_batch<T, true><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
+      else
+        k_pass4_batch<T, false><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
+      break;
+    case 5:  // coordination alone: forward
+      k_pass1_batch<T, true, false><<<g, kBlock, lds_pos, st>>>(tab, blk_start, W);
+      break;
+    case 6:  // coordination alone: forces
+      k_cn_force_batch<T><<<g, kBlock, lds_pos, st>>>(tab, blk_start, W);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+#define GM_INSTANTIATE(T)                                                                              \
+  template hipError_t launch_q6_forward<T>(const CvArgs<T>&, bool, hipStream_t);                        \
+  template hipError_t launch_q6_adjoint<T>(const CvArgs<T>&, hipStream_t);                              \
+  template hipError_t launch_q6_force<T>(const CvArgs<T>&, bool, hipStream_t);                          \
+  template hipError_t launch_cn_forward<T>(const CvArgs<T>&, hipStream_t);                              \
+  template hipError_t launch_cn_force<T>(const CvArgs<T>&, hipStream_t);                                \
+  template hipError_t launch_atom_values<T>(const CvArgs<T>&, int, int, double*, hipStream_t);             \
+  template hipError_t launch_pass_batch<T>(int, bool, bool, const CvArgs<T>*, const int32_t*, int32_t, int32_t, \
+                                           int32_t, hipStream_t);
+
+GM_INSTANTIATE(float)
+GM_INSTANTIATE(double)
+
+}  // namespace gm

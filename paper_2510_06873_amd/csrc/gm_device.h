@@ -1,0 +1,250 @@
+// Device helpers shared by the kernel files of libgpumetad (gfx950).
+#pragma once
+
+#include <math.h>
+
+#include "gm_internal.h"
+
+namespace gm {
+
+// --------------------------------------------------------------------------
+// Small device helpers
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float g_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double g_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float g_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double g_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float g_exp(float x) { return __expf(x); }
+__device__ __forceinline__ double g_exp(double x) { return exp(x); }
+__device__ __forceinline__ float g_rint(float x) { return rintf(x); }
+__device__ __forceinline__ double g_rint(double x) { return rint(x); }
+__device__ __forceinline__ void g_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void g_sincos(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ float g_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double g_sqrt(double x) { return sqrt(x); }
+
+template <typename T>
+__device__ __forceinline__ T logistic(T x) {
+  return g_rcp(T(1) + g_exp(-x));
+}
+
+// Logical block index: XCD x (= blockIdx % 8) gets the contiguous block range
+// [x*G/8, (x+1)*G/8) so that neighbouring atoms share an L2.
+__device__ __forceinline__ int64_t logical_block() {
+  int64_t b = blockIdx.x;
+  int64_t per = gridDim.x / kXcd;
+  return (b % kXcd) * per + b / kXcd;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Fixed-order block sum; the result is valid in thread 0.  All threads call.
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); i++) r += lds[i];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void store_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// True in every thread of the workgroup that finishes last among the nblk
+// workgroups sharing this ticket (all threads call).
+__device__ __forceinline__ bool last_block_done(unsigned* ticket, int32_t nblk) {
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(ticket, 1u);
+    is_last = (prev == (unsigned)nblk - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last != 0;
+}
+
+__device__ __forceinline__ void release_ticket(unsigned* ticket) {
+  if (threadIdx.x == 0) atomicExch(ticket, 0u);
+}
+
+// Minimum image in T: d - L*rint(d/L), with L split in high and low parts so
+// that an FP32 box length does not bias wrapped pairs.
+template <typename T>
+__device__ __forceinline__ T mic(T d, T L, T invL, T Llo) {
+  T k = g_rint(d * invL);
+  return (d - k * L) - k * Llo;
+}
+
+template <typename T>
+__device__ __forceinline__ T pair_vec(const vec4_t<T>& pi, const vec4_t<T>& pj, const CvArgs<T>& a,
+                                      T& dx, T& dy, T& dz) {
+  dx = mic(pj.x - pi.x, a.L[0], a.invL[0], a.Llo[0]);
+  dy = mic(pj.y - pi.y, a.L[1], a.invL[1], a.Llo[1]);
+  dz = mic(pj.z - pi.z, a.L[2], a.invL[2], a.Llo[2]);
+  return dx * dx + dy * dy + dz * dz;
+}
+
+// Cosine-tapered q6 weight f(r) and f'(r).
+template <typename T>
+__device__ __forceinline__ T taper_w(T r, const CvArgs<T>& a, T& df) {
+  if (r <= a.taper_lo) {
+    df = T(0);
+    return T(1);
+  }
+  T s, c;
+  g_sincos((r - a.taper_lo) * a.pi_over_D, &s, &c);
+  df = -a.half_pi_over_D * s;
+  return T(0.5) + T(0.5) * c;
+}
+
+template <typename T>
+__device__ __forceinline__ void eval_E(const YCoef<T>& c, T z, T E[7]) {
+  const T z2 = z * z;
+  E[0] = c.e0[0] + z2 * (c.e0[1] + z2 * (c.e0[2] + z2 * c.e0[3]));
+  E[1] = z * (c.e1[0] + z2 * (c.e1[1] + z2 * c.e1[2]));
+  E[2] = c.e2[0] + z2 * (c.e2[1] + z2 * c.e2[2]);
+  E[3] = z * (c.e3[0] + z2 * c.e3[1]);
+  E[4] = c.e4[0] + z2 * c.e4[1];
+  E[5] = z * c.e5;
+  E[6] = c.e6;
+}
+
+// Q += f * v(u), v the real 13-vector of l = 6 harmonics:
+// v_0 = E_0, v_{2m-1} = E_m Re (ux + i uy)^m, v_{2m} = E_m Im (ux + i uy)^m.
+template <typename T>
+__device__ __forceinline__ void accumulate_y(const YCoef<T>& c, T ux, T uy, T uz, T f, T Q[13]) {
+  T E[7];
+  eval_E(c, uz, E);
+  Q[0] += f * E[0];
+  T R = ux, I = uy;
+#pragma unroll
+  for (int m = 1; m <= 6; m++) {
+    const T fE = f * E[m];
+    Q[2 * m - 1] += fE * R;
+    Q[2 * m] += fE * I;
+    if (m < 6) {
+      const T R2 = R * ux - I * uy;
+      const T I2 = R * uy + I * ux;
+      R = R2;
+      I = I2;
+    }
+  }
+}
+
+// S = w . v(u) and its gradient with respect to (ux, uy, uz) taken as free
+// variables (v is a polynomial in them).  d(zeta^m)/dux = m zeta^(m-1),
+// d(zeta^m)/duy = i m zeta^(m-1), dE_m/duz = rat_m E_{m+1}.
+template <typename T>
+__device__ __forceinline__ void grad_s(const YCoef<T>& c, T ux, T uy, T uz, const T w[13], T& S,
+                                       T& Sx, T& Sy, T& Sz) {
+  T E[7];
+  eval_E(c, uz, E);
+  S = w[0] * E[0];
+  Sz = w[0] * c.rat[0] * E[1];
+  Sx = T(0);
+  Sy = T(0);
+  T Rp = T(1), Ip = T(0), R = ux, I = uy;
+#pragma unroll
+  for (int m = 1; m <= 6; m++) {
+    const T wa = w[2 * m - 1], wb = w[2 * m];
+    const T Tm = wa * R + wb * I;
+    const T U = wa * Rp + wb * Ip;
+    const T V = wb * Rp - wa * Ip;
+    const T mE = T(m) * E[m];
+    S += E[m] * Tm;
+    Sx += mE * U;
+    Sy += mE * V;
+    if (m < 6) {
+      Sz += c.rat[m] * E[m + 1] * Tm;
+      const T R2 = R * ux - I * uy;
+      const T I2 = R * uy + I * ux;
+      Rp = R;
+      Ip = I;
+      R = R2;
+      I = I2;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_row16(const T* row, T v[16]) {
+  const vec4_t<T>* p = reinterpret_cast<const vec4_t<T>*>(row);
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    vec4_t<T> x = p[q];
+    v[4 * q + 0] = x.x;
+    v[4 * q + 1] = x.y;
+    v[4 * q + 2] = x.z;
+    v[4 * q + 3] = x.w;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_row16(T* row, const T v[16]) {
+  vec4_t<T>* p = reinterpret_cast<vec4_t<T>*>(row);
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    vec4_t<T> x;
+    x.x = v[4 * q + 0];
+    x.y = v[4 * q + 1];
+    x.z = v[4 * q + 2];
+    x.w = v[4 * q + 3];
+    p[q] = x;
+  }
+}
+
+
+// Brick coordinates and cell-id helpers.
+__device__ __forceinline__ int32_t wrap_cell(int32_t c, int32_t n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+struct BrickShape {
+  int32_t o[3];   // first cell of the brick on each axis
+  int32_t e[3];   // brick extent in cells (edge bricks may be smaller)
+  int32_t h[3];   // halo extent (e + 2)
+};
+
+__device__ __forceinline__ BrickShape brick_shape(int64_t b, const BrickGeom& g) {
+  BrickShape s;
+  int32_t ib[3];
+  ib[0] = (int32_t)(b % g.nb[0]);
+  ib[1] = (int32_t)((b / g.nb[0]) % g.nb[1]);
+  ib[2] = (int32_t)(b / ((int64_t)g.nb[0] * g.nb[1]));
+  for (int a = 0; a < 3; a++) {
+    s.o[a] = ib[a] * g.b[a];
+    s.e[a] = min(g.b[a], g.nc[a] - s.o[a]);
+    s.h[a] = s.e[a] + 2;
+  }
+  return s;
+}
+
+// Global cell id of halo cell (hx, hy, hz) of a brick (halo coordinates start at -1).
+__device__ __forceinline__ int32_t halo_cell_id(const BrickShape& s, const BrickGeom& g, int hx, int hy, int hz) {
+  const int32_t cx = wrap_cell(s.o[0] - 1 + hx, g.nc[0]);
+  const int32_t cy = wrap_cell(s.o[1] - 1 + hy, g.nc[1]);
+  const int32_t cz = wrap_cell(s.o[2] - 1 + hz, g.nc[2]);
+  return (cz * g.nc[1] + cy) * g.nc[0] + cx;
+}
+
+// Logical brick of this workgroup: XCD x (= blockIdx % 8) walks a contiguous
+// range of bricks, so the halos it stages overlap in its own L2.
+__device__ __forceinline__ int64_t logical_brick(const BrickGeom& g) {
+  const int64_t b = blockIdx.x;
+  const int64_t per = gridDim.x / kXcd;
+  return (b % kXcd) * per + b / kXcd;
+}
+
+}  // namespace gm

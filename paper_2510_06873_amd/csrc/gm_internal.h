@@ -47,13 +47,44 @@ struct CellGeom {
   int32_t nc[3];
 };
 
-// Arguments of the per-atom CV kernels.
+// Brick decomposition of the cell grid.  A brick is b[0] x b[1] x b[2] cells;
+// its halo adds one cell on every side (periodic).  One workgroup handles one
+// brick: it stages the halo atoms in LDS ("slots", in halo-cell order), and
+// neighbour entries are 16-bit slot numbers into that halo.
+constexpr int kMaxBrick = 4;                                  // cells per axis
+constexpr int kHaloCells = (kMaxBrick + 2) * (kMaxBrick + 2) * (kMaxBrick + 2);
+constexpr int kOwnCells = kMaxBrick * kMaxBrick * kMaxBrick;
+
+struct BrickGeom {
+  int32_t nc[3];   // cells per axis
+  int32_t b[3];    // brick size in cells
+  int32_t nb[3];   // bricks per axis
+  int32_t nbricks;
+  int32_t cap;     // halo slots staged in LDS (slots beyond are read from global memory)
+  int32_t blocks;  // workgroups launched per brick pass (nbricks rounded up to the XCD count)
+};
+
+struct BrickIndex {
+  const int32_t* hb;          // [nbricks+1] first halo slot of each brick (global numbering)
+  const int32_t* ob;          // [nbricks+1] first owned atom of each brick (brick order)
+  const int32_t* hp;          // [nbricks][kHaloCells+1] slot prefix over the halo cells
+  const int32_t* halo_rank;   // [sum H] sorted position of each halo slot
+  const int32_t* owned_slot;  // [N] halo slot of each owned atom (brick order)
+  const int32_t* owned_rank;  // [N] sorted position of each owned atom
+  const int32_t* owned_hcell; // [N] halo-cell index of the owned atom's own cell
+};
+
+// Arguments of the per-brick CV kernels.
 template <typename T>
 struct CvArgs {
   const vec4_t<T>* pos_s;  // positions in sorted (cell) order
-  const int32_t* nbr;      // [n][kmax] sorted positions of neighbours
-  const int32_t* cnt;      // [n] true row lengths
+  const uint16_t* nbr;     // neighbour slots, per brick [kmax][O] (column-major)
+  const int32_t* cnt;      // [N] row lengths, brick order
+  uint16_t* cut;           // in-cutoff slots of the current step, same layout as nbr
+  int32_t* ccnt;           // [N] in-cutoff counts, brick order
   const int32_t* perm;     // sorted position -> caller's atom id
+  BrickGeom bg;
+  BrickIndex bi;
   int64_t n;
   int32_t kmax;
   int32_t dims;
@@ -63,15 +94,16 @@ struct CvArgs {
   T cn_r0inv;
   double inv_n;
   YCoef<T> yc;
-  T* qrow;     // [n][16]: qhat(13), |Q|, c', sum f
-  T* grow;     // [n][16]: g(13), c'
-  T* nb;       // [n] bond counts
-  T* cn_atom;  // [n] per-atom coordination sums
-  double* part_a;  // per-block FP64 partial sums (count / coordination)
+  T* qrow;          // [N][16] by sorted position: qhat(13), |Q|, c', sum f
+  T* grow;          // [N][16]: g(13), c'
+  vec4_t<T>* frad;  // [N]: sum over taper pairs of (c'_i + c'_j) b_ij f'(r) r_hat
+  T* nb;            // [N] bond counts
+  T* cn_atom;       // [N] per-atom coordination sums
+  double* part_a;   // per-workgroup FP64 partial sums (count / coordination)
   double* part_b;
   unsigned* ticket;
-  double* s_out;   // caller's s (dev), may equal s_int
-  double* s_int;   // library copy of s
+  double* s_out;    // caller's s (dev), may be NULL
+  double* s_int;    // library copy of s
   int32_t* err;
   const double* seed;  // dV/ds or backward seed (dev double[dims]); NULL = 1
   int32_t mode;        // 0: F -= G (apply), 1: grad = G
@@ -96,23 +128,34 @@ struct BiasArgs {
   int32_t* err;
 };
 
-// ---- launchers (gm_kernels.hip) ------------------------------------------
+struct GatherArgs {
+  const float4* pos;
+  const int32_t* perm;
+  int64_t n;
+  void* pos_s;
+  int32_t* err;
+};
+
+// ---- launchers -------------------------------------------------------------
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 hipError_t launch_cell_ids(const float4* pos, int64_t n, const CellGeom& g, int32_t* cell,
                            int32_t* count, int32_t* err, hipStream_t st);
-hipError_t launch_scan_cells(const int32_t* count, int64_t ncells, int32_t* start, int32_t* fill,
-                             hipStream_t st);
+hipError_t launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* zero, hipStream_t st);
 hipError_t launch_scatter(const int32_t* cell, int64_t n, const int32_t* start, int32_t* fill,
                           int32_t* perm, hipStream_t st);
 hipError_t launch_sort_cells(const int32_t* start, int64_t ncells, int32_t* perm, hipStream_t st);
+hipError_t launch_brick_count(const int32_t* start, const BrickGeom& g, int32_t* H, int32_t* O,
+                              hipStream_t st);
+hipError_t launch_brick_fill(const int32_t* start, const BrickGeom& g, const BrickIndex& bi,
+                             int32_t* hp, int32_t* halo_rank, int32_t* owned_slot, int32_t* owned_rank,
+                             int32_t* owned_hcell, int32_t* err, hipStream_t st);
 template <typename T>
 hipError_t launch_gather(const float4* pos, const int32_t* perm, int64_t n, vec4_t<T>* pos_s,
                          int32_t* err, hipStream_t st);
 template <typename T>
-hipError_t launch_build_nbr(const vec4_t<T>* pos_s, int64_t n, const CellGeom& g, double rl2,
-                            const int32_t* start, int32_t* nbr, int32_t kmax, int32_t* cnt,
-                            int32_t* err, int32_t* maxcnt, unsigned long long* total,
-                            hipStream_t st);
+hipError_t launch_build_nbr(const vec4_t<T>* pos_s, const CellGeom& cg, const BrickGeom& g,
+                            const BrickIndex& bi, double rl2, uint16_t* nbr, int32_t kmax, int32_t* cnt,
+                            int32_t* err, int32_t* stats, hipStream_t st);
 template <typename T>
 hipError_t launch_q6_forward(const CvArgs<T>& a, bool with_cn, hipStream_t st);
 template <typename T>
@@ -126,7 +169,29 @@ hipError_t launch_cn_force(const CvArgs<T>& a, hipStream_t st);
 template <typename T>
 hipError_t launch_atom_values(const CvArgs<T>& a, int what, int cv_kind, double* dst,
                               hipStream_t st);
+hipError_t launch_neighbor_ranks(const uint16_t* nbr, const int32_t* cnt, const BrickGeom& g,
+                                 const BrickIndex& bi, int32_t kmax, int32_t* nbr_out, int32_t* cnt_out,
+                                 hipStream_t st);
 hipError_t launch_bias(const BiasArgs& a, int blocks, hipStream_t st);
+// Batched launches over many contexts ("walkers"): tab[W] device tables,
+// blk_start[W+1] device prefix of the workgroups of each walker.
+template <typename T>
+hipError_t launch_gather_batch(const GatherArgs* tab, const int32_t* blk_start, int32_t W, int32_t blocks,
+                               hipStream_t st);
+// pass: 1..4 = q6 passes, 5 = coordination forward, 6 = coordination forces
+template <typename T>
+hipError_t launch_pass_batch(int pass, bool with_cn, bool fp_rows, const CvArgs<T>* tab, const int32_t* blk_start,
+                             int32_t W, int32_t blocks, int32_t cap, hipStream_t st);
+hipError_t launch_bias_batch(const BiasArgs* tab, const int32_t* blk_start, int32_t W, int32_t blocks,
+                             hipStream_t st);
+hipError_t launch_sum_i32(const int32_t* v, int64_t n, unsigned long long* out, hipStream_t st);
+
+// LDS bytes of one staged halo slot: position only, or position + 16-wide row.
+template <typename T>
+constexpr int slot_bytes(bool with_row) {
+  return (int)sizeof(vec4_t<T>) * (with_row ? 5 : 1);
+}
+constexpr int kLdsBudget = 63 * 1024;  // dynamic LDS per workgroup for the halo (static arrays use the rest of 64 KB)
 
 // Number of blocks launched for n atoms: a multiple of the XCD count.
 inline int64_t atom_blocks(int64_t n) {

@@ -1,0 +1,79 @@
+"""Batched walkers: one launch per pass for many uneven systems gives, per
+walker, bitwise the same CV, bias, forces and hills as stepping it alone."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.helpers import params_for
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+Q6 = dict(cv="q6", precision="fp32", r_c=3.6, skin=0.4, taper=0.2, cn_r0=2.5, bond_d0=0.7, bond_w=0.02,
+          count_n0=5.5, count_w=0.25, sigma=[20.0], w0=W.W0_EV, gamma=10.0, kBT=W.KBT_EV, hills=dict(k=64))
+
+
+def walkers():
+    """(workload params, structure) of uneven walkers with all three CV kinds."""
+    out = []
+    for spec in (dict(nx=4, ny=3, nz=6, seed=21), dict(nx=8, ny=4, nz=8, seed=5), dict(nx=12, ny=6, nz=6, seed=7)):
+        out.append((Q6, W.wurtzite_slab(**spec)))
+    out.append((dict(W.WORKLOADS["wz2048"], precision="fp32"), W.structure(W.WORKLOADS["wz2048"]["structure"])))
+    out.append((dict(W.WORKLOADS["fcc864"], precision="fp32"), W.structure(W.WORKLOADS["fcc864"]["structure"])))
+    return out
+
+
+def setup(wl, d, dev, k):
+    from paper_2510_06873_amd import Pipeline
+
+    n = len(d["pos"])
+    pipe = Pipeline(n, params_for(wl, max_neighbors=96))
+    p4 = torch.from_numpy(W.as_float4(d["pos"], d["species"])).to(dev)
+    F = torch.from_numpy(W.external_forces(n, seed=100 + k)).to(dev)
+    pipe.build_neighbors_checked(p4, d["box"])
+    s0 = pipe.cv_forward(p4).cpu().numpy()
+    sig = np.array(wl["sigma"])
+    cen = W.hill_centres(50, s0 - 2 * sig, s0 + 2 * sig, seed=200 + k)
+    pipe.hills_set(cen, np.full(50, wl["w0"]))
+    return pipe, p4, F
+
+
+def test_batch_bitwise_equals_solo():
+    from paper_2510_06873_amd import Batch
+
+    dev = torch.device("cuda", 0)
+    ws = walkers()
+    solo = []
+    for k, (wl, d) in enumerate(ws):
+        pipe, p4, F = setup(wl, d, dev, k)
+        for step in range(3):
+            if step == 1:
+                pipe.deposit_hill()
+            pipe.step(p4, F)
+        torch.cuda.synchronize()
+        assert pipe.status(True) == 0
+        solo.append((pipe.s.cpu().numpy().copy(), pipe.V.cpu().numpy().copy(), F.cpu().numpy().copy(),
+                     pipe.hills_get()))
+    pipes, pos, forces = [], [], []
+    for k, (wl, d) in enumerate(ws):
+        pipe, p4, F = setup(wl, d, dev, k)
+        pipes.append(pipe)
+        pos.append(p4)
+        forces.append(F)
+    batch = Batch(pipes, pos, forces)
+    batch.build([d["box"] for _, d in ws])
+    for step in range(3):
+        if step == 1:
+            batch.deposit()
+        batch.step()
+    s, V = batch.values()
+    torch.cuda.synchronize()
+    for k, p in enumerate(pipes):
+        assert p.status(True) == 0
+        s_solo, V_solo, F_solo, (c_solo, h_solo) = solo[k]
+        dims = p.dims
+        assert np.array_equal(s[k, :dims].cpu().numpy(), s_solo[:dims]), k
+        assert V[k].item() == V_solo[0], k
+        assert np.array_equal(forces[k].cpu().numpy(), F_solo), k
+        c, h = p.hills_get()
+        assert np.array_equal(c, c_solo) and np.array_equal(h, h_solo), k

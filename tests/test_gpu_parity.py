@@ -295,3 +295,39 @@ def test_errors_and_call_order():
         small.deposit_hill(s)
     assert small.status(True) == -6
     assert len(small.hills_get()[1]) == 2
+
+
+# ---------------------------------------------------------------------------
+# torch.autograd: V(s(x)).backward() through the hand-written adjoint
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["stored", "recompute", "interleaved"])
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("fp64", 1e-6)])
+def test_autograd_2d_bias_gradient(orc, mode, precision, tol):
+    from paper_2510_06873_amd.autograd import GaussianBias, cv
+
+    wl = dict(W.WORKLOADS["wz2048"], precision=precision)
+    d = W.structure(wl["structure"])
+    pos, box = d["pos"], d["box"]
+    n = len(pos)
+    s_ref, g_ref, _ = oracle_cvs(orc, pos, box, wl)
+    sig = np.array(wl["sigma"])
+    cen = W.hill_centres(200, s_ref - 3 * sig, s_ref + 3 * sig, seed=15)
+    hts = orc.deposit_sequence(cen, sig, wl["w0"], wl["gamma"], wl["kBT"])
+    pipe = make_pipe(wl, n)
+    pipe.hills_set(cen, hts)
+    p4 = to_dev(W.as_float4(pos)).requires_grad_(True)
+    pipe.build_neighbors_checked(p4.detach(), box)
+    s = cv(p4, pipe, "recompute" if mode == "recompute" else "stored")
+    V = GaussianBias.apply(s, pipe)
+    if mode == "interleaved":
+        pipe.cv_forward(p4.detach())  # a second forward in between: backward must recompute
+    V.backward()
+    torch.cuda.synchronize()
+    s_gpu = s.detach().cpu().numpy()
+    assert np.all(np.abs(s_gpu - s_ref) <= (1e-5 if precision == "fp32" else 1e-10) * np.abs(s_ref))
+    Vr, dVr = orc.bias(cen, hts, sig, s_gpu)
+    assert abs(V.item() - Vr) <= 1e-12 * Vr
+    grad_ref = dVr[0] * g_ref[0] + dVr[1] * g_ref[1]
+    g = p4.grad.cpu().numpy().astype(np.float64)
+    assert rel_force_err(g[:, :3], grad_ref) <= tol
+    assert np.all(g[:, 3] == 0)
