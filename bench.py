@@ -25,6 +25,16 @@ MD_STEPS_PER_WINDOW = 10
 HBM_PEAK_GBS = 8000.0
 # FP32 vector peak without packed FP32: 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+FLOPS_PER_PAIR_P4 = 228
+# k_pass4 per owned atom: slot/rank tables 8, cutoff count 4, position 16, adjoint
+# row 64, taper term 16, permutation 4, force read + write 32
+P4_BYTES_PER_ATOM = 144
+# one MD step per atom: gather (perm 4, positions 16 read + 16 write), pass 1
+# (positions 16, q-hat row write 64), pass 2 (q-hat row 64, c' 4, count 4),
+# pass 3 (q-hat row 64, adjoint row write 64, taper term 16), pass 4 (as above
+# less what is counted), plus the per-step cutoff rows (2 B per pair, written
+# once and read three times, counted as 8 B per pair) and the rebuild / 10
+STEP_BYTES_PER_ATOM = 36 + 80 + 72 + 144 + 144
 
 
 def parse():
@@ -35,6 +45,9 @@ def parse():
     ap.add_argument("--workload", default="wz1m")
     ap.add_argument("--graph", action="store_true", help="replay each window as a captured HIP graph")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--serving", action="store_true",
+                    help="also run the walker-serving workload (256 requests, continuous batching vs sequential)")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving workload")
     return ap.parse_args()
 
 
@@ -110,13 +123,6 @@ def window(S, ev=None):
     timed("deposit_hill", pipe.deposit_hill)
 
 
-def neighbor_pairs(S):
-    """Total list entries and pairs inside r_c (for the per-launch work model)."""
-    pipe = S["pipe"]
-    _, total = pipe.neighbor_stats()
-    return total
-
-
 def cpu_baseline(wl_name="wz96k"):
     """The oracle as it stands, single threaded, on the same recipe at 96,000
     atoms: one neighbour build amortised over 10 steps plus one step of
@@ -154,6 +160,44 @@ def cpu_baseline(wl_name="wz96k"):
                       f"FP64, single thread, {time.time() - t_all:.1f} s"}
 
 
+def serving_requests(count=256, seed=7, n_hi=200000):
+    """The serving workload as library requests."""
+    import workloads as W
+    from paper_2510_06873_amd import FP32, Params
+    from paper_2510_06873_amd.serving import Request
+
+    out = []
+    for r in W.serving_requests(count=count, seed=seed, n_hi=n_hi):
+        p = r["params"]
+        kind = {"coord": 1, "q6": 2}[p["cv"]]
+        prm = Params(cv_kind=kind, precision=FP32, r_c=p["r_c"], skin=p["skin"], taper=p["taper"], cn_r0=p["cn_r0"],
+                     sigma=p["sigma"], w0=r["w0"], gamma=10.0, kBT=r["kBT"],
+                     hill_capacity=r["centres"].shape[0] + 64, max_neighbors=p["kmax"])
+        out.append(Request(r["rid"], r["arrival"], r["pos"], r["box"], prm, r["centres"], r["heights"], r["forces"]))
+    return out
+
+
+def serving(args):
+    """p50/p99 request latency and aggregate atom-steps/s, batched vs sequential."""
+    from paper_2510_06873_amd.serving import serve_batched, serve_sequential, summarize
+
+    reqs = serving_requests()
+    warm = serving_requests(count=4, seed=99, n_hi=5000)
+    serve_batched(warm, hbm_budget=64 << 30)
+    serve_sequential(warm)
+    log(f"[bench] serving: {len(reqs)} requests, {sum(r.n for r in reqs)} atoms")
+    rb, sb = serve_batched(reqs, hbm_budget=64 << 30, max_slots=64)
+    log(f"[bench] batched: {sb['wall_s']:.2f} s")
+    rs, ss = serve_sequential(reqs)
+    log(f"[bench] sequential: {ss['wall_s']:.2f} s")
+    steps = reqs[0].steps
+    b = summarize(rb, sb, steps)
+    q = summarize(rs, ss, steps)
+    return {"requests": len(reqs), "steps_per_request": steps, "arrival_rate_per_s": 2000.0,
+            "hbm_budget_gib": 64, "slots": 64, "batched": b, "sequential": q,
+            "speedup_atom_steps": b["atom_steps_per_s"] / q["atom_steps_per_s"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -162,6 +206,9 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.serving_only:
+        print(json.dumps({"serving": serving(args)}), flush=True)
+        return
     S = setup(args.workload)
     n = S["n"]
     stream = S["stream"]
@@ -209,20 +256,27 @@ def main():
             per_call.setdefault(name, []).append(e0.elapsed_time(e1))
     per_call_us = {k: 1e3 * float(np.mean(v)) for k, v in per_call.items()}
 
-    total_entries = neighbor_pairs(S)
-    # apply_bias_forces is one launch of the force kernel (the dominant kernel).
-    # Algorithmic HBM bytes per atom for that launch: own position 16, own
-    # adjoint row 64, row length 4, permutation 4, force read+write 32, and its
-    # neighbour row 4 per entry (neighbour rows of q-hat/adjoint assumed cached).
-    force_bytes = n * (16 + 64 + 4 + 4 + 32) + 4 * total_entries
+    mx, total_entries, cut_pairs = S["pipe"].neighbor_stats(cutoff_pairs=True)
     roofline = None
     if "apply_bias_forces" in per_call_us:
+        # Dominant launch: k_pass4 (apply_bias_forces), bound by FP32 VALU work.
+        # Algorithmic flops per ordered pair inside r_c (FMA = 2): geometry and
+        # minimum image 26, 1/r and unit vector 5, g_i + g_j 13, S and its
+        # gradient by the complex recurrence 166, tangential projection and
+        # accumulation 18: 228.  Peak: 256 CUs x 64 FP32 lanes x 2 x 2.4 GHz
+        # (packed FP32 is not used).
         t_us = per_call_us["apply_bias_forces"]
-        achieved = force_bytes / (t_us * 1e-6) / 1e9
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": "k_q6_p4 (apply_bias_forces)", "avg_launch_us": round(t_us, 2),
-                    "bytes_per_launch": int(force_bytes)}
+        flops = FLOPS_PER_PAIR_P4 * cut_pairs
+        achieved = flops / (t_us * 1e-6) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                    "kernel": "k_pass4 (apply_bias_forces)", "avg_launch_us": round(t_us, 2),
+                    "flops_per_launch": int(flops), "pairs_in_cutoff": int(cut_pairs),
+                    "hbm_bytes_per_launch": int(n * P4_BYTES_PER_ATOM + 2 * cut_pairs)}
+    # Whole step against HBM: algorithmic bytes per atom-step (each array the
+    # dependency chain forces through memory, once per write and once per read).
+    step_bytes = n * STEP_BYTES_PER_ATOM + 2 * 4 * cut_pairs + n * (4 * (total_entries / n) + 40) / MD_STEPS_PER_WINDOW
+    step_hbm = step_bytes / (ms_per_window / MD_STEPS_PER_WINDOW * 1e-3) / 1e9
     out = {
         "metric": "atom-steps/s for q6-CV+bias+force at 1.02M atoms (%HBM roofline)",
         "value": value,
@@ -244,7 +298,11 @@ def main():
                    "neighbor_entries": int(total_entries)},
         "per_call_us": {k: round(v, 2) for k, v in per_call_us.items()},
         "roofline": roofline,
+        "step_hbm": {"achieved_gbs": round(step_hbm, 1), "peak_gbs": HBM_PEAK_GBS,
+                     "frac": round(step_hbm / HBM_PEAK_GBS, 4), "bytes_per_step": int(step_bytes)},
     }
+    if args.serving:
+        out["serving"] = serving(args)
     if not args.no_cpu:
         log("[bench] timing the oracle on the host cores ...")
         out["cpu_baseline"] = cpu_baseline()

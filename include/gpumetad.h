@@ -92,7 +92,8 @@ typedef struct gm_params {
   double kBT;            /* k_B T in the energy unit of w0                    */
   int64_t hill_capacity; /* maximum number of hills kept on the device        */
   int32_t max_neighbors; /* neighbour-list row width (rounded up to 4)        */
-  int32_t reserved;      /* must be 0                                         */
+  int32_t brick[3];      /* cells per brick and axis (1..4); 0 = chosen per build */
+  int32_t lds_kb;        /* LDS staging budget per workgroup in KiB; 0 = auto */
 } gm_params;
 
 typedef struct gm_ctx gm_ctx;
@@ -153,7 +154,8 @@ int gm_apply_bias_forces(gm_ctx* ctx, const float* pos4, const double* dVds_dev,
  *   h = w0 exp(-V(s) / (kBT (gamma - 1)))     (gamma == 0: h = w0)
  * where V(s) is the bias of the hills already deposited (Barducci, Bussi,
  * Parrinello 2008; the paper names well-tempered metadynamics for its
- * rutile study).  The hill count lives on the device, so the call can be
+ * rutile study).  s_dev == NULL deposits at the CV value of the context's
+ * last forward pass (GM_ERR_STATE if there was none).  The hill count lives on the device, so the call can be
  * replayed inside a graph; a full buffer sets the sticky GM_ERR_HILL_CAPACITY
  * and deposits nothing. */
 int gm_deposit_hill(gm_ctx* ctx, const double* s_dev);

@@ -47,7 +47,7 @@ class GmParams(C.Structure):
         ("r_c", C.c_double), ("skin", C.c_double), ("taper", C.c_double), ("cn_r0", C.c_double),
         ("bond_d0", C.c_double), ("bond_w", C.c_double), ("count_n0", C.c_double), ("count_w", C.c_double),
         ("sigma", C.c_double * 2), ("w0", C.c_double), ("gamma", C.c_double), ("kBT", C.c_double),
-        ("hill_capacity", C.c_int64), ("max_neighbors", C.c_int32), ("reserved", C.c_int32),
+        ("hill_capacity", C.c_int64), ("max_neighbors", C.c_int32), ("brick", C.c_int32 * 3), ("lds_kb", C.c_int32),
     ]
 
 
@@ -138,6 +138,8 @@ class Params:
     kBT: float = 2.494
     hill_capacity: int = 100000
     max_neighbors: int = 64
+    brick: Sequence[int] = (0, 0, 0)  # cells per brick and axis; 0 = chosen per build
+    lds_kb: int = 0                   # LDS staging budget per workgroup; 0 = auto
 
     @property
     def dims(self) -> int:
@@ -147,7 +149,8 @@ class Params:
         sig = list(self.sigma) + [0.0] * (2 - len(self.sigma))
         return GmParams(self.cv_kind, self.precision, self.r_c, self.skin, self.taper, self.cn_r0,
                         self.bond_d0, self.bond_w, self.count_n0, self.count_w, (C.c_double * 2)(*sig[:2]),
-                        self.w0, self.gamma, self.kBT, self.hill_capacity, self.max_neighbors, 0)
+                        self.w0, self.gamma, self.kBT, self.hill_capacity, self.max_neighbors,
+                        (C.c_int32 * 3)(*[int(b) for b in self.brick]), int(self.lds_kb))
 
 
 class Pipeline:
@@ -228,8 +231,8 @@ class Pipeline:
         return force4
 
     def deposit_hill(self, s=None):
-        s = self.s if s is None else s
-        _check(_lib.gm_deposit_hill(self.h, self._vec(s, "s")), "gm_deposit_hill")
+        """Deposit at s (device double[dims]); None = at the last forward's CV."""
+        _check(_lib.gm_deposit_hill(self.h, self._vec(s, "s") if s is not None else None), "gm_deposit_hill")
 
     # ---- one MD step's bias pipeline ---------------------------------------
     def step(self, pos4, force4):

@@ -29,6 +29,8 @@ struct gm_ctx {
 
   // cell list (canonical sorted order)
   int32_t *cell = nullptr, *count = nullptr, *start = nullptr, *fill = nullptr, *perm = nullptr;
+  int32_t* scan_tmp = nullptr;  // tile sums of the prefix scans
+  int64_t scan_tmp_cap = 0;
   // bricks
   int32_t *brick_H = nullptr, *brick_O = nullptr, *brick_hb = nullptr, *brick_ob = nullptr, *brick_hp = nullptr;
   int32_t *halo_rank = nullptr, *owned_slot = nullptr, *owned_rank = nullptr, *owned_hcell = nullptr;
@@ -37,13 +39,13 @@ struct gm_ctx {
   int32_t *cnt = nullptr, *ccnt = nullptr, *err = nullptr, *stats = nullptr;
   void *pos_s = nullptr, *qrow = nullptr, *grow = nullptr, *frad = nullptr, *nb = nullptr, *cn_atom = nullptr;
   double *part_a = nullptr, *part_b = nullptr, *s_int = nullptr, *V_int = nullptr, *dV_int = nullptr;
-  unsigned* tickets = nullptr;
   double *centres = nullptr, *heights = nullptr, *bias_part = nullptr;
   int64_t* hill_count = nullptr;
 
   bool built = false, fwd = false, bwd = false;
   int last_status = GM_OK;
   int64_t version = 0;  // bumped whenever the kernel arguments may change
+  int lds_budget = 0;   // bytes of dynamic LDS for the staged halo
   YCoef<float> ycf;
   YCoef<double> ycd;
 };
@@ -119,8 +121,11 @@ int validate(const gm_params* p, int64_t n) {
     if (!(p->sigma[d] > 0.0)) return GM_ERR_INVALID_ARG;
   if (!(p->w0 >= 0.0) || !(p->gamma == 0.0 || p->gamma > 1.0)) return GM_ERR_INVALID_ARG;
   if (p->gamma > 1.0 && !(p->kBT > 0.0)) return GM_ERR_INVALID_ARG;
-  if (p->hill_capacity < 0 || p->max_neighbors < 0 || p->max_neighbors > 4096 || p->reserved != 0)
-    return GM_ERR_INVALID_ARG;
+  if (p->hill_capacity < 0 || p->max_neighbors < 0 || p->max_neighbors > 4096) return GM_ERR_INVALID_ARG;
+  for (int a = 0; a < 3; a++)
+    if (p->brick[a] < 0 || p->brick[a] > kMaxBrick) return GM_ERR_INVALID_ARG;
+  if ((p->brick[0] == 0) != (p->brick[1] == 0) || (p->brick[0] == 0) != (p->brick[2] == 0)) return GM_ERR_INVALID_ARG;
+  if (p->lds_kb < 0 || p->lds_kb > 160) return GM_ERR_INVALID_ARG;
   return GM_OK;
 }
 
@@ -179,34 +184,43 @@ CvArgs<T> make_args(gm_ctx* c) {
   a.cn_atom = reinterpret_cast<T*>(c->cn_atom);
   a.part_a = c->part_a;
   a.part_b = c->part_b;
-  a.ticket = c->tickets;
   a.s_int = c->s_int;
   a.err = c->err;
   return a;
 }
 
-// Brick size: the most cells per brick whose expected halo (atoms of the
-// (b+2)^3 cells around it, with a 15% margin) fits the LDS staging budget and
-// whose expected owned atoms fit one pass of a 256-thread workgroup.
+// Brick size and threads per atom: among the bricks whose expected halo (atoms
+// of the (b+2)^3 cells around them, 5% margin) fits the LDS staging budget,
+// the one that keeps the most lanes of a 256-thread workgroup busy
+// (owned atoms x threads per atom, at most 92% of 256 so that fluctuations
+// rarely need a second pass), discounted by the halo re-load ratio.
 void choose_bricks(gm_ctx* c, const int32_t nc[3]) {
   const int rec = c->fp64 ? slot_bytes<double>(c->has_q6) : slot_bytes<float>(c->has_q6);
-  const int cap = kLdsBudget / rec;
+  const int cap = c->lds_budget / rec;
   const double rho = (double)c->n / ((double)nc[0] * nc[1] * nc[2]);
-  int best[3] = {1, 1, 1};
-  double best_own = -1.0, best_ratio = 1e30;
+  int best[3] = {1, 1, 1}, best_tpa = 1;
+  double best_score = -1.0;
+  const bool fixed = c->p.brick[0] > 0;
   for (int bx = 1; bx <= kMaxBrick && bx <= nc[0]; bx++)
     for (int by = 1; by <= kMaxBrick && by <= nc[1]; by++)
       for (int bz = 1; bz <= kMaxBrick && bz <= nc[2]; bz++) {
-        const double halo = (double)(bx + 2) * (by + 2) * (bz + 2) * rho * 1.15;
+        if (fixed && (bx != (c->p.brick[0] < nc[0] ? c->p.brick[0] : nc[0]) ||
+                      by != (c->p.brick[1] < nc[1] ? c->p.brick[1] : nc[1]) ||
+                      bz != (c->p.brick[2] < nc[2] ? c->p.brick[2] : nc[2])))
+          continue;
+        const double halo = (double)(bx + 2) * (by + 2) * (bz + 2) * rho;
         const double own = (double)bx * by * bz * rho;
-        if (halo > cap || own > 0.95 * kBlock) continue;
-        const double ratio = halo / own;
-        if (own > best_own * 1.0001 || (own > best_own * 0.9999 && ratio < best_ratio)) {
-          best_own = own;
-          best_ratio = ratio;
-          best[0] = bx;
-          best[1] = by;
-          best[2] = bz;
+        if (!fixed && halo * 1.05 > cap) continue;
+        for (int tpa = 1; tpa <= 4; tpa *= 2) {
+          if (own * tpa > 0.92 * kBlock && !(fixed && tpa == 1)) continue;
+          const double score = own * tpa * (1.0 - 0.02 * halo / own);
+          if (score > best_score) {
+            best_score = score;
+            best[0] = bx;
+            best[1] = by;
+            best[2] = bz;
+            best_tpa = tpa;
+          }
         }
       }
   BrickGeom& g = c->bg;
@@ -218,6 +232,7 @@ void choose_bricks(gm_ctx* c, const int32_t nc[3]) {
   g.nbricks = g.nb[0] * g.nb[1] * g.nb[2];
   g.cap = cap;
   g.blocks = (g.nbricks + kXcd - 1) / kXcd * kXcd;
+  g.tpa = best_tpa;
 }
 
 // Upper bound of the total halo slots: each cell is counted once per brick
@@ -256,7 +271,6 @@ BiasArgs make_bias(gm_ctx* c, const double* s, int deposit) {
   b.w0 = c->p.w0;
   b.wt_scale = c->p.gamma == 0.0 ? 0.0 : 1.0 / (c->p.kBT * (c->p.gamma - 1.0));
   b.part = c->bias_part;
-  b.ticket = c->tickets + 1;
   b.err = c->err;
   return b;
 }
@@ -266,6 +280,7 @@ void free_all(gm_ctx* c) {
   dfree(c->count);
   dfree(c->start);
   dfree(c->fill);
+  dfree(c->scan_tmp);
   dfree(c->perm);
   dfree(c->brick_H);
   dfree(c->brick_O);
@@ -293,7 +308,6 @@ void free_all(gm_ctx* c) {
   dfree(c->s_int);
   dfree(c->V_int);
   dfree(c->dV_int);
-  dfree(c->tickets);
   dfree(c->centres);
   dfree(c->heights);
   dfree(c->bias_part);
@@ -375,6 +389,20 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   c->bias_blocks = (int)(hb < 1 ? 1 : (hb > 1024 ? 1024 : hb));
   make_ycoef(c->ycf);
   make_ycoef(c->ycd);
+  {
+    // LDS staging budget: the caller's, else what keeps two workgroups per CU
+    // within the device limit (static arrays take the last 2 KiB).
+    int dev = 0, lim = 65536;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      lim = 65536;
+    (void)hipGetLastError();
+    int want = params->lds_kb > 0 ? params->lds_kb * 1024 : 80 * 1024;
+    if (want > lim) want = lim;
+    c->lds_budget = want - 2048;
+    allow_cv_lds(c->lds_budget);
+    allow_build_lds(c->lds_budget);
+  }
 
   const size_t n = (size_t)n_atoms, T = c->fp64 ? 8 : 4;
   const size_t cap = (size_t)(params->hill_capacity > 0 ? params->hill_capacity : 1);
@@ -385,7 +413,7 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   if (rc == GM_OK) rc = dalloc(&c->owned_rank, n * 4);
   if (rc == GM_OK) rc = dalloc(&c->owned_hcell, n * 4);
   if (rc == GM_OK) rc = dalloc(&c->cnt, n * 4);
-  if (rc == GM_OK) rc = dalloc(&c->ccnt, n * 4);
+  if (rc == GM_OK) rc = dalloc(&c->ccnt, n * 4 * 4);  // up to 4 parts per atom
   if (rc == GM_OK) rc = dalloc(&c->nbr, n * (size_t)c->kmax * 2);
   if (rc == GM_OK) rc = dalloc(&c->cut, n * (size_t)c->kmax * 2);
   if (rc == GM_OK) rc = dalloc(&c->pos_s, n * 4 * T);
@@ -397,7 +425,6 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   if (rc == GM_OK) rc = dalloc(&c->s_int, 16);
   if (rc == GM_OK) rc = dalloc(&c->V_int, 16);
   if (rc == GM_OK) rc = dalloc(&c->dV_int, 16);
-  if (rc == GM_OK) rc = dalloc(&c->tickets, 16);
   if (rc == GM_OK) rc = dalloc(&c->err, 16);
   if (rc == GM_OK) rc = dalloc(&c->stats, 32);
   if (rc == GM_OK) rc = dalloc(&c->centres, cap * c->dims * 8);
@@ -405,7 +432,7 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   if (rc == GM_OK) rc = dalloc(&c->hill_count, 16);
   if (rc == GM_OK) rc = dalloc(&c->bias_part, (size_t)c->bias_blocks * 3 * 8);
   if (rc == GM_OK) {
-    bool ok = hipMemset(c->tickets, 0, 16) == hipSuccess && hipMemset(c->err, 0, 16) == hipSuccess &&
+    bool ok = hipMemset(c->err, 0, 16) == hipSuccess &&
               hipMemset(c->hill_count, 0, 16) == hipSuccess && hipMemset(c->stats, 0, 32) == hipSuccess &&
               hipMemset(c->s_int, 0, 16) == hipSuccess && hipMemset(c->V_int, 0, 16) == hipSuccess &&
               hipMemset(c->dV_int, 0, 16) == hipSuccess && hipMemset(c->cn_atom, 0, n * T) == hipSuccess &&
@@ -496,6 +523,14 @@ int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
     c->ncells_cap = ncells;
   }
   c->ncells = ncells;
+  const int64_t tiles = (ncells + 1023) / 1024 + 1;
+  if (tiles > c->scan_tmp_cap) {
+    (void)hipStreamSynchronize(c->stream);
+    dfree(c->scan_tmp);
+    c->scan_tmp_cap = 0;
+    GM_TRY(dalloc(&c->scan_tmp, (size_t)tiles * 4));
+    c->scan_tmp_cap = tiles;
+  }
   for (int a = 0; a < 3; a++) {
     c->box[a] = box[a];
     c->geom.L[a] = box[a];
@@ -512,13 +547,13 @@ int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
   GM_TRY(hip_rc(launch_fill_i32(c->count, 0, ncells, st)));
   GM_TRY(hip_rc(launch_fill_i32(c->stats, 0, 4, st)));
   GM_TRY(hip_rc(launch_cell_ids(p4, c->n, c->geom, c->cell, c->count, c->err, st)));
-  GM_TRY(hip_rc(launch_scan(c->count, ncells, c->start, c->fill, st)));
+  GM_TRY(hip_rc(launch_scan(c->count, ncells, c->start, c->fill, c->scan_tmp, st)));
   GM_TRY(hip_rc(launch_scatter(c->cell, c->n, c->start, c->fill, c->perm, st)));
   GM_TRY(hip_rc(launch_sort_cells(c->start, ncells, c->perm, st)));
   // bricks: halo and owned sizes, their prefix sums, the slot tables
   GM_TRY(hip_rc(launch_brick_count(c->start, c->bg, c->brick_H, c->brick_O, st)));
-  GM_TRY(hip_rc(launch_scan(c->brick_H, c->bg.nbricks, c->brick_hb, nullptr, st)));
-  GM_TRY(hip_rc(launch_scan(c->brick_O, c->bg.nbricks, c->brick_ob, nullptr, st)));
+  GM_TRY(hip_rc(launch_scan(c->brick_H, c->bg.nbricks, c->brick_hb, nullptr, c->scan_tmp, st)));
+  GM_TRY(hip_rc(launch_scan(c->brick_O, c->bg.nbricks, c->brick_ob, nullptr, c->scan_tmp, st)));
   const BrickIndex bi = brick_index(c);
   GM_TRY(hip_rc(launch_brick_fill(c->start, c->bg, bi, c->brick_hp, c->halo_rank, c->owned_slot, c->owned_rank,
                                   c->owned_hcell, c->err, st)));
@@ -557,8 +592,9 @@ int gm_bias_eval(gm_ctx* c, const double* s_dev, double* V_dev, double* dVds_dev
 }
 
 int gm_deposit_hill(gm_ctx* c, const double* s_dev) {
-  if (!c || !s_dev) return GM_ERR_INVALID_ARG;
-  BiasArgs b = make_bias(c, s_dev, 1);
+  if (!c) return GM_ERR_INVALID_ARG;
+  if (!s_dev && !c->fwd) return GM_ERR_STATE;
+  BiasArgs b = make_bias(c, s_dev ? s_dev : c->s_int, 1);
   return hip_rc(launch_bias(b, c->bias_blocks, c->stream));
 }
 
@@ -633,7 +669,9 @@ int gm_neighbor_stats(gm_ctx* c, int32_t* max_count, int64_t* total, int64_t* cu
   if (!c->built) return GM_ERR_STATE;
   if (cutoff_pairs) {
     GM_TRY(hip_rc(launch_fill_i32(c->stats + 4, 0, 2, c->stream)));
-    if (c->fwd) GM_TRY(hip_rc(launch_sum_i32(c->ccnt, c->n, reinterpret_cast<unsigned long long*>(c->stats + 4), c->stream)));
+    if (c->fwd)
+      GM_TRY(hip_rc(launch_sum_i32(c->ccnt, c->n * c->bg.tpa, reinterpret_cast<unsigned long long*>(c->stats + 4),
+                                   c->stream)));
   }
   if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
   int32_t s[8];
@@ -708,6 +746,7 @@ struct gm_batch {
     std::vector<int> members;     // indices into walkers
     std::vector<int64_t> versions;
     std::vector<unsigned char> h_cv, h_gather, h_bias, h_dep;  // host images of the tables
+    std::vector<int32_t> h_blk_cv, h_blk_gather, h_blk_bias;
     void *d_cv = nullptr, *d_gather = nullptr, *d_bias = nullptr, *d_dep = nullptr;
     int32_t *d_blk_cv = nullptr, *d_blk_gather = nullptr, *d_blk_bias = nullptr;
     int32_t blocks_cv = 0, blocks_gather = 0, blocks_bias = 0, cap = 0;
@@ -779,9 +818,12 @@ int refresh_group(gm_batch* B, gm_batch::Group& g, bool force) {
   if (force || ga != g.h_gather) GM_TRY(upload(ga, &g.d_gather, B->stream));
   if (force || bi != g.h_bias) GM_TRY(upload(bi, &g.d_bias, B->stream));
   if (force || de != g.h_dep) GM_TRY(upload(de, &g.d_dep, B->stream));
-  GM_TRY(upload_i32(bcv, &g.d_blk_cv, B->stream));
-  GM_TRY(upload_i32(bga, &g.d_blk_gather, B->stream));
-  GM_TRY(upload_i32(bbi, &g.d_blk_bias, B->stream));
+  if (force || bcv != g.h_blk_cv) GM_TRY(upload_i32(bcv, &g.d_blk_cv, B->stream));
+  if (force || bga != g.h_blk_gather) GM_TRY(upload_i32(bga, &g.d_blk_gather, B->stream));
+  if (force || bbi != g.h_blk_bias) GM_TRY(upload_i32(bbi, &g.d_blk_bias, B->stream));
+  g.h_blk_cv.swap(bcv);
+  g.h_blk_gather.swap(bga);
+  g.h_blk_bias.swap(bbi);
   g.h_cv.swap(cv);
   g.h_gather.swap(ga);
   g.h_bias.swap(bi);

@@ -31,44 +31,56 @@ __device__ __forceinline__ void bias_body(const BiasArgs& a, int32_t blk, int32_
   g0 = block_sum(g0, red);
   if (a.dims > 1) g1 = block_sum(g1, red);
   if (threadIdx.x == 0) {
-    store_agent(&a.part[blk * 3 + 0], v);
-    store_agent(&a.part[blk * 3 + 1], g0);
-    store_agent(&a.part[blk * 3 + 2], g1);
+    a.part[blk * 3 + 0] = v;
+    a.part[blk * 3 + 1] = g0;
+    a.part[blk * 3 + 2] = g1;
   }
-  if (last_block_done(a.ticket, nblk)) {
-    double V = 0.0, G0 = 0.0, G1 = 0.0;
-    for (int64_t i = threadIdx.x; i < (int64_t)nblk; i += blockDim.x) {
-      V += load_agent(&a.part[i * 3 + 0]);
-      G0 += load_agent(&a.part[i * 3 + 1]);
-      G1 += load_agent(&a.part[i * 3 + 2]);
-    }
-    V = block_sum(V, red);
-    G0 = block_sum(G0, red);
-    if (a.dims > 1) G1 = block_sum(G1, red);
-    if (threadIdx.x == 0) {
-      if (!isfinite(V)) atomicOr(a.err, kErrNonFinite);
-      if (a.deposit) {
-        const double h = a.wt_scale == 0.0 ? a.w0 : a.w0 * exp(-V * a.wt_scale);
-        if (K < a.capacity) {
-          for (int d = 0; d < a.dims; d++) a.centres[K * a.dims + d] = s[d];
-          a.heights[K] = h;
-          *a.count = K + 1;
-        } else {
-          atomicOr(a.err, kErrCapacity);
-        }
+}
+
+// Fixed-order sum of the bias partials (its own launch); V and dV/ds, or the
+// deposit of one hill.
+__device__ __forceinline__ void bias_finish_body(const BiasArgs& a, int32_t nblk) {
+  __shared__ double red[kBlock / 64];
+  const int64_t K = *a.count;
+  double V = 0.0, G0 = 0.0, G1 = 0.0;
+  for (int64_t i = threadIdx.x; i < (int64_t)nblk; i += blockDim.x) {
+    V += a.part[i * 3 + 0];
+    G0 += a.part[i * 3 + 1];
+    G1 += a.part[i * 3 + 2];
+  }
+  V = block_sum(V, red);
+  G0 = block_sum(G0, red);
+  if (a.dims > 1) G1 = block_sum(G1, red);
+  if (threadIdx.x == 0) {
+    if (!isfinite(V)) atomicOr(a.err, kErrNonFinite);
+    if (a.deposit) {
+      const double h = a.wt_scale == 0.0 ? a.w0 : a.w0 * exp(-V * a.wt_scale);
+      if (K < a.capacity) {
+        for (int d = 0; d < a.dims; d++) a.centres[K * a.dims + d] = a.s[d];
+        a.heights[K] = h;
+        *a.count = K + 1;
       } else {
-        if (a.V_out) a.V_out[0] = V;
-        if (a.dV_out) {
-          a.dV_out[0] = G0;
-          if (a.dims > 1) a.dV_out[1] = G1;
-        }
+        atomicOr(a.err, kErrCapacity);
+      }
+    } else {
+      if (a.V_out) a.V_out[0] = V;
+      if (a.dV_out) {
+        a.dV_out[0] = G0;
+        if (a.dims > 1) a.dV_out[1] = G1;
       }
     }
-    release_ticket(a.ticket);
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_bias(BiasArgs a) { bias_body(a, blockIdx.x, gridDim.x); }
+
+__global__ __launch_bounds__(kBlock) void k_bias_finish(BiasArgs a, int32_t nblk) { bias_finish_body(a, nblk); }
+
+__global__ __launch_bounds__(kBlock) void k_bias_finish_batch(const BiasArgs* __restrict__ tab,
+                                                              const int32_t* __restrict__ blk_start) {
+  const int32_t w = blockIdx.x;
+  bias_finish_body(tab[w], blk_start[w + 1] - blk_start[w]);
+}
 
 // One launch for many walkers: workgroup g serves walker w with
 // blk_start[w] <= g < blk_start[w+1].
@@ -86,11 +98,13 @@ __global__ __launch_bounds__(kBlock) void k_bias_batch(const BiasArgs* __restric
 hipError_t launch_bias_batch(const BiasArgs* tab, const int32_t* blk_start, int32_t W, int32_t blocks,
                              hipStream_t st) {
   k_bias_batch<<<(unsigned)blocks, kBlock, 0, st>>>(tab, blk_start, W);
+  k_bias_finish_batch<<<(unsigned)W, kBlock, 0, st>>>(tab, blk_start);
   return hipGetLastError();
 }
 
 hipError_t launch_bias(const BiasArgs& a, int blocks, hipStream_t st) {
   k_bias<<<(unsigned)blocks, kBlock, 0, st>>>(a);
+  k_bias_finish<<<1, kBlock, 0, st>>>(a, blocks);
   return hipGetLastError();
 }
 

@@ -53,35 +53,65 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids(const float4* __restrict__ 
   atomicAdd(&count[id], 1);
 }
 
-// Exclusive prefix sum of n int32 values in one block of 1024 threads: each
-// thread sums a contiguous chunk, the chunk sums are scanned in LDS, then each
-// thread writes its chunk; out[n] receives the total.  If zero != NULL it is
+// Exclusive prefix sum of n int32 values, out[n] = total, in three launches:
+// tile sums (1024 values per workgroup), a scan of the tile sums in one
+// workgroup, and the scan of each tile from its offset.  If zero != NULL it is
 // cleared alongside (the scatter cursors of the cell sort).
-__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ in, int64_t n,
-                                               int32_t* __restrict__ out, int32_t* __restrict__ zero) {
-  __shared__ int32_t sums[1024];
+constexpr int kScanTile = 1024;
+
+__device__ __forceinline__ int32_t block_scan_incl(int32_t v, int32_t* lds) {
   const int tid = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t b = tid * per;
-  const int64_t e = b + per < n ? b + per : n;
-  int32_t s = 0;
-  for (int64_t i = b; i < e; i++) s += in[i];
-  sums[tid] = s;
+  lds[tid] = v;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int32_t v = tid >= off ? sums[tid - off] : 0;
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int32_t u = tid >= off ? lds[tid - off] : 0;
     __syncthreads();
-    sums[tid] += v;
+    lds[tid] += u;
     __syncthreads();
   }
-  int32_t run = sums[tid] - s;
-  for (int64_t i = b; i < e; i++) {
-    const int32_t c = in[i];
-    out[i] = run;
-    run += c;
+  const int32_t r = lds[tid];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kScanTile) void k_tile_sums(const int32_t* __restrict__ in, int64_t n,
+                                                         int32_t* __restrict__ sums) {
+  __shared__ double red[kScanTile / 64];
+  const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+  const double v = i < n ? (double)in[i] : 0.0;
+  const double t = block_sum(v, red);
+  if (threadIdx.x == 0) sums[blockIdx.x] = (int32_t)t;
+}
+
+__global__ __launch_bounds__(kScanTile) void k_scan_sums(int32_t* __restrict__ sums, int64_t ntiles,
+                                                         int32_t* __restrict__ out, int64_t n) {
+  __shared__ int32_t lds[kScanTile];
+  __shared__ int32_t total;
+  int32_t carry = 0;
+  for (int64_t base = 0; base < ntiles; base += kScanTile) {
+    const int64_t i = base + threadIdx.x;
+    const int32_t v = i < ntiles ? sums[i] : 0;
+    const int32_t incl = block_scan_incl(v, lds);
+    if (i < ntiles) sums[i] = carry + incl - v;
+    if (threadIdx.x == kScanTile - 1) total = incl;
+    __syncthreads();
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ __launch_bounds__(kScanTile) void k_scan_tiles(const int32_t* __restrict__ in, int64_t n,
+                                                          const int32_t* __restrict__ offs, int32_t* __restrict__ out,
+                                                          int32_t* __restrict__ zero) {
+  __shared__ int32_t lds[kScanTile];
+  const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+  const int32_t v = i < n ? in[i] : 0;
+  const int32_t incl = block_scan_incl(v, lds);
+  if (i < n) {
+    out[i] = offs[blockIdx.x] + incl - v;
     if (zero) zero[i] = 0;
   }
-  if (tid == 1023) out[n] = sums[1023];
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ cell, int64_t n,
@@ -149,22 +179,32 @@ __global__ __launch_bounds__(kBlock) void k_gather_batch(const GatherArgs* __res
 // --------------------------------------------------------------------------
 // Bricks: halo sizes, halo slot tables, owned atoms (every rebuild)
 // --------------------------------------------------------------------------
+// One wave per brick: lanes over the halo cells, wave sums of the halo and
+// owned atom counts.
 __global__ __launch_bounds__(kBlock) void k_brick_count(const int32_t* __restrict__ start, BrickGeom g,
                                                         int32_t* __restrict__ H, int32_t* __restrict__ O) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (b >= g.nbricks) return;
   const BrickShape s = brick_shape(b, g);
+  const int nh = s.h[0] * s.h[1] * s.h[2];
   int32_t h = 0, own = 0;
-  for (int hz = 0; hz < s.h[2]; hz++)
-    for (int hy = 0; hy < s.h[1]; hy++)
-      for (int hx = 0; hx < s.h[0]; hx++) {
-        const int32_t c = halo_cell_id(s, g, hx, hy, hz);
-        const int32_t k = start[c + 1] - start[c];
-        h += k;
-        if (hx >= 1 && hx <= s.e[0] && hy >= 1 && hy <= s.e[1] && hz >= 1 && hz <= s.e[2]) own += k;
-      }
-  H[b] = h;
-  O[b] = own;
+  for (int i = lane; i < nh; i += 64) {
+    const int hx = i % s.h[0], hy = (i / s.h[0]) % s.h[1], hz = i / (s.h[0] * s.h[1]);
+    const int32_t c = halo_cell_id(s, g, hx, hy, hz);
+    const int32_t k = start[c + 1] - start[c];
+    h += k;
+    if (hx >= 1 && hx <= s.e[0] && hy >= 1 && hy <= s.e[1] && hz >= 1 && hz <= s.e[2]) own += k;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    h += __shfl_down(h, o, 64);
+    own += __shfl_down(own, o, 64);
+  }
+  if (lane == 0) {
+    H[b] = h;
+    O[b] = own;
+  }
 }
 
 // One workgroup per brick: slot prefix over the halo cells, the sorted
@@ -376,8 +416,11 @@ hipError_t launch_cell_ids(const float4* pos, int64_t n, const CellGeom& g, int3
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* zero, hipStream_t st) {
-  k_scan<<<1, 1024, 0, st>>>(in, n, out, zero);
+hipError_t launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* zero, int32_t* tmp, hipStream_t st) {
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  k_tile_sums<<<(unsigned)ntiles, kScanTile, 0, st>>>(in, n, tmp);
+  k_scan_sums<<<1, kScanTile, 0, st>>>(tmp, ntiles, out, n);
+  k_scan_tiles<<<(unsigned)ntiles, kScanTile, 0, st>>>(in, n, tmp, out, zero);
   return hipGetLastError();
 }
 
@@ -393,7 +436,7 @@ hipError_t launch_sort_cells(const int32_t* start, int64_t ncells, int32_t* perm
 }
 
 hipError_t launch_brick_count(const int32_t* start, const BrickGeom& g, int32_t* H, int32_t* O, hipStream_t st) {
-  k_brick_count<<<grid_of(g.nbricks, kBlock), kBlock, 0, st>>>(start, g, H, O);
+  k_brick_count<<<grid_of(g.nbricks, kBlock / 64), kBlock, 0, st>>>(start, g, H, O);
   return hipGetLastError();
 }
 
@@ -425,6 +468,13 @@ hipError_t launch_neighbor_ranks(const uint16_t* nbr, const int32_t* cnt, const 
                                  int32_t kmax, int32_t* nbr_out, int32_t* cnt_out, hipStream_t st) {
   k_neighbor_ranks<<<(unsigned)g.nbricks, kBlock, 0, st>>>(nbr, cnt, g, bi, kmax, nbr_out, cnt_out);
   return hipGetLastError();
+}
+
+void allow_build_lds(int bytes) {
+  const hipFuncAttribute A = hipFuncAttributeMaxDynamicSharedMemorySize;
+  (void)hipFuncSetAttribute((const void*)k_build_nbr<float>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_build_nbr<double>, A, bytes);
+  (void)hipGetLastError();
 }
 
 template <typename T>

@@ -99,31 +99,72 @@ __device__ __forceinline__ void write_out(const CvArgs<T>& a, int32_t rank, T gx
   if (!(isfinite(v.x) && isfinite(v.y) && isfinite(v.z))) atomicOr(a.err, kErrNonFinite);
 }
 
-// Sum of the per-workgroup partials by the last workgroup to finish; writes s.
+// Fixed-order sum of the per-workgroup partials, in one workgroup (its own
+// launch, so every partial is visible without fences); writes s.
 // TWO: part_b holds the coordination (scaled by 1/N), part_a the q6 count.
 // SCALE: one CV held in part_a that is scaled by 1/N (the coordination alone).
 template <typename T, bool TWO, bool SCALE>
-__device__ __forceinline__ void finish_sum(const CvArgs<T>& a, double* red, int32_t nblk) {
-  if (last_block_done(a.ticket, nblk)) {
-    double sa = 0.0, sb = 0.0;
-    for (int64_t i = threadIdx.x; i < (int64_t)nblk; i += blockDim.x) {
-      sa += load_agent(&a.part_a[i]);
-      if (TWO) sb += load_agent(&a.part_b[i]);
+__device__ __forceinline__ void finish_body(const CvArgs<T>& a) {
+  __shared__ double red[kBlock / 64];
+  const int32_t nblk = a.bg.blocks;
+  double sa = 0.0, sb = 0.0;
+  for (int32_t i = threadIdx.x; i < nblk; i += blockDim.x) {
+    sa += a.part_a[i];
+    if (TWO) sb += a.part_b[i];
+  }
+  sa = block_sum(sa, red);
+  if (TWO) sb = block_sum(sb, red);
+  if (threadIdx.x == 0) {
+    const double s0 = TWO ? sb * a.inv_n : (SCALE ? sa * a.inv_n : sa);
+    const double s1 = TWO ? sa : 0.0;
+    a.s_int[0] = s0;
+    if (a.s_out) a.s_out[0] = s0;
+    if (TWO) {
+      a.s_int[1] = s1;
+      if (a.s_out) a.s_out[1] = s1;
     }
-    sa = block_sum(sa, red);
-    if (TWO) sb = block_sum(sb, red);
-    if (threadIdx.x == 0) {
-      const double s0 = TWO ? sb * a.inv_n : (SCALE ? sa * a.inv_n : sa);
-      const double s1 = TWO ? sa : 0.0;
-      a.s_int[0] = s0;
-      if (a.s_out) a.s_out[0] = s0;
-      if (TWO) {
-        a.s_int[1] = s1;
-        if (a.s_out) a.s_out[1] = s1;
-      }
-      if (!isfinite(s0) || !isfinite(s1)) atomicOr(a.err, kErrNonFinite);
+    if (!isfinite(s0) || !isfinite(s1)) atomicOr(a.err, kErrNonFinite);
+  }
+}
+
+template <typename T, bool TWO, bool SCALE>
+__global__ __launch_bounds__(kBlock) void k_finish(CvArgs<T> a) {
+  finish_body<T, TWO, SCALE>(a);
+}
+
+template <typename T, bool TWO, bool SCALE>
+__global__ __launch_bounds__(kBlock) void k_finish_batch(const CvArgs<T>* __restrict__ tab) {
+  finish_body<T, TWO, SCALE>(tab[blockIdx.x]);
+}
+
+// Threads per atom: TPA adjacent lanes share one owned atom; lane part p
+// walks the atom's rows at entries p, p + TPA, ...  (the per-step cutoff rows
+// are stored as TPA interleaved sub-lists, one per part), and the parts'
+// partial sums are combined with xor shuffles (same result in every part).
+template <typename T>
+__device__ __forceinline__ T group_sum(T v, int TPA) {
+  if (TPA >= 2) v += __shfl_xor(v, 1, 64);
+  if (TPA >= 4) v += __shfl_xor(v, 2, 64);
+  return v;
+}
+
+// Walk n cutoff slots of one part, two records in flight: the next record is
+// fetched from LDS before the current one is used.
+template <typename T, class Body>
+__device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr, const T* rows,
+                                             const uint16_t* crow, int TPA, int32_t part, int32_t n, Body body) {
+  if (n <= 0) return;
+  vec4_t<T> pa, pb;
+  T va[16], vb[16];
+  fetch_rec(a, k, lr, rows, crow[(int64_t)part * k.O], pa, va);
+  for (int32_t j = 0; j < n; j += 2) {
+    const bool b_ok = j + 1 < n;
+    if (b_ok) fetch_rec(a, k, lr, rows, crow[(int64_t)((j + 1) * TPA + part) * k.O], pb, vb);
+    body(pa, va);
+    if (b_ok) {
+      if (j + 2 < n) fetch_rec(a, k, lr, rows, crow[(int64_t)((j + 2) * TPA + part) * k.O], pa, va);
+      body(pb, vb);
     }
-    release_ticket(a.ticket);
   }
 }
 
@@ -139,7 +180,9 @@ __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, in
   stage_pos(a, k, lp);
   __syncthreads();
   double cn_part = 0.0;
-  for (int32_t o = threadIdx.x; o < k.O; o += blockDim.x) {
+  const int TPA = a.bg.tpa;
+  const int32_t part = threadIdx.x & (TPA - 1);
+  for (int32_t o = threadIdx.x / TPA; o < k.O; o += blockDim.x / TPA) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     const vec4_t<T> pi = fetch_pos(a, k, lp, si);
@@ -151,13 +194,13 @@ __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, in
     for (int m = 0; m < 13; m++) Q[m] = T(0);
     T fsum = T(0), cnsum = T(0);
     int32_t nc = 0;
-    for (int32_t e = 0; e < c; e++) {
+    for (int32_t e = part; e < c; e += TPA) {
       const int32_t s = row[(int64_t)e * k.O];
       const vec4_t<T> pj = fetch_pos(a, k, lp, s);
       T dx, dy, dz;
       const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
       if (r2 < a.rc2) {
-        crow[(int64_t)nc * k.O] = (uint16_t)s;
+        crow[(int64_t)(nc * TPA + part) * k.O] = (uint16_t)s;
         nc++;
         const T rinv = g_rsqrt(r2);
         const T r = r2 * rinv;
@@ -174,30 +217,37 @@ __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, in
         }
       }
     }
-    a.ccnt[k.ob + o] = nc;
+    a.ccnt[(int64_t)(k.ob + o) * TPA + part] = nc;
     if (Q6) {
-      T qq = T(0);
 #pragma unroll
-      for (int m = 0; m < 13; m++) qq += Q[m] * Q[m];
-      const T qn = g_sqrt(qq);
-      const T inv = qn >= T(1e-12) ? T(1) / qn : T(0);
-      T rowv[16];
-#pragma unroll
-      for (int m = 0; m < 13; m++) rowv[m] = Q[m] * inv;
-      rowv[13] = qn;
-      rowv[14] = T(0);
-      rowv[15] = fsum;
-      store_row16(a.qrow + (int64_t)ri * 16, rowv);
+      for (int m = 0; m < 13; m++) Q[m] = group_sum(Q[m], TPA);
+      fsum = group_sum(fsum, TPA);
     }
-    if (CN) {
-      a.cn_atom[ri] = cnsum;
-      cn_part += (double)cnsum;
+    if (CN) cnsum = group_sum(cnsum, TPA);
+    if (part == 0) {
+      if (Q6) {
+        T qq = T(0);
+#pragma unroll
+        for (int m = 0; m < 13; m++) qq += Q[m] * Q[m];
+        const T qn = g_sqrt(qq);
+        const T inv = qn >= T(1e-12) ? T(1) / qn : T(0);
+        T rowv[16];
+#pragma unroll
+        for (int m = 0; m < 13; m++) rowv[m] = Q[m] * inv;
+        rowv[13] = qn;
+        rowv[14] = T(0);
+        rowv[15] = fsum;
+        store_row16(a.qrow + (int64_t)ri * 16, rowv);
+      }
+      if (CN) {
+        a.cn_atom[ri] = cnsum;
+        cn_part += (double)cnsum;
+      }
     }
   }
   if (CN) {
     const double b = block_sum(cn_part, red);
-    if (threadIdx.x == 0) store_agent(Q6 ? &a.part_b[blk] : &a.part_a[blk], b);
-    if (!Q6) finish_sum<T, false, true>(a, red, nblk);
+    if (threadIdx.x == 0) (Q6 ? a.part_b : a.part_a)[blk] = b;
   }
 }
 
@@ -213,20 +263,18 @@ __device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, in
   stage_rows(a, k, a.qrow, lr);
   __syncthreads();
   double c_part = 0.0;
-  for (int32_t o = threadIdx.x; o < k.O; o += blockDim.x) {
+  const int TPA = a.bg.tpa;
+  const int32_t part = threadIdx.x & (TPA - 1);
+  for (int32_t o = threadIdx.x / TPA; o < k.O; o += blockDim.x / TPA) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     vec4_t<T> pi;
     T qi[16];
     fetch_rec(a, k, lr, a.qrow, si, pi, qi);
-    const int32_t nc = a.ccnt[k.ob + o];
+    const int32_t nc = a.ccnt[(int64_t)(k.ob + o) * TPA + part];
     const uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
     T nbond = T(0);
-    for (int32_t e = 0; e < nc; e++) {
-      const int32_t s = crow[(int64_t)e * k.O];
-      vec4_t<T> pj;
-      T qj[16];
-      fetch_rec(a, k, lr, a.qrow, s, pj, qj);
+    walk_records(a, k, lr, a.qrow, crow, TPA, part, nc, [&](const vec4_t<T>& pj, const T* qj) {
       T dx, dy, dz;
       const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
       const T r = g_sqrt(r2);
@@ -236,16 +284,18 @@ __device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, in
 #pragma unroll
       for (int m = 0; m < 13; m++) d += qi[m] * qj[m];
       nbond += f * logistic((d - a.bond_d0) * a.inv_bond_w);
+    });
+    nbond = group_sum(nbond, TPA);
+    if (part == 0) {
+      const T cc = logistic((nbond - a.count_n0) * a.inv_count_w);
+      const T dc = cc * (T(1) - cc) * a.inv_count_w;
+      a.qrow[(int64_t)ri * 16 + 14] = dc;
+      a.nb[ri] = nbond;
+      c_part += (double)cc;
     }
-    const T cc = logistic((nbond - a.count_n0) * a.inv_count_w);
-    const T dc = cc * (T(1) - cc) * a.inv_count_w;
-    a.qrow[(int64_t)ri * 16 + 14] = dc;
-    a.nb[ri] = nbond;
-    c_part += (double)cc;
   }
   const double b = block_sum(c_part, red);
-  if (threadIdx.x == 0) store_agent(&a.part_a[blk], b);
-  finish_sum<T, CN, false>(a, red, nblk);
+  if (threadIdx.x == 0) a.part_a[blk] = b;
 }
 
 // --------------------------------------------------------------------------
@@ -258,24 +308,22 @@ __device__ __forceinline__ void pass3_body(const CvArgs<T>& a, int64_t brick, in
   const Brick k = brick_begin(a, brick);
   stage_rows(a, k, a.qrow, lr);
   __syncthreads();
-  for (int32_t o = threadIdx.x; o < k.O; o += blockDim.x) {
+  const int TPA = a.bg.tpa;
+  const int32_t part = threadIdx.x & (TPA - 1);
+  for (int32_t o = threadIdx.x / TPA; o < k.O; o += blockDim.x / TPA) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     vec4_t<T> pi;
     T qi[16];
     fetch_rec(a, k, lr, a.qrow, si, pi, qi);
     const T dci = qi[14];
-    const int32_t nc = a.ccnt[k.ob + o];
+    const int32_t nc = a.ccnt[(int64_t)(k.ob + o) * TPA + part];
     const uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
     T h[13];
 #pragma unroll
     for (int m = 0; m < 13; m++) h[m] = T(0);
     T rx = T(0), ry = T(0), rz = T(0);
-    for (int32_t e = 0; e < nc; e++) {
-      const int32_t s = crow[(int64_t)e * k.O];
-      vec4_t<T> pj;
-      T qj[16];
-      fetch_rec(a, k, lr, a.qrow, s, pj, qj);
+    walk_records(a, k, lr, a.qrow, crow, TPA, part, nc, [&](const vec4_t<T>& pj, const T* qj) {
       T dx, dy, dz;
       const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
@@ -296,24 +344,31 @@ __device__ __forceinline__ void pass3_body(const CvArgs<T>& a, int64_t brick, in
         ry += rad * dy;
         rz += rad * dz;
       }
+    });
+#pragma unroll
+    for (int m = 0; m < 13; m++) h[m] = group_sum(h[m], TPA);
+    rx = group_sum(rx, TPA);
+    ry = group_sum(ry, TPA);
+    rz = group_sum(rz, TPA);
+    if (part == 0) {
+      T proj = T(0);
+#pragma unroll
+      for (int m = 0; m < 13; m++) proj += qi[m] * h[m];
+      const T inv = qi[13] >= T(1e-12) ? T(1) / qi[13] : T(0);
+      T g[16];
+#pragma unroll
+      for (int m = 0; m < 13; m++) g[m] = (h[m] - proj * qi[m]) * inv;
+      g[13] = dci;
+      g[14] = T(0);
+      g[15] = T(0);
+      store_row16(a.grow + (int64_t)ri * 16, g);
+      vec4_t<T> fr;
+      fr.x = rx;
+      fr.y = ry;
+      fr.z = rz;
+      fr.w = T(0);
+      a.frad[ri] = fr;
     }
-    T proj = T(0);
-#pragma unroll
-    for (int m = 0; m < 13; m++) proj += qi[m] * h[m];
-    const T inv = qi[13] >= T(1e-12) ? T(1) / qi[13] : T(0);
-    T g[16];
-#pragma unroll
-    for (int m = 0; m < 13; m++) g[m] = (h[m] - proj * qi[m]) * inv;
-    g[13] = dci;
-    g[14] = T(0);
-    g[15] = T(0);
-    store_row16(a.grow + (int64_t)ri * 16, g);
-    vec4_t<T> fr;
-    fr.x = rx;
-    fr.y = ry;
-    fr.z = rz;
-    fr.w = T(0);
-    a.frad[ri] = fr;
   }
 }
 
@@ -330,21 +385,19 @@ __device__ __forceinline__ void pass4_body(const CvArgs<T>& a, int64_t brick, in
   __syncthreads();
   const T seed_q = a.seed ? (T)a.seed[a.dims - 1] : T(1);
   const T seed_cn = (CN && a.seed) ? (T)(a.seed[0] * 2.0 * a.inv_n) : T(0);
-  for (int32_t o = threadIdx.x; o < k.O; o += blockDim.x) {
+  const int TPA = a.bg.tpa;
+  const int32_t part = threadIdx.x & (TPA - 1);
+  for (int32_t o = threadIdx.x / TPA; o < k.O; o += blockDim.x / TPA) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     vec4_t<T> pi;
     T gi[16];
     fetch_rec(a, k, lr, a.grow, si, pi, gi);
-    const int32_t nc = a.ccnt[k.ob + o];
+    const int32_t nc = a.ccnt[(int64_t)(k.ob + o) * TPA + part];
     const uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
     T ax = T(0), ay = T(0), az = T(0);
     T cx = T(0), cy = T(0), cz = T(0);
-    for (int32_t e = 0; e < nc; e++) {
-      const int32_t s = crow[(int64_t)e * k.O];
-      vec4_t<T> pj;
-      T gj[16];
-      fetch_rec(a, k, lr, a.grow, s, pj, gj);
+    walk_records(a, k, lr, a.grow, crow, TPA, part, nc, [&](const vec4_t<T>& pj, const T* gj) {
       T dx, dy, dz;
       const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
@@ -380,12 +433,22 @@ __device__ __forceinline__ void pass4_body(const CvArgs<T>& a, int64_t brick, in
         cy += swp * uy;
         cz += swp * uz;
       }
+    });
+    ax = group_sum(ax, TPA);
+    ay = group_sum(ay, TPA);
+    az = group_sum(az, TPA);
+    if (CN) {
+      cx = group_sum(cx, TPA);
+      cy = group_sum(cy, TPA);
+      cz = group_sum(cz, TPA);
     }
-    const vec4_t<T> fr = a.frad[ri];
-    ax += fr.x;
-    ay += fr.y;
-    az += fr.z;
-    write_out(a, ri, -(seed_q * ax + seed_cn * cx), -(seed_q * ay + seed_cn * cy), -(seed_q * az + seed_cn * cz));
+    if (part == 0) {
+      const vec4_t<T> fr = a.frad[ri];
+      ax += fr.x;
+      ay += fr.y;
+      az += fr.z;
+      write_out(a, ri, -(seed_q * ax + seed_cn * cx), -(seed_q * ay + seed_cn * cy), -(seed_q * az + seed_cn * cz));
+    }
   }
 }
 
@@ -400,15 +463,17 @@ __device__ __forceinline__ void cn_force_body(const CvArgs<T>& a, int64_t brick,
   stage_pos(a, k, lp);
   __syncthreads();
   const T seed = (T)((a.seed ? a.seed[0] : 1.0) * 2.0 * a.inv_n);
-  for (int32_t o = threadIdx.x; o < k.O; o += blockDim.x) {
+  const int TPA = a.bg.tpa;
+  const int32_t part = threadIdx.x & (TPA - 1);
+  for (int32_t o = threadIdx.x / TPA; o < k.O; o += blockDim.x / TPA) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     const vec4_t<T> pi = fetch_pos(a, k, lp, si);
-    const int32_t nc = a.ccnt[k.ob + o];
+    const int32_t nc = a.ccnt[(int64_t)(k.ob + o) * TPA + part];
     const uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
     T cx = T(0), cy = T(0), cz = T(0);
-    for (int32_t e = 0; e < nc; e++) {
-      const vec4_t<T> pj = fetch_pos(a, k, lp, crow[(int64_t)e * k.O]);
+    for (int32_t j = 0; j < nc; j++) {
+      const vec4_t<T> pj = fetch_pos(a, k, lp, crow[(int64_t)(j * TPA + part) * k.O]);
       T dx, dy, dz;
       const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
@@ -421,17 +486,19 @@ __device__ __forceinline__ void cn_force_body(const CvArgs<T>& a, int64_t brick,
       cy += swp * dy;
       cz += swp * dz;
     }
-    write_out(a, ri, -seed * cx, -seed * cy, -seed * cz);
+    cx = group_sum(cx, TPA);
+    cy = group_sum(cy, TPA);
+    cz = group_sum(cz, TPA);
+    if (part == 0) write_out(a, ri, -seed * cx, -seed * cy, -seed * cz);
   }
 }
-
 
 // --------------------------------------------------------------------------
 // Kernels: one context (its bricks remapped per XCD), or a batch of contexts
 // ("walkers") in one launch.  In a batch, workgroup g (after the same XCD
 // remap over the whole grid) belongs to the walker w with
 // blk_start[w] <= g < blk_start[w+1] and handles that walker's brick
-// g - blk_start[w]; every walker keeps its own tickets and partial sums, so
+// g - blk_start[w]; every walker keeps its own partial sums, so
 // its results are bitwise the same alone and in a batch.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ int32_t find_walker(const int32_t* __restrict__ blk_start, int32_t W, int64_t g) {
@@ -504,9 +571,11 @@ hipError_t launch_q6_forward(const CvArgs<T>& a, bool with_cn, hipStream_t st) {
   if (with_cn) {
     k_pass1<T, true, true><<<g, kBlock, lds_bytes(a, false), st>>>(a);
     k_pass2<T, true><<<g, kBlock, lds_bytes(a, true), st>>>(a);
+    k_finish<T, true, false><<<1, kBlock, 0, st>>>(a);
   } else {
     k_pass1<T, false, true><<<g, kBlock, lds_bytes(a, false), st>>>(a);
     k_pass2<T, false><<<g, kBlock, lds_bytes(a, true), st>>>(a);
+    k_finish<T, false, false><<<1, kBlock, 0, st>>>(a);
   }
   return hipGetLastError();
 }
@@ -530,6 +599,7 @@ hipError_t launch_q6_force(const CvArgs<T>& a, bool with_cn, hipStream_t st) {
 template <typename T>
 hipError_t launch_cn_forward(const CvArgs<T>& a, hipStream_t st) {
   k_pass1<T, true, false><<<(unsigned)a.bg.blocks, kBlock, lds_bytes(a, false), st>>>(a);
+  k_finish<T, false, true><<<1, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -559,10 +629,13 @@ hipError_t launch_pass_batch(int pass, bool with_cn, bool fp_rows, const CvArgs<
         k_pass1_batch<T, false, true><<<g, kBlock, lds_pos, st>>>(tab, blk_start, W);
       break;
     case 2:
-      if (with_cn)
+      if (with_cn) {
         k_pass2_batch<T, true><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
-      else
+        k_finish_batch<T, true, false><<<(unsigned)W, kBlock, 0, st>>>(tab);
+      } else {
         k_pass2_batch<T, false><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
+        k_finish_batch<T, false, false><<<(unsigned)W, kBlock, 0, st>>>(tab);
+      }
       break;
     case 3:
       k_pass3_batch<T><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
@@ -575,6 +648,7 @@ hipError_t launch_pass_batch(int pass, bool with_cn, bool fp_rows, const CvArgs<
       break;
     case 5:  // coordination alone: forward
       k_pass1_batch<T, true, false><<<g, kBlock, lds_pos, st>>>(tab, blk_start, W);
+      k_finish_batch<T, false, true><<<(unsigned)W, kBlock, 0, st>>>(tab);
       break;
     case 6:  // coordination alone: forces
       k_cn_force_batch<T><<<g, kBlock, lds_pos, st>>>(tab, blk_start, W);
@@ -583,6 +657,37 @@ hipError_t launch_pass_batch(int pass, bool with_cn, bool fp_rows, const CvArgs<
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// Allow dynamic LDS up to `bytes` for every staging kernel (ignored where the
+// runtime needs no opt-in).
+template <typename T>
+static void allow_lds_t(int bytes) {
+  const hipFuncAttribute A = hipFuncAttributeMaxDynamicSharedMemorySize;
+  (void)hipFuncSetAttribute((const void*)k_pass1<T, true, true>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass1<T, false, true>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass1<T, true, false>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass2<T, true>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass2<T, false>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass3<T>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass4<T, true>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass4<T, false>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_cn_force<T>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass1_batch<T, true, true>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass1_batch<T, false, true>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass1_batch<T, true, false>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass2_batch<T, true>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass2_batch<T, false>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass3_batch<T>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass4_batch<T, true>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_pass4_batch<T, false>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_cn_force_batch<T>, A, bytes);
+}
+
+void allow_cv_lds(int bytes) {
+  allow_lds_t<float>(bytes);
+  allow_lds_t<double>(bytes);
+  (void)hipGetLastError();
 }
 
 #define GM_INSTANTIATE(T)                                                                              \

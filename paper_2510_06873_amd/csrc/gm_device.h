@@ -55,32 +55,6 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return r;
 }
 
-__device__ __forceinline__ void store_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_agent(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// True in every thread of the workgroup that finishes last among the nblk
-// workgroups sharing this ticket (all threads call).
-__device__ __forceinline__ bool last_block_done(unsigned* ticket, int32_t nblk) {
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(ticket, 1u);
-    is_last = (prev == (unsigned)nblk - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last != 0;
-}
-
-__device__ __forceinline__ void release_ticket(unsigned* ticket) {
-  if (threadIdx.x == 0) atomicExch(ticket, 0u);
-}
-
 // Minimum image in T: d - L*rint(d/L), with L split in high and low parts so
 // that an FP32 box length does not bias wrapped pairs.
 template <typename T>

@@ -62,6 +62,7 @@ struct BrickGeom {
   int32_t nbricks;
   int32_t cap;     // halo slots staged in LDS (slots beyond are read from global memory)
   int32_t blocks;  // workgroups launched per brick pass (nbricks rounded up to the XCD count)
+  int32_t tpa;     // threads per owned atom (1, 2 or 4): lanes that split one atom's rows
 };
 
 struct BrickIndex {
@@ -101,7 +102,6 @@ struct CvArgs {
   T* cn_atom;       // [N] per-atom coordination sums
   double* part_a;   // per-workgroup FP64 partial sums (count / coordination)
   double* part_b;
-  unsigned* ticket;
   double* s_out;    // caller's s (dev), may be NULL
   double* s_int;    // library copy of s
   int32_t* err;
@@ -122,7 +122,6 @@ struct BiasArgs {
   double invs2[2];         // 1 / sigma_d^2
   double w0, wt_scale;     // wt_scale = 1/(kBT (gamma-1)), 0 for plain metad
   double* part;            // [blocks][3]
-  unsigned* ticket;
   double* V_out;
   double* dV_out;
   int32_t* err;
@@ -140,7 +139,8 @@ struct GatherArgs {
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 hipError_t launch_cell_ids(const float4* pos, int64_t n, const CellGeom& g, int32_t* cell,
                            int32_t* count, int32_t* err, hipStream_t st);
-hipError_t launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* zero, hipStream_t st);
+// tmp: device int32[(n + 1023)/1024] scratch for the tile sums
+hipError_t launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* zero, int32_t* tmp, hipStream_t st);
 hipError_t launch_scatter(const int32_t* cell, int64_t n, const int32_t* start, int32_t* fill,
                           int32_t* perm, hipStream_t st);
 hipError_t launch_sort_cells(const int32_t* start, int64_t ncells, int32_t* perm, hipStream_t st);
@@ -173,6 +173,9 @@ hipError_t launch_neighbor_ranks(const uint16_t* nbr, const int32_t* cnt, const 
                                  const BrickIndex& bi, int32_t kmax, int32_t* nbr_out, int32_t* cnt_out,
                                  hipStream_t st);
 hipError_t launch_bias(const BiasArgs& a, int blocks, hipStream_t st);
+// Opt the staging kernels in to `bytes` of dynamic LDS.
+void allow_cv_lds(int bytes);
+void allow_build_lds(int bytes);
 // Batched launches over many contexts ("walkers"): tab[W] device tables,
 // blk_start[W+1] device prefix of the workgroups of each walker.
 template <typename T>
@@ -191,7 +194,6 @@ template <typename T>
 constexpr int slot_bytes(bool with_row) {
   return (int)sizeof(vec4_t<T>) * (with_row ? 5 : 1);
 }
-constexpr int kLdsBudget = 63 * 1024;  // dynamic LDS per workgroup for the halo (static arrays use the rest of 64 KB)
 
 // Number of blocks launched for n atoms: a multiple of the XCD count.
 inline int64_t atom_blocks(int64_t n) {

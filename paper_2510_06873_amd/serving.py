@@ -1,0 +1,218 @@
+"""Continuous batching of bias-force requests from many independent walkers.
+
+A request is one walker (its own atoms, box, CV kind and resident hill
+history) that needs ``steps`` MD steps of the bias pipeline, with a neighbour
+rebuild and a hill deposit every ``pace`` steps of its own.  The server keeps
+each admitted walker's lists and hills on the device, admits new requests at
+tick boundaries while a slot and HBM budget are free, and advances every
+active walker by one step per tick with one launch per pass for all of them
+(``Batch``).  Finished walkers free their slot and memory for the queue.
+
+``serve_sequential`` runs the same requests one after another with the
+per-walker calls, the baseline the batched loop is measured against.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from .binding import Batch, Params, Pipeline
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float              # seconds after the start of the run
+    pos: np.ndarray             # (N, 4) float32 positions
+    box: np.ndarray             # (3,) float64
+    params: Params
+    centres: np.ndarray         # (K, dims) hill centres
+    heights: np.ndarray         # (K,) hill heights
+    forces: np.ndarray          # (N, 4) external forces (float32)
+    steps: int = 100
+    pace: int = 10
+
+    @property
+    def n(self) -> int:
+        return self.pos.shape[0]
+
+
+@dataclass
+class Result:
+    rid: int
+    n: int
+    arrival: float
+    admitted: float
+    finished: float
+    s: np.ndarray
+    V: float
+    forces: Optional[np.ndarray] = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def device_bytes(req: Request) -> int:
+    """Device memory a walker holds while admitted (library buffers plus its
+    resident positions and forces), from the sizes the library allocates."""
+    p = req.params
+    n = req.n
+    t = 8 if p.precision == 1 else 4
+    kmax = (max(p.max_neighbors, 4) + 3) // 4 * 4
+    per_atom = 16 + 16 * t                      # caller positions + forces
+    per_atom += 4 * 7 + 2 * 2 * kmax            # cell, perm, owned tables, counts, neighbour + cutoff rows
+    per_atom += 4 * t + 2 * t                   # sorted positions, bond count, coordination
+    if p.cv_kind != 1:
+        per_atom += 16 * t * 2 + 4 * t          # q-hat and adjoint rows, taper term
+    per_atom += 4 * 8                           # halo slot table (bounded by 8 halo copies per atom)
+    hills = p.hill_capacity * (p.dims + 1) * 8
+    return int(n * per_atom + hills + (1 << 20))
+
+
+class _Walker:
+    def __init__(self, req: Request, dev, torch, stream):
+        self.req = req
+        self.pipe = Pipeline(req.n, req.params, stream=stream)
+        self.pos = torch.from_numpy(req.pos).to(dev)
+        self.F = torch.from_numpy(req.forces).to(device=dev, dtype=self.pipe.fdtype)
+        self.pipe.hills_set(req.centres, req.heights)
+        self.done = 0
+        self.bytes = device_bytes(req)
+
+    def close(self):
+        self.pipe.close()
+
+
+def _finish(w: _Walker, t: float, admitted: float, keep_forces: bool) -> Result:
+    s = w.pipe.s.cpu().numpy().copy() if w.pipe.s is not None else None
+    return Result(w.req.rid, w.req.n, w.req.arrival, admitted, t, s, float(w.pipe.V.item()),
+                  w.F.cpu().numpy().copy() if keep_forces else None)
+
+
+def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64, keep_forces: bool = False,
+                  device=None):
+    """Run the requests with continuous batching; returns (results, stats)."""
+    import torch
+
+    dev = device or torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    pending = sorted(requests, key=lambda r: r.arrival)
+    active: List[_Walker] = []
+    admitted_at = {}
+    results: List[Result] = []
+    used = 0
+    peak_used = 0
+    ticks = 0
+    batch = None
+    members = None
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        while pending or active:
+            now = time.perf_counter() - t0
+            while (pending and pending[0].arrival <= now and len(active) < max_slots
+                   and used + device_bytes(pending[0]) <= hbm_budget):
+                req = pending.pop(0)
+                w = _Walker(req, dev, torch, stream)
+                w.pipe.build_neighbors_checked(w.pos, req.box)
+                active.append(w)
+                used += w.bytes
+                peak_used = max(peak_used, used)
+                admitted_at[req.rid] = time.perf_counter() - t0
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
+                continue
+            ids = tuple(w.req.rid for w in active)
+            if ids != members:
+                if batch is not None:
+                    batch.close()
+                batch = Batch([w.pipe for w in active], [w.pos for w in active], [w.F for w in active],
+                              stream=stream)
+                members = ids
+            for w in active:  # rebuilds due at this walker's own step count
+                if w.done > 0 and w.done % w.req.pace == 0:
+                    w.pipe.build_neighbors(w.pos, w.req.box)
+            batch.step()
+            ticks += 1
+            for w in active:
+                w.done += 1
+                if w.done % w.req.pace == 0:
+                    w.pipe.deposit_hill()
+            finished = [w for w in active if w.done >= w.req.steps]
+            if finished:
+                s, V = batch.values()
+                for w in active:
+                    k = members.index(w.req.rid)
+                    w.pipe.s = s[k, :w.pipe.dims].clone()
+                    w.pipe.V = V[k:k + 1].clone()
+                stream.synchronize()
+                t = time.perf_counter() - t0
+                for w in finished:
+                    w.pipe.check()
+                    results.append(_finish(w, t, admitted_at[w.req.rid], keep_forces))
+                    used -= w.bytes
+                active = [w for w in active if w.done < w.req.steps]
+                batch.close()
+                batch = None
+                members = None
+                for w in finished:
+                    w.close()
+        stream.synchronize()
+    wall = time.perf_counter() - t0
+    return results, _stats(results, wall, ticks=ticks, peak_bytes=peak_used)
+
+
+def serve_sequential(requests: List[Request], keep_forces: bool = False, device=None):
+    """Baseline: one walker at a time, per-walker launches, arrival order."""
+    import torch
+
+    dev = device or torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    results = []
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for req in sorted(requests, key=lambda r: r.arrival):
+            now = time.perf_counter() - t0
+            if req.arrival > now:
+                time.sleep(req.arrival - now)
+            admitted = time.perf_counter() - t0
+            w = _Walker(req, dev, torch, stream)
+            w.pipe.build_neighbors_checked(w.pos, req.box)
+            for step in range(req.steps):
+                if step > 0 and step % req.pace == 0:
+                    w.pipe.build_neighbors(w.pos, req.box)
+                w.pipe.step(w.pos, w.F)
+                if (step + 1) % req.pace == 0:
+                    w.pipe.deposit_hill()
+            stream.synchronize()
+            w.pipe.check()
+            results.append(_finish(w, time.perf_counter() - t0, admitted, keep_forces))
+            w.close()
+    wall = time.perf_counter() - t0
+    return results, _stats(results, wall)
+
+
+def _stats(results: List[Result], wall: float, **extra) -> dict:
+    lat = np.array([r.latency for r in results]) * 1e3
+    out = {
+        "requests": len(results),
+        "wall_s": wall,
+        "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+        "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+        "mean_ms": float(lat.mean()) if len(lat) else None,
+        "atoms": int(sum(r.n for r in results)),
+    }
+    out.update(extra)
+    return out
+
+
+def summarize(results: List[Result], stats: dict, steps: int) -> dict:
+    """Aggregate atom-steps/s over the makespan plus the latency percentiles."""
+    total = sum(r.n for r in results) * steps
+    d = dict(stats)
+    d["atom_steps_per_s"] = total / stats["wall_s"] if stats["wall_s"] > 0 else None
+    return d

@@ -256,3 +256,63 @@ def structure(spec: dict):
 def small_wurtzite_slab(nx=4, ny=3, nz=6, seed=21, jitter=0.05):
     """A small slab (a few hundred atoms) with crystal and random halves."""
     return wurtzite_slab(nx, ny, nz, jitter=jitter, seed=seed)
+
+
+# --------------------------------------------------------------------------
+# Serving: many uneven walkers with Poisson arrivals
+# --------------------------------------------------------------------------
+WALKER_CV = {
+    # (structure, cv): CV parameters
+    ("fcc", "coord"): dict(cv="coord", r_c=6.0, skin=0.5, cn_r0=3.0, taper=0.2, sigma=[0.1], kmax=128),
+    ("fcc", "q6"): dict(cv="q6", r_c=3.2, skin=0.4, cn_r0=2.5, taper=0.2, sigma=[20.0], kmax=48),
+    ("wz", "coord"): dict(cv="coord", r_c=3.6, skin=0.4, cn_r0=2.5, taper=0.2, sigma=[0.1], kmax=48),
+    ("wz", "q6"): dict(cv="q6", r_c=3.6, skin=0.4, cn_r0=2.5, taper=0.2, sigma=[20.0], kmax=48),
+}
+
+
+def walker_structure(kind: str, n_target: int, seed: int):
+    """Near-cubic crystal of about n_target atoms with N(0, jitter) noise
+    (fcc a = 3.615, jitter 0.1; wurtzite jitter 0.05), large enough for 3 cells
+    of the walker's neighbour cutoff on every axis."""
+    rng = np.random.default_rng(seed)
+    if kind == "fcc":
+        n = max(6, int(round((n_target / 4) ** (1 / 3))))
+        ideal, box = fcc_ideal(n, 3.615)
+        jit = 0.1
+        species = np.zeros(ideal.shape[0], np.int32)
+    else:
+        side = (n_target / 0.08745) ** (1 / 3)
+        nx = max(4, int(round(side / 3.19)))
+        ny = max(3, int(round(side / (3.19 * np.sqrt(3)))))
+        nz = max(3, int(round(side / 5.19)))
+        ideal, species, box = wurtzite_ideal(nx, ny, nz)
+        jit = 0.05
+    pos = ideal + rng.normal(0.0, jit, ideal.shape)
+    return _wrap_f32(pos, box), species, box
+
+
+def serving_requests(count=256, n_lo=1000, n_hi=200000, rate=2000.0, k_lo=100, k_hi=20000, seed=7):
+    """Walker requests: atom counts log-uniform in [n_lo, n_hi], fcc or wurtzite
+    and coordination or q6 count with equal odds, hill histories log-uniform in
+    [k_lo, k_hi] (centres around the range the CV can take, heights in
+    [0.2, 1] w0), Poisson arrival times at `rate` per second.  Plain arrays and
+    parameter dicts; the caller turns them into library objects."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, count))
+    out = []
+    for i in range(count):
+        n_t = int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        kind = "fcc" if rng.random() < 0.5 else "wz"
+        cv = "coord" if rng.random() < 0.5 else "q6"
+        pos, species, box = walker_structure(kind, n_t, seed=1000 + i)
+        n = pos.shape[0]
+        prm = dict(WALKER_CV[(kind, cv)])
+        k = int(np.exp(rng.uniform(np.log(k_lo), np.log(k_hi))))
+        hi = (14.0 if kind == "fcc" else 8.0) if cv == "coord" else 1.05 * n
+        centres = rng.uniform(0.0, hi, (k, 1))
+        w0 = W0_EV
+        heights = w0 * rng.uniform(0.2, 1.0, k)
+        forces = external_forces(n, seed=5000 + i)
+        out.append(dict(rid=i, arrival=float(t[i]), pos=as_float4(pos, species), box=box, kind=kind, params=prm,
+                        centres=centres, heights=heights, forces=forces, w0=w0, kBT=KBT_EV))
+    return out
