@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--serving", action="store_true",
                     help="also run the walker-serving workload (256 requests, continuous batching vs sequential)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving workload")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time candidate brick shapes / LDS budgets on this system first and use the fastest")
+    ap.add_argument("--brick", default=None, help="force the brick shape, e.g. 3x3x4")
+    ap.add_argument("--lds-kb", type=int, default=0, help="LDS staging budget per workgroup (KiB)")
     return ap.parse_args()
 
 
@@ -55,7 +59,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def setup(wl_name):
+def setup(wl_name, args=None):
     import torch
 
     import workloads as W
@@ -70,6 +74,18 @@ def setup(wl_name):
                  bond_w=wl.get("bond_w", 0.02), count_n0=wl.get("count_n0", 5.5), count_w=wl.get("count_w", 0.25),
                  sigma=wl["sigma"], w0=wl["w0"], gamma=wl["gamma"], kBT=wl["kBT"],
                  hill_capacity=wl["hills"]["k"] + 1024, max_neighbors=48)
+    if args is not None and args.brick:
+        prm.brick = tuple(int(x) for x in args.brick.split("x"))
+    if args is not None and args.lds_kb:
+        prm.lds_kb = args.lds_kb
+    tuned = None
+    if args is not None and args.autotune:
+        from paper_2510_06873_amd.autotune import autotune
+
+        p4 = torch.from_numpy(W.as_float4(d["pos"], d["species"])).to(torch.device("cuda", 0))
+        prm, timings = autotune(p4, d["box"], prm, steps=3)
+        tuned = {"brick": list(prm.brick), "lds_kb": prm.lds_kb, "ms_per_md_step": timings}
+        log(f"[bench] autotune: {tuned}")
     stream = torch.cuda.Stream()
     dev = torch.device("cuda", 0)
     with torch.cuda.stream(stream):
@@ -94,7 +110,7 @@ def setup(wl_name):
         stream.synchronize()
         log(f"[bench] {wl_name}: N={n}, hills deposited: {cen.shape[0]} in {time.time() - t:.1f}s")
         pipe.check()
-    return dict(wl=wl, d=d, n=n, pipe=pipe, pos4=pos4, F=F, stream=stream, cen=cen, box=d["box"])
+    return dict(wl=wl, d=d, n=n, pipe=pipe, pos4=pos4, F=F, stream=stream, cen=cen, box=d["box"], tuned=tuned)
 
 
 def window(S, ev=None):
@@ -209,7 +225,7 @@ def main():
     if args.serving_only:
         print(json.dumps({"serving": serving(args)}), flush=True)
         return
-    S = setup(args.workload)
+    S = setup(args.workload, args)
     n = S["n"]
     stream = S["stream"]
     graph = None
@@ -295,7 +311,7 @@ def main():
                                f"window = 1 rebuild + 10 x (cv_forward, bias_eval, cv_backward, "
                                f"apply_bias_forces) + 1 deposit",
                    "atoms": n, "md_steps_per_step": MD_STEPS_PER_WINDOW, "graph": bool(args.graph),
-                   "neighbor_entries": int(total_entries)},
+                   "neighbor_entries": int(total_entries), "autotuned": S["tuned"]},
         "per_call_us": {k: round(v, 2) for k, v in per_call_us.items()},
         "roofline": roofline,
         "step_hbm": {"achieved_gbs": round(step_hbm, 1), "peak_gbs": HBM_PEAK_GBS,

@@ -175,6 +175,7 @@ class Pipeline:
         self.V = torch.zeros(1, dtype=torch.float64, device=dev)
         self.dVds = torch.zeros(self.dims, dtype=torch.float64, device=dev)
         self.generation = 0  # number of cv_forward calls (autograd checks it)
+        self._begin()  # the context stream must see the zero-filled buffers
 
     def close(self):
         if getattr(self, "h", None):
@@ -291,6 +292,21 @@ class Pipeline:
             rc = self.status(True)
         _check(rc, "gm_build_neighbors")
 
+    def _begin(self):
+        """Order the context stream after the caller's stream (for tensors the
+        binding allocates on the caller's stream and the library writes)."""
+        cur = self.torch.cuda.current_stream()
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _end(self, *tensors):
+        """Make the caller's stream wait for the library's writes."""
+        cur = self.torch.cuda.current_stream()
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+            for t in tensors:
+                t.record_stream(self.stream)
+
     def cell_list(self):
         torch = self.torch
         perm = torch.empty(self.n, dtype=torch.int32, device=self.s.device)
@@ -298,7 +314,9 @@ class Pipeline:
         _check(_lib.gm_copy_cell_list(self.h, _ptr(perm), None, nc), "gm_copy_cell_list")
         ncells = nc[0] * nc[1] * nc[2]
         start = torch.empty(ncells + 1, dtype=torch.int32, device=self.s.device)
+        self._begin()
         _check(_lib.gm_copy_cell_list(self.h, _ptr(perm), _ptr(start), nc), "gm_copy_cell_list")
+        self._end(perm, start)
         return (nc[0], nc[1], nc[2]), perm, start
 
     def neighbor_lists(self):
@@ -307,13 +325,17 @@ class Pipeline:
         _check(_lib.gm_copy_neighbors(self.h, None, None, C.byref(w)), "gm_copy_neighbors")
         nbr = torch.empty((self.n, w.value), dtype=torch.int32, device=self.s.device)
         cnt = torch.empty(self.n, dtype=torch.int32, device=self.s.device)
+        self._begin()
         _check(_lib.gm_copy_neighbors(self.h, _ptr(nbr), _ptr(cnt), C.byref(w)), "gm_copy_neighbors")
+        self._end(nbr, cnt)
         return nbr, cnt
 
     def atom_values(self, what: int):
         out = self.torch.empty(self.n, dtype=self.torch.float64, device=self.s.device)
+        self._begin()
         _check(_lib.gm_atom_values(self.h, int(what), _ptr(out, self.n, self.torch.float64, "out")),
                "gm_atom_values")
+        self._end(out)
         return out
 
 
@@ -347,6 +369,9 @@ class Batch:
         dev = self.pos4[0].device
         self.s = torch.zeros((w, 2), dtype=torch.float64, device=dev)
         self.V = torch.zeros(w, dtype=torch.float64, device=dev)
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
 
     def close(self):
         if getattr(self, "h", None):

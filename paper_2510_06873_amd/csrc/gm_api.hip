@@ -177,6 +177,7 @@ CvArgs<T> make_args(gm_ctx* c) {
     a.yc = c->ycf;
   else
     a.yc = c->ycd;
+  a.ycd = c->ycd;
   a.qrow = reinterpret_cast<T*>(c->qrow);
   a.grow = reinterpret_cast<T*>(c->grow);
   a.frad = reinterpret_cast<vec4_t<T>*>(c->frad);
@@ -233,6 +234,7 @@ void choose_bricks(gm_ctx* c, const int32_t nc[3]) {
   g.cap = cap;
   g.blocks = (g.nbricks + kXcd - 1) / kXcd * kXcd;
   g.tpa = best_tpa;
+  g.kpart = ((c->kmax + best_tpa - 1) / best_tpa + 7) / 8 * 8;
 }
 
 // Upper bound of the total halo slots: each cell is counted once per brick
@@ -414,8 +416,8 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   if (rc == GM_OK) rc = dalloc(&c->owned_hcell, n * 4);
   if (rc == GM_OK) rc = dalloc(&c->cnt, n * 4);
   if (rc == GM_OK) rc = dalloc(&c->ccnt, n * 4 * 4);  // up to 4 parts per atom
-  if (rc == GM_OK) rc = dalloc(&c->nbr, n * (size_t)c->kmax * 2);
-  if (rc == GM_OK) rc = dalloc(&c->cut, n * (size_t)c->kmax * 2);
+  if (rc == GM_OK) rc = dalloc(&c->nbr, n * (size_t)(c->kmax + 32) * 2);  // tpa sub-rows of kpart entries
+  if (rc == GM_OK) rc = dalloc(&c->cut, n * (size_t)(c->kmax + 32) * 2);
   if (rc == GM_OK) rc = dalloc(&c->pos_s, n * 4 * T);
   if (rc == GM_OK && c->has_q6) rc = dalloc(&c->qrow, n * 16 * T);
   if (rc == GM_OK && c->has_q6) rc = dalloc(&c->grow, n * 16 * T);
@@ -697,8 +699,8 @@ int gm_reserve_neighbors(gm_ctx* c, int32_t max_neighbors) {
   c->kmax = (max_neighbors + 3) / 4 * 4;
   c->built = c->fwd = c->bwd = false;
   c->version++;
-  GM_TRY(dalloc(&c->nbr, (size_t)c->n * c->kmax * 2));
-  return dalloc(&c->cut, (size_t)c->n * c->kmax * 2);
+  GM_TRY(dalloc(&c->nbr, (size_t)c->n * (c->kmax + 32) * 2));
+  return dalloc(&c->cut, (size_t)c->n * (c->kmax + 32) * 2);
 }
 
 int gm_copy_cell_list(gm_ctx* c, int32_t* perm_dev, int32_t* cell_start_dev, int32_t* ncell) {

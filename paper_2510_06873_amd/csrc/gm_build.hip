@@ -315,8 +315,14 @@ __global__ __launch_bounds__(kBlock) void k_build_nbr(const vec4_t<T>* __restric
       pi = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
     }
     const double xi = (double)pi.x, yi = (double)pi.y, zi = (double)pi.z;
-    uint16_t* row = nbr + (int64_t)ob * kmax + k;
     int32_t count = 0;
+    // entry e of the row goes to sub-row e % tpa; each sub-row is written in
+    // 16-byte pieces
+    SlotWriter w0, w1, w2, w3;
+    w0.init(nbr + subrow(g, ob, k, 0));
+    w1.init(nbr + subrow(g, ob, k, g.tpa > 1 ? 1 : 0));
+    w2.init(nbr + subrow(g, ob, k, g.tpa > 2 ? 2 : 0));
+    w3.init(nbr + subrow(g, ob, k, g.tpa > 3 ? 3 : 0));
     for (int dz = -1; dz <= 1; dz++)
       for (int dy = -1; dy <= 1; dy++)
         for (int dx = -1; dx <= 1; dx++) {
@@ -339,11 +345,25 @@ __global__ __launch_bounds__(kBlock) void k_build_nbr(const vec4_t<T>* __restric
             d2 = d2 - cg.L[2] * rint(d2 * cg.invL[2]);
             const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
             if (r2 < rl2) {
-              if (count < kmax) row[(int64_t)count * O] = (uint16_t)sl;
+              if (count < kmax) {
+                const int prt = count & (g.tpa - 1);
+                if (prt == 0)
+                  w0.push(sl);
+                else if (prt == 1)
+                  w1.push(sl);
+                else if (prt == 2)
+                  w2.push(sl);
+                else
+                  w3.push(sl);
+              }
               count++;
             }
           }
         }
+    w0.flush();
+    if (g.tpa > 1) w1.flush();
+    if (g.tpa > 2) w2.flush();
+    if (g.tpa > 3) w3.flush();
     cnt[ob + k] = count;
     if (count > kmax) atomicOr(err, kErrOverflow);
     mymax = count > mymax ? count : mymax;
@@ -376,7 +396,8 @@ __global__ __launch_bounds__(kBlock) void k_neighbor_ranks(const uint16_t* __res
     const int32_t r = bi.owned_rank[ob + k];
     const int32_t c = cnt[ob + k];
     const int32_t m = c < kmax ? c : kmax;
-    for (int32_t e = 0; e < m; e++) nbr_out[(int64_t)r * kmax + e] = bi.halo_rank[hb + nbr[(int64_t)ob * kmax + (int64_t)e * O + k]];
+    for (int32_t e = 0; e < m; e++)
+      nbr_out[(int64_t)r * kmax + e] = bi.halo_rank[hb + nbr[subrow(g, ob, k, e % g.tpa) + e / g.tpa]];
     cnt_out[r] = c;
   }
 }

@@ -36,12 +36,14 @@ __device__ __forceinline__ Brick brick_begin(const CvArgs<T>& a, int64_t brick) 
 
 template <typename T>
 __device__ __forceinline__ void stage_pos(const CvArgs<T>& a, const Brick& k, vec4_t<T>* lp) {
+#pragma unroll 4
   for (int32_t s = threadIdx.x; s < k.ns; s += blockDim.x) lp[s] = a.pos_s[a.bi.halo_rank[k.hb + s]];
 }
 
 // LDS record of a slot: position, then the 16-wide row (4 vectors).
 template <typename T>
 __device__ __forceinline__ void stage_rows(const CvArgs<T>& a, const Brick& k, const T* rows, vec4_t<T>* lr) {
+#pragma unroll 4
   for (int32_t s = threadIdx.x; s < k.ns; s += blockDim.x) {
     const int32_t r = a.bi.halo_rank[k.hb + s];
     const vec4_t<T>* src = reinterpret_cast<const vec4_t<T>*>(rows + (int64_t)r * 16);
@@ -54,16 +56,18 @@ __device__ __forceinline__ void stage_rows(const CvArgs<T>& a, const Brick& k, c
   }
 }
 
-template <typename T>
+// Fetch a slot's position (and row) from LDS; slots past the staged capacity
+// come from global memory.  ALL: the whole halo is staged (no fallback path).
+template <bool ALL, typename T>
 __device__ __forceinline__ vec4_t<T> fetch_pos(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lp, int32_t s) {
-  if (s < a.bg.cap) return lp[s];
+  if (ALL || s < a.bg.cap) return lp[s];
   return a.pos_s[a.bi.halo_rank[k.hb + s]];
 }
 
-template <typename T>
+template <bool ALL, typename T>
 __device__ __forceinline__ void fetch_rec(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr, const T* rows,
                                           int32_t s, vec4_t<T>& p, T v[16]) {
-  if (s < a.bg.cap) {
+  if (ALL || s < a.bg.cap) {
     const vec4_t<T>* src = lr + 5 * s;
     p = src[0];
 #pragma unroll
@@ -148,76 +152,94 @@ __device__ __forceinline__ T group_sum(T v, int TPA) {
   return v;
 }
 
-// Walk n cutoff slots of one part, two records in flight: the next record is
-// fetched from LDS before the current one is used.
-template <typename T, class Body>
+// Walk the n cutoff slots of one part, two records in flight: the next
+// record is fetched from LDS before the current one is used; slot numbers
+// come from a register stream over the part's sub-row.
+template <bool ALL, typename T, class Body>
 __device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr, const T* rows,
-                                             const uint16_t* crow, int TPA, int32_t part, int32_t n, Body body) {
+                                             const uint16_t* crow, int32_t n, Body body) {
   if (n <= 0) return;
+  SlotStream st;
+  st.init(crow, n);
   vec4_t<T> pa, pb;
   T va[16], vb[16];
-  fetch_rec(a, k, lr, rows, crow[(int64_t)part * k.O], pa, va);
+  fetch_rec<ALL>(a, k, lr, rows, st.pop(), pa, va);
   for (int32_t j = 0; j < n; j += 2) {
     const bool b_ok = j + 1 < n;
-    if (b_ok) fetch_rec(a, k, lr, rows, crow[(int64_t)((j + 1) * TPA + part) * k.O], pb, vb);
+    if (b_ok) fetch_rec<ALL>(a, k, lr, rows, st.pop(), pb, vb);
     body(pa, va);
     if (b_ok) {
-      if (j + 2 < n) fetch_rec(a, k, lr, rows, crow[(int64_t)((j + 2) * TPA + part) * k.O], pa, va);
+      if (j + 2 < n) fetch_rec<ALL>(a, k, lr, rows, st.pop(), pa, va);
       body(pb, vb);
     }
   }
 }
 
+// Owned atoms of this workgroup's brick: thread -> (atom o, part).
+#define GM_FOR_OWNED(a, k)                                         \
+  const int TPA = (a).bg.tpa;                                      \
+  const int32_t part = threadIdx.x & (TPA - 1);                    \
+  for (int32_t o = threadIdx.x / TPA; o < (k).O; o += blockDim.x / TPA)
+
 // --------------------------------------------------------------------------
 // Pass 1
 // --------------------------------------------------------------------------
-template <typename T, bool CN, bool Q6>
-__device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  vec4_t<T>* lp = reinterpret_cast<vec4_t<T>*>(smem);
-  __shared__ double red[kBlock / 64];
-  const Brick k = brick_begin(a, brick);
-  stage_pos(a, k, lp);
-  __syncthreads();
+template <typename T, bool CN, bool Q6, bool ALL>
+__device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lp) {
   double cn_part = 0.0;
-  const int TPA = a.bg.tpa;
-  const int32_t part = threadIdx.x & (TPA - 1);
-  for (int32_t o = threadIdx.x / TPA; o < k.O; o += blockDim.x / TPA) {
+  GM_FOR_OWNED(a, k) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
-    const vec4_t<T> pi = fetch_pos(a, k, lp, si);
+    const vec4_t<T> pi = fetch_pos<ALL>(a, k, lp, si);
     const int32_t c = min(a.cnt[k.ob + o], a.kmax);
-    const uint16_t* row = a.nbr + (int64_t)k.ob * a.kmax + o;
-    uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
-    T Q[13];
+    const int32_t cp = c > part ? (c - part + TPA - 1) / TPA : 0;
+    // Phase 1: distance filter over the neighbour sub-row, writing this
+    // step's in-cutoff slots (cheap, so divergence costs little).
+    uint16_t* crow = a.cut + subrow(a.bg, k.ob, o, part);
+    SlotStream st;
+    st.init(a.nbr + subrow(a.bg, k.ob, o, part), cp);
+    SlotWriter wr;
+    wr.init(crow);
+    for (int32_t j = 0; j < cp; j++) {
+      const int32_t s = st.pop();
+      const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
+      T dx, dy, dz;
+      if (pair_vec(pi, pj, a, dx, dy, dz) < a.rc2) wr.push(s);
+    }
+    wr.flush();
+    const int32_t nc = wr.n;
+    a.ccnt[(int64_t)(k.ob + o) * TPA + part] = nc;
+    // Phase 2: the weighted harmonics over the in-cutoff slots only (the
+    // thread reads back its own sub-row).  The unit vector, the harmonics and
+    // q_lm are formed in FP64 from the pair vector: the bond dots of pass 2
+    // feed two steep logistics, which turn the cancellation error of an FP32
+    // degree-6 polynomial into visible force error; FP64 FMA issues at the
+    // FP32 rate, and the stored rows stay in T.
+    double Q[13];
 #pragma unroll
-    for (int m = 0; m < 13; m++) Q[m] = T(0);
+    for (int m = 0; m < 13; m++) Q[m] = 0.0;
     T fsum = T(0), cnsum = T(0);
-    int32_t nc = 0;
-    for (int32_t e = part; e < c; e += TPA) {
-      const int32_t s = row[(int64_t)e * k.O];
-      const vec4_t<T> pj = fetch_pos(a, k, lp, s);
+    SlotStream sc;
+    sc.init(crow, nc);
+    for (int32_t j = 0; j < nc; j++) {
+      const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, sc.pop());
       T dx, dy, dz;
       const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
-      if (r2 < a.rc2) {
-        crow[(int64_t)(nc * TPA + part) * k.O] = (uint16_t)s;
-        nc++;
-        const T rinv = g_rsqrt(r2);
-        const T r = r2 * rinv;
-        if (Q6) {
-          T df;
-          const T f = taper_w(r, a, df);
-          accumulate_y(a.yc, dx * rinv, dy * rinv, dz * rinv, f, Q);
-          fsum += f;
-        }
-        if (CN) {
-          const T x = r * a.cn_r0inv;
-          const T x2 = x * x;
-          cnsum += g_rcp(T(1) + x2 * x2 * x2);
-        }
+      const T rinv = g_rsqrt(r2);
+      const T r = r2 * rinv;
+      if (Q6) {
+        T df;
+        const T f = taper_w(r, a, df);
+        const double ri64 = rsqrt_fp64(r2);
+        accumulate_y(a.ycd, (double)dx * ri64, (double)dy * ri64, (double)dz * ri64, (double)f, Q);
+        fsum += f;
+      }
+      if (CN) {
+        const T x = r * a.cn_r0inv;
+        const T x2 = x * x;
+        cnsum += g_rcp(T(1) + x2 * x2 * x2);
       }
     }
-    a.ccnt[(int64_t)(k.ob + o) * TPA + part] = nc;
     if (Q6) {
 #pragma unroll
       for (int m = 0; m < 13; m++) Q[m] = group_sum(Q[m], TPA);
@@ -226,15 +248,15 @@ __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, in
     if (CN) cnsum = group_sum(cnsum, TPA);
     if (part == 0) {
       if (Q6) {
-        T qq = T(0);
+        double qq = 0.0;
 #pragma unroll
         for (int m = 0; m < 13; m++) qq += Q[m] * Q[m];
-        const T qn = g_sqrt(qq);
-        const T inv = qn >= T(1e-12) ? T(1) / qn : T(0);
+        const double qn = sqrt(qq);
+        const double inv = qn >= 1e-12 ? 1.0 / qn : 0.0;
         T rowv[16];
 #pragma unroll
-        for (int m = 0; m < 13; m++) rowv[m] = Q[m] * inv;
-        rowv[13] = qn;
+        for (int m = 0; m < 13; m++) rowv[m] = (T)(Q[m] * inv);
+        rowv[13] = (T)qn;
         rowv[14] = T(0);
         rowv[15] = fsum;
         store_row16(a.qrow + (int64_t)ri * 16, rowv);
@@ -245,6 +267,19 @@ __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, in
       }
     }
   }
+  return cn_part;
+}
+
+template <typename T, bool CN, bool Q6>
+__device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  vec4_t<T>* lp = reinterpret_cast<vec4_t<T>*>(smem);
+  __shared__ double red[kBlock / 64];
+  const Brick k = brick_begin(a, brick);
+  stage_pos(a, k, lp);
+  __syncthreads();
+  const double cn_part =
+      k.H <= a.bg.cap ? pass1_atoms<T, CN, Q6, true>(a, k, lp) : pass1_atoms<T, CN, Q6, false>(a, k, lp);
   if (CN) {
     const double b = block_sum(cn_part, red);
     if (threadIdx.x == 0) (Q6 ? a.part_b : a.part_a)[blk] = b;
@@ -254,27 +289,18 @@ __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, in
 // --------------------------------------------------------------------------
 // Pass 2
 // --------------------------------------------------------------------------
-template <typename T, bool CN>
-__device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
-  __shared__ double red[kBlock / 64];
-  const Brick k = brick_begin(a, brick);
-  stage_rows(a, k, a.qrow, lr);
-  __syncthreads();
+template <typename T, bool ALL>
+__device__ __forceinline__ double pass2_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr) {
   double c_part = 0.0;
-  const int TPA = a.bg.tpa;
-  const int32_t part = threadIdx.x & (TPA - 1);
-  for (int32_t o = threadIdx.x / TPA; o < k.O; o += blockDim.x / TPA) {
+  GM_FOR_OWNED(a, k) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     vec4_t<T> pi;
     T qi[16];
-    fetch_rec(a, k, lr, a.qrow, si, pi, qi);
+    fetch_rec<ALL>(a, k, lr, a.qrow, si, pi, qi);
     const int32_t nc = a.ccnt[(int64_t)(k.ob + o) * TPA + part];
-    const uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
     T nbond = T(0);
-    walk_records(a, k, lr, a.qrow, crow, TPA, part, nc, [&](const vec4_t<T>& pj, const T* qj) {
+    walk_records<ALL>(a, k, lr, a.qrow, a.cut + subrow(a.bg, k.ob, o, part), nc, [&](const vec4_t<T>& pj, const T* qj) {
       T dx, dy, dz;
       const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
       const T r = g_sqrt(r2);
@@ -294,6 +320,18 @@ __device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, in
       c_part += (double)cc;
     }
   }
+  return c_part;
+}
+
+template <typename T, bool CN>
+__device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
+  __shared__ double red[kBlock / 64];
+  const Brick k = brick_begin(a, brick);
+  stage_rows(a, k, a.qrow, lr);
+  __syncthreads();
+  const double c_part = k.H <= a.bg.cap ? pass2_atoms<T, true>(a, k, lr) : pass2_atoms<T, false>(a, k, lr);
   const double b = block_sum(c_part, red);
   if (threadIdx.x == 0) a.part_a[blk] = b;
 }
@@ -301,29 +339,21 @@ __device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, in
 // --------------------------------------------------------------------------
 // Pass 3
 // --------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void pass3_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
-  const Brick k = brick_begin(a, brick);
-  stage_rows(a, k, a.qrow, lr);
-  __syncthreads();
-  const int TPA = a.bg.tpa;
-  const int32_t part = threadIdx.x & (TPA - 1);
-  for (int32_t o = threadIdx.x / TPA; o < k.O; o += blockDim.x / TPA) {
+template <typename T, bool ALL>
+__device__ __forceinline__ void pass3_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr) {
+  GM_FOR_OWNED(a, k) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     vec4_t<T> pi;
     T qi[16];
-    fetch_rec(a, k, lr, a.qrow, si, pi, qi);
+    fetch_rec<ALL>(a, k, lr, a.qrow, si, pi, qi);
     const T dci = qi[14];
     const int32_t nc = a.ccnt[(int64_t)(k.ob + o) * TPA + part];
-    const uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
     T h[13];
 #pragma unroll
     for (int m = 0; m < 13; m++) h[m] = T(0);
     T rx = T(0), ry = T(0), rz = T(0);
-    walk_records(a, k, lr, a.qrow, crow, TPA, part, nc, [&](const vec4_t<T>& pj, const T* qj) {
+    walk_records<ALL>(a, k, lr, a.qrow, a.cut + subrow(a.bg, k.ob, o, part), nc, [&](const vec4_t<T>& pj, const T* qj) {
       T dx, dy, dz;
       const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
@@ -372,32 +402,37 @@ __device__ __forceinline__ void pass3_body(const CvArgs<T>& a, int64_t brick, in
   }
 }
 
+template <typename T>
+__device__ __forceinline__ void pass3_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
+  const Brick k = brick_begin(a, brick);
+  stage_rows(a, k, a.qrow, lr);
+  __syncthreads();
+  if (k.H <= a.bg.cap)
+    pass3_atoms<T, true>(a, k, lr);
+  else
+    pass3_atoms<T, false>(a, k, lr);
+}
+
 // --------------------------------------------------------------------------
 // Pass 4: chain rule onto positions (u(r) = f(r) v(r_hat) is even in r, so
 // both ends of a pair reuse one Jacobian with g_i + g_j).
 // --------------------------------------------------------------------------
-template <typename T, bool CN>
-__device__ __forceinline__ void pass4_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
-  const Brick k = brick_begin(a, brick);
-  stage_rows(a, k, a.grow, lr);
-  __syncthreads();
+template <typename T, bool CN, bool ALL>
+__device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr) {
   const T seed_q = a.seed ? (T)a.seed[a.dims - 1] : T(1);
   const T seed_cn = (CN && a.seed) ? (T)(a.seed[0] * 2.0 * a.inv_n) : T(0);
-  const int TPA = a.bg.tpa;
-  const int32_t part = threadIdx.x & (TPA - 1);
-  for (int32_t o = threadIdx.x / TPA; o < k.O; o += blockDim.x / TPA) {
+  GM_FOR_OWNED(a, k) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     vec4_t<T> pi;
     T gi[16];
-    fetch_rec(a, k, lr, a.grow, si, pi, gi);
+    fetch_rec<ALL>(a, k, lr, a.grow, si, pi, gi);
     const int32_t nc = a.ccnt[(int64_t)(k.ob + o) * TPA + part];
-    const uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
     T ax = T(0), ay = T(0), az = T(0);
     T cx = T(0), cy = T(0), cz = T(0);
-    walk_records(a, k, lr, a.grow, crow, TPA, part, nc, [&](const vec4_t<T>& pj, const T* gj) {
+    walk_records<ALL>(a, k, lr, a.grow, a.cut + subrow(a.bg, k.ob, o, part), nc, [&](const vec4_t<T>& pj, const T* gj) {
       T dx, dy, dz;
       const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
@@ -452,28 +487,35 @@ __device__ __forceinline__ void pass4_body(const CvArgs<T>& a, int64_t brick, in
   }
 }
 
+template <typename T, bool CN>
+__device__ __forceinline__ void pass4_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
+  const Brick k = brick_begin(a, brick);
+  stage_rows(a, k, a.grow, lr);
+  __syncthreads();
+  if (k.H <= a.bg.cap)
+    pass4_atoms<T, CN, true>(a, k, lr);
+  else
+    pass4_atoms<T, CN, false>(a, k, lr);
+}
+
 // --------------------------------------------------------------------------
 // Coordination number alone: forces over the in-cutoff slots of pass 1.
 // --------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void cn_force_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  vec4_t<T>* lp = reinterpret_cast<vec4_t<T>*>(smem);
-  const Brick k = brick_begin(a, brick);
-  stage_pos(a, k, lp);
-  __syncthreads();
+template <typename T, bool ALL>
+__device__ __forceinline__ void cn_force_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lp) {
   const T seed = (T)((a.seed ? a.seed[0] : 1.0) * 2.0 * a.inv_n);
-  const int TPA = a.bg.tpa;
-  const int32_t part = threadIdx.x & (TPA - 1);
-  for (int32_t o = threadIdx.x / TPA; o < k.O; o += blockDim.x / TPA) {
+  GM_FOR_OWNED(a, k) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
-    const vec4_t<T> pi = fetch_pos(a, k, lp, si);
+    const vec4_t<T> pi = fetch_pos<ALL>(a, k, lp, si);
     const int32_t nc = a.ccnt[(int64_t)(k.ob + o) * TPA + part];
-    const uint16_t* crow = a.cut + (int64_t)k.ob * a.kmax + o;
+    SlotStream st;
+    st.init(a.cut + subrow(a.bg, k.ob, o, part), nc);
     T cx = T(0), cy = T(0), cz = T(0);
     for (int32_t j = 0; j < nc; j++) {
-      const vec4_t<T> pj = fetch_pos(a, k, lp, crow[(int64_t)(j * TPA + part) * k.O]);
+      const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, st.pop());
       T dx, dy, dz;
       const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
@@ -491,6 +533,19 @@ __device__ __forceinline__ void cn_force_body(const CvArgs<T>& a, int64_t brick,
     cz = group_sum(cz, TPA);
     if (part == 0) write_out(a, ri, -seed * cx, -seed * cy, -seed * cz);
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void cn_force_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  vec4_t<T>* lp = reinterpret_cast<vec4_t<T>*>(smem);
+  const Brick k = brick_begin(a, brick);
+  stage_pos(a, k, lp);
+  __syncthreads();
+  if (k.H <= a.bg.cap)
+    cn_force_atoms<T, true>(a, k, lp);
+  else
+    cn_force_atoms<T, false>(a, k, lp);
 }
 
 // --------------------------------------------------------------------------

@@ -23,6 +23,14 @@ __device__ __forceinline__ void g_sincos(double x, double* s, double* c) { sinco
 __device__ __forceinline__ float g_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double g_sqrt(double x) { return sqrt(x); }
 
+// 1/sqrt(r2) in FP64 from an FP32 argument: hardware FP32 estimate, then one
+// Newton step in FP64 (relative error ~1e-14).
+__device__ __forceinline__ double rsqrt_fp64(float r2f) {
+  const double r2 = (double)r2f, y = (double)__builtin_amdgcn_rsqf(r2f);
+  return y * (1.5 - 0.5 * r2 * y * y);
+}
+__device__ __forceinline__ double rsqrt_fp64(double r2) { return 1.0 / sqrt(r2); }
+
 template <typename T>
 __device__ __forceinline__ T logistic(T x) {
   return g_rcp(T(1) + g_exp(-x));
@@ -55,20 +63,27 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return r;
 }
 
-// Minimum image in T: d - L*rint(d/L), with L split in high and low parts so
-// that an FP32 box length does not bias wrapped pairs.
+// Minimum-image difference xj - xi - k L, k = rint((xj - xi)/L), with the
+// box length split in a high part L (in T) and a low part Llo.  The image
+// shift is subtracted from the coordinate that lies near the far face (xj for
+// k > 0, xi for k < 0) before the two are differenced: there both operands
+// are within a factor of two, so the subtraction is exact, and the result is
+// rounded only at its own magnitude.  Forming xj - xi first would round a
+// wrapped pair at the magnitude of L (ulp(200 A) ~ 1.5e-5 A in FP32).
 template <typename T>
-__device__ __forceinline__ T mic(T d, T L, T invL, T Llo) {
-  T k = g_rint(d * invL);
-  return (d - k * L) - k * Llo;
+__device__ __forceinline__ T mic(T xj, T xi, T L, T invL, T Llo) {
+  const T k = g_rint((xj - xi) * invL);
+  const T a = xj - fmax(k, T(0)) * L;
+  const T b = xi + fmin(k, T(0)) * L;
+  return (a - b) - k * Llo;
 }
 
 template <typename T>
 __device__ __forceinline__ T pair_vec(const vec4_t<T>& pi, const vec4_t<T>& pj, const CvArgs<T>& a,
                                       T& dx, T& dy, T& dz) {
-  dx = mic(pj.x - pi.x, a.L[0], a.invL[0], a.Llo[0]);
-  dy = mic(pj.y - pi.y, a.L[1], a.invL[1], a.Llo[1]);
-  dz = mic(pj.z - pi.z, a.L[2], a.invL[2], a.Llo[2]);
+  dx = mic(pj.x, pi.x, a.L[0], a.invL[0], a.Llo[0]);
+  dy = mic(pj.y, pi.y, a.L[1], a.invL[1], a.Llo[1]);
+  dz = mic(pj.z, pi.z, a.L[2], a.invL[2], a.Llo[2]);
   return dx * dx + dy * dy + dz * dz;
 }
 
@@ -220,5 +235,76 @@ __device__ __forceinline__ int64_t logical_brick(const BrickGeom& g) {
   const int64_t per = gridDim.x / kXcd;
   return (b % kXcd) * per + b / kXcd;
 }
+
+// First entry of the sub-row of part `part` of owned atom `o` of a brick whose
+// owned atoms start at `ob`.  Entry e of an atom's row lives in sub-row
+// e % tpa at index e / tpa.
+__device__ __forceinline__ int64_t subrow(const BrickGeom& g, int32_t ob, int32_t o, int32_t part) {
+  return ((int64_t)(ob + o) * g.tpa + part) * g.kpart;
+}
+
+// Sequential reader of one sub-row of 16-bit slots: 8 entries per 16-byte
+// load, the next 8 prefetched, entries popped from registers by funnel
+// shifts (no dynamic register indexing).  All lanes pop in lockstep.
+struct SlotStream {
+  const uint4* src;
+  uint4 cur, nxt;
+  int32_t n, j;
+
+  __device__ __forceinline__ void init(const uint16_t* row, int32_t count) {
+    src = reinterpret_cast<const uint4*>(row);
+    n = count;
+    j = 0;
+    cur = make_uint4(0, 0, 0, 0);
+    nxt = cur;
+    if (n > 0) cur = src[0];
+    if (n > 8) nxt = src[1];
+  }
+
+  __device__ __forceinline__ int32_t pop() {
+    const int32_t s = (int32_t)(cur.x & 0xffffu);
+    cur.x = __builtin_amdgcn_alignbit(cur.y, cur.x, 16);
+    cur.y = __builtin_amdgcn_alignbit(cur.z, cur.y, 16);
+    cur.z = __builtin_amdgcn_alignbit(cur.w, cur.z, 16);
+    cur.w = cur.w >> 16;
+    j++;
+    if ((j & 7) == 0) {
+      cur = nxt;
+      if (j + 8 < n) nxt = src[(j >> 3) + 1];
+    }
+    return s;
+  }
+};
+
+// Appends 16-bit slots to one sub-row, 8 per 16-byte store.
+struct SlotWriter {
+  uint4* dst;
+  uint4 buf;
+  int32_t n;
+
+  __device__ __forceinline__ void init(uint16_t* row) {
+    dst = reinterpret_cast<uint4*>(row);
+    buf = make_uint4(0, 0, 0, 0);
+    n = 0;
+  }
+
+  __device__ __forceinline__ void push(int32_t s) {
+    const uint32_t v = ((uint32_t)s & 0xffffu) << ((n & 1) * 16);
+    const int w = (n >> 1) & 3;
+    buf.x |= w == 0 ? v : 0u;
+    buf.y |= w == 1 ? v : 0u;
+    buf.z |= w == 2 ? v : 0u;
+    buf.w |= w == 3 ? v : 0u;
+    n++;
+    if ((n & 7) == 0) {
+      dst[(n >> 3) - 1] = buf;
+      buf = make_uint4(0, 0, 0, 0);
+    }
+  }
+
+  __device__ __forceinline__ void flush() {
+    if (n & 7) dst[n >> 3] = buf;
+  }
+};
 
 }  // namespace gm

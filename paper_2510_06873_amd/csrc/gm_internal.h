@@ -63,6 +63,7 @@ struct BrickGeom {
   int32_t cap;     // halo slots staged in LDS (slots beyond are read from global memory)
   int32_t blocks;  // workgroups launched per brick pass (nbricks rounded up to the XCD count)
   int32_t tpa;     // threads per owned atom (1, 2 or 4): lanes that split one atom's rows
+  int32_t kpart;   // length of one part's sub-row (multiple of 8 entries, 16-byte aligned)
 };
 
 struct BrickIndex {
@@ -79,10 +80,10 @@ struct BrickIndex {
 template <typename T>
 struct CvArgs {
   const vec4_t<T>* pos_s;  // positions in sorted (cell) order
-  const uint16_t* nbr;     // neighbour slots, per brick [kmax][O] (column-major)
+  const uint16_t* nbr;     // neighbour slots: sub-row (owned atom, part) of kpart entries
   const int32_t* cnt;      // [N] row lengths, brick order
   uint16_t* cut;           // in-cutoff slots of the current step, same layout as nbr
-  int32_t* ccnt;           // [N] in-cutoff counts, brick order
+  int32_t* ccnt;           // [N][tpa] in-cutoff counts per part, brick order
   const int32_t* perm;     // sorted position -> caller's atom id
   BrickGeom bg;
   BrickIndex bi;
@@ -95,6 +96,7 @@ struct CvArgs {
   T cn_r0inv;
   double inv_n;
   YCoef<T> yc;
+  YCoef<double> ycd;  // the same coefficients in FP64 (pass 1 forms q_lm in FP64)
   T* qrow;          // [N][16] by sorted position: qhat(13), |Q|, c', sum f
   T* grow;          // [N][16]: g(13), c'
   vec4_t<T>* frad;  // [N]: sum over taper pairs of (c'_i + c'_j) b_ij f'(r) r_hat

@@ -134,6 +134,33 @@ def test_q6_cv_and_forces(orc, spec, precision, tol_s, tol_f):
     assert np.max(np.abs(pipe.atom_values(ATOM_C).cpu().numpy() - o["c"])) <= 50 * tol_a
 
 
+def test_q6_forces_wrapped_pairs_long_box(orc):
+    """Pairs across the periodic faces of a 204 A box: the minimum-image
+    difference must not round at the magnitude of the box length (FP32 ulp at
+    200 A is 1.5e-5 A).  Forming x_j - x_i before removing the image shift put
+    a 4e-4 relative force error on the atoms at the faces; with the shift taken
+    from the coordinate near the far face the error stays at the FP32 level of
+    the interior, so the bar here is tighter than the general one."""
+    d = W.wurtzite_slab(64, 3, 4, seed=31)
+    pos, box, sp = d["pos"], d["box"], d["species"]
+    n = len(pos)
+    assert box[0] > 200.0
+    pipe = make_pipe(Q6CV, n)
+    F_in = np.zeros((n, 4), np.float32)
+    dv = [1.0]
+    s, F = run_step(pipe, pos, sp, box, F_in, dv)
+    s_ref, g_ref, _ = oracle_cvs(orc, pos, box, Q6CV)
+    assert abs(s[0] - s_ref[0]) <= 1e-6 * abs(s_ref[0])
+    err = rel_force_err(F[:, :3], -g_ref[0])
+    # atoms within 2 A of an x face against the rest
+    face = np.minimum(pos[:, 0], box[0] - pos[:, 0]) < 2.0
+    gmax = np.linalg.norm(g_ref[0], axis=1).max()
+    err_face = np.linalg.norm(F[face, :3] + g_ref[0][face], axis=1).max() / gmax
+    print(f"[wrap] N={n} force err {err:.2e}, at the x faces {err_face:.2e}")
+    assert err <= 2e-5
+    assert err_face <= 2e-5
+
+
 def test_q6_backward_gradient_output(orc):
     d = W.wurtzite_slab(5, 3, 5, seed=23)
     pos, box = d["pos"], d["box"]
