@@ -88,6 +88,39 @@ double fact(int k) {
 //   D5 = 166320 z/16                          D6 = 166320/16
 // and Y_6m = K_m (-1)^m D_m(z) (x + i y)^m with K_m = sqrt(13/(4 pi) (6-m)!/(6+m)!)
 // (Condon-Shortley phase).  The real basis scales m > 0 by sqrt(2).
+// The deg real roots in (0, 1) of sum_k p[k] t^k (known to be simple and to
+// lie there): sign changes on a fine grid, then bisection to full precision.
+void unit_roots(const double* p, int deg, double* out) {
+  auto val = [&](double t) {
+    double v = p[deg];
+    for (int k = deg - 1; k >= 0; k--) v = v * t + p[k];
+    return v;
+  };
+  const int grid = 4096;
+  int found = 0;
+  double a = 0.0, fa = val(0.0);
+  for (int i = 1; i <= grid && found < deg; i++) {
+    const double b = (double)i / grid, fb = val(b);
+    if ((fa < 0.0) != (fb < 0.0)) {
+      double lo = a, hi = b, flo = fa;
+      for (int it = 0; it < 200 && hi - lo > 0.0; it++) {
+        const double mid = 0.5 * (lo + hi), fm = val(mid);
+        if (mid <= lo || mid >= hi) break;
+        if ((fm < 0.0) == (flo < 0.0)) {
+          lo = mid;
+          flo = fm;
+        } else {
+          hi = mid;
+        }
+      }
+      out[found++] = 0.5 * (lo + hi);
+    }
+    a = b;
+    fa = fb;
+  }
+  for (; found < deg; found++) out[found] = 0.0;  // not reached for these polynomials
+}
+
 template <typename T>
 void make_ycoef(YCoef<T>& c) {
   const double D0[4] = {-5, 105, -315, 231}, D1[3] = {210, -1260, 1386}, D2[3] = {210, -3780, 6930};
@@ -105,6 +138,17 @@ void make_ycoef(YCoef<T>& c) {
   c.e5 = (T)(A[5] * D5 / 16.0);
   c.e6 = (T)(A[6] * D6 / 16.0);
   for (int m = 0; m < 6; m++) c.rat[m] = (T)(A[m] / A[m + 1]);
+  // Product form: every d^m P_6/dz^m has its 6-m zeros real and inside
+  // (-1, 1) (Rolle), so its even/odd part has real roots t = z^2 in (0, 1).
+  const double* P[5] = {D0, D1, D2, D3, D4};
+  const int deg[5] = {3, 2, 2, 1, 1};
+  int at = 0;
+  for (int m = 0; m < 5; m++) {
+    c.lead[m] = (T)(A[m] * P[m][deg[m]] / 16.0);
+    double roots[3];
+    unit_roots(P[m], deg[m], roots);
+    for (int k = 0; k < deg[m]; k++) c.t[at++] = (T)roots[k];
+  }
 }
 
 int validate(const gm_params* p, int64_t n) {
@@ -177,7 +221,6 @@ CvArgs<T> make_args(gm_ctx* c) {
     a.yc = c->ycf;
   else
     a.yc = c->ycd;
-  a.ycd = c->ycd;
   a.qrow = reinterpret_cast<T*>(c->qrow);
   a.grow = reinterpret_cast<T*>(c->grow);
   a.frad = reinterpret_cast<vec4_t<T>*>(c->frad);
@@ -254,6 +297,17 @@ int64_t halo_bound(const gm_ctx* c) {
     m *= best;
   }
   return m * c->n;
+}
+
+GatherArgs gather_args(gm_ctx* c, const float* pos4) {
+  GatherArgs g;
+  g.pos = reinterpret_cast<const float4*>(pos4);
+  g.perm = c->perm;
+  g.n = c->n;
+  g.pos_s = c->pos_s;
+  g.err = c->err;
+  for (int d = 0; d < 3; d++) g.L[d] = (float)c->geom.L[d];
+  return g;
 }
 
 BiasArgs make_bias(gm_ctx* c, const double* s, int deposit) {
@@ -334,8 +388,7 @@ int status_from_bits(int32_t bits) {
 template <typename T>
 static int cv_forward_t(gm_ctx* c, const float* pos4, double* s_dev) {
   hipStream_t st = c->stream;
-  auto* ps = reinterpret_cast<vec4_t<T>*>(c->pos_s);
-  GM_TRY(hip_rc(launch_gather<T>(reinterpret_cast<const float4*>(pos4), c->perm, c->n, ps, c->err, st)));
+  GM_TRY(hip_rc(launch_gather<T>(gather_args(c, pos4), st)));
   CvArgs<T> a = make_args<T>(c);
   a.s_out = s_dev;
   if (c->has_q6) return hip_rc(launch_q6_forward<T>(a, c->has_cn, st));
@@ -548,6 +601,7 @@ int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
   // canonical cell list: counts, scan, scatter, per-cell sort by atom id
   GM_TRY(hip_rc(launch_fill_i32(c->count, 0, ncells, st)));
   GM_TRY(hip_rc(launch_fill_i32(c->stats, 0, 4, st)));
+  GM_TRY(hip_rc(launch_fill_i32(c->err + 1, 0, 1, st)));  // out-of-box flag (see the gather)
   GM_TRY(hip_rc(launch_cell_ids(p4, c->n, c->geom, c->cell, c->count, c->err, st)));
   GM_TRY(hip_rc(launch_scan(c->count, ncells, c->start, c->fill, c->scan_tmp, st)));
   GM_TRY(hip_rc(launch_scatter(c->cell, c->n, c->start, c->fill, c->perm, st)));
@@ -562,12 +616,12 @@ int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
   const double rl2 = c->r_list * c->r_list;
   if (c->fp64) {
     auto* ps = reinterpret_cast<double4*>(c->pos_s);
-    GM_TRY(hip_rc(launch_gather<double>(p4, c->perm, c->n, ps, c->err, st)));
+    GM_TRY(hip_rc(launch_gather<double>(gather_args(c, pos4), st)));
     GM_TRY(hip_rc(launch_build_nbr<double>(ps, c->geom, c->bg, bi, rl2, c->nbr, c->kmax, c->cnt, c->err, c->stats,
                                            st)));
   } else {
     auto* ps = reinterpret_cast<float4*>(c->pos_s);
-    GM_TRY(hip_rc(launch_gather<float>(p4, c->perm, c->n, ps, c->err, st)));
+    GM_TRY(hip_rc(launch_gather<float>(gather_args(c, pos4), st)));
     GM_TRY(hip_rc(launch_build_nbr<float>(ps, c->geom, c->bg, bi, rl2, c->nbr, c->kmax, c->cnt, c->err, c->stats,
                                           st)));
   }
@@ -800,7 +854,7 @@ int refresh_group(gm_batch* B, gm_batch::Group& g, bool force) {
     a.mode = 0;
     a.out4 = B->force[m];
     append(cv, a);
-    GatherArgs gth{reinterpret_cast<const float4*>(B->pos[m]), c->perm, c->n, c->pos_s, c->err};
+    GatherArgs gth = gather_args(c, B->pos[m]);
     append(ga, gth);
     BiasArgs ev = make_bias(c, c->s_int, 0);
     ev.V_out = c->V_int;

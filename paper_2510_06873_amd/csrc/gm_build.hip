@@ -143,23 +143,27 @@ __global__ __launch_bounds__(kBlock) void k_sort_cells(const int32_t* __restrict
 }
 
 template <typename T>
-__device__ __forceinline__ void gather_body(const float4* __restrict__ pos, const int32_t* __restrict__ perm, int64_t n,
-                                            vec4_t<T>* __restrict__ pos_s, int32_t* err, int64_t t) {
-  if (t >= n) return;
-  float4 p = pos[perm[t]];
-  if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z))) atomicOr(err, kErrNonFinite);
+__device__ __forceinline__ void gather_body(const GatherArgs& a, int64_t t) {
+  if (t >= a.n) return;
+  const float4 p = a.pos[a.perm[t]];
+  if (!(isfinite(p.x) && isfinite(p.y) && isfinite(p.z))) atomicOr(a.err, kErrNonFinite);
+  // A coordinate outside [0, L) may sit in a cell of another image: the CV
+  // passes then take the minimum image for every pair until the next rebuild
+  // clears the flag (one atomic per wave).
+  const bool out = !(p.x >= 0.f && p.x < a.L[0] && p.y >= 0.f && p.y < a.L[1] && p.z >= 0.f && p.z < a.L[2]);
+  const uint64_t m = __ballot(out);
+  if (m != 0 && (int)(threadIdx.x & 63) == __ffsll((unsigned long long)m) - 1) atomicOr(a.err + 1, 1);
   vec4_t<T> q;
   q.x = (T)p.x;
   q.y = (T)p.y;
   q.z = (T)p.z;
   q.w = (T)p.w;
-  pos_s[t] = q;
+  reinterpret_cast<vec4_t<T>*>(a.pos_s)[t] = q;
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gather(const float4* __restrict__ pos, const int32_t* __restrict__ perm,
-                                                   int64_t n, vec4_t<T>* __restrict__ pos_s, int32_t* err) {
-  gather_body<T>(pos, perm, n, pos_s, err, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
+  gather_body<T>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <typename T>
@@ -171,9 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_batch(const GatherArgs* __res
     const int32_t mid = (lo + hi) >> 1;
     if (blk_start[mid] <= g) lo = mid; else hi = mid;
   }
-  const GatherArgs& a = tab[lo];
-  gather_body<T>(a.pos, a.perm, a.n, reinterpret_cast<vec4_t<T>*>(a.pos_s), a.err,
-                 (g - blk_start[lo]) * blockDim.x + threadIdx.x);
+  gather_body<T>(tab[lo], (g - blk_start[lo]) * blockDim.x + threadIdx.x);
 }
 
 // --------------------------------------------------------------------------
@@ -470,9 +472,8 @@ hipError_t launch_brick_fill(const int32_t* start, const BrickGeom& g, const Bri
 }
 
 template <typename T>
-hipError_t launch_gather(const float4* pos, const int32_t* perm, int64_t n, vec4_t<T>* pos_s, int32_t* err,
-                         hipStream_t st) {
-  k_gather<T><<<grid_of(n, kBlock), kBlock, 0, st>>>(pos, perm, n, pos_s, err);
+hipError_t launch_gather(const GatherArgs& a, hipStream_t st) {
+  k_gather<T><<<grid_of(a.n, kBlock), kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -506,8 +507,8 @@ hipError_t launch_gather_batch(const GatherArgs* tab, const int32_t* blk_start, 
 }
 template hipError_t launch_gather_batch<float>(const GatherArgs*, const int32_t*, int32_t, int32_t, hipStream_t);
 template hipError_t launch_gather_batch<double>(const GatherArgs*, const int32_t*, int32_t, int32_t, hipStream_t);
-template hipError_t launch_gather<float>(const float4*, const int32_t*, int64_t, float4*, int32_t*, hipStream_t);
-template hipError_t launch_gather<double>(const float4*, const int32_t*, int64_t, double4*, int32_t*, hipStream_t);
+template hipError_t launch_gather<float>(const GatherArgs&, hipStream_t);
+template hipError_t launch_gather<double>(const GatherArgs&, hipStream_t);
 template hipError_t launch_build_nbr<float>(const float4*, const CellGeom&, const BrickGeom&, const BrickIndex&,
                                             double, uint16_t*, int32_t, int32_t*, int32_t*, int32_t*, hipStream_t);
 template hipError_t launch_build_nbr<double>(const double4*, const CellGeom&, const BrickGeom&, const BrickIndex&,

@@ -10,6 +10,8 @@
 //   pass 3  g_i = ds/dQ_i and the taper radial term of ds/dx_i
 //   pass 4  ds/dx_i = -sum_j [ (du/dr)(r_ij)^T (g_i + g_j) + radial ],
 //           F_i -= sum_d dV/ds_d ds_d/dx_i  (or the gradient alone)
+#include <type_traits>
+
 #include "gm_device.h"
 
 namespace gm {
@@ -17,6 +19,7 @@ namespace gm {
 struct Brick {
   int64_t b;
   int32_t hb, H, ob, O, ns;
+  bool wrap;  // pairs may cross a periodic face: minimum image needed
 };
 
 template <typename T>
@@ -24,14 +27,39 @@ __device__ __forceinline__ Brick brick_begin(const CvArgs<T>& a, int64_t brick) 
   Brick k;
   k.b = brick;
   k.hb = k.H = k.ob = k.O = k.ns = 0;
+  k.wrap = true;
   if (k.b < a.bg.nbricks) {
     k.hb = a.bi.hb[k.b];
     k.H = a.bi.hb[k.b + 1] - k.hb;
     k.ob = a.bi.ob[k.b];
     k.O = a.bi.ob[k.b + 1] - k.ob;
     k.ns = k.H < a.bg.cap ? k.H : a.bg.cap;
+    // The halo window of a brick is cells [o-1, o+e] on each axis.  If it
+    // keeps off cells 0 and nc-1 on every axis, its atoms sat at least one
+    // cell (> the skin) from every face at the rebuild, so with coordinates
+    // inside the box (the gather flags any that are not) no pair wraps.
+    int64_t r = k.b;
+    bool edge = false;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const int32_t ib = (int32_t)(r % a.bg.nb[d]);
+      r /= a.bg.nb[d];
+      const int32_t o = ib * a.bg.b[d], e = min(a.bg.b[d], a.bg.nc[d] - o);
+      edge = edge || o < 2 || o + e > a.bg.nc[d] - 2;
+    }
+    k.wrap = edge || a.err[1] != 0;
   }
   return k;
+}
+
+// Run a pass's per-atom loop in the variant for this brick: whole halo in
+// LDS or not, pairs that may wrap or not.
+template <typename T, class F>
+__device__ __forceinline__ auto brick_variant(const CvArgs<T>& a, const Brick& k, F f) {
+  using Y = std::true_type;
+  using N = std::false_type;
+  if (k.H <= a.bg.cap) return k.wrap ? f(Y{}, Y{}) : f(Y{}, N{});
+  return k.wrap ? f(N{}, Y{}) : f(N{}, N{});
 }
 
 template <typename T>
@@ -184,7 +212,7 @@ __device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k,
 // --------------------------------------------------------------------------
 // Pass 1
 // --------------------------------------------------------------------------
-template <typename T, bool CN, bool Q6, bool ALL>
+template <typename T, bool CN, bool Q6, bool ALL, bool WRAP>
 __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lp) {
   double cn_part = 0.0;
   GM_FOR_OWNED(a, k) {
@@ -204,34 +232,29 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
       const int32_t s = st.pop();
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
-      if (pair_vec(pi, pj, a, dx, dy, dz) < a.rc2) wr.push(s);
+      if (pair_vec<WRAP>(pi, pj, a, dx, dy, dz) < a.rc2) wr.push(s);
     }
     wr.flush();
     const int32_t nc = wr.n;
     a.ccnt[(int64_t)(k.ob + o) * TPA + part] = nc;
     // Phase 2: the weighted harmonics over the in-cutoff slots only (the
-    // thread reads back its own sub-row).  The unit vector, the harmonics and
-    // q_lm are formed in FP64 from the pair vector: the bond dots of pass 2
-    // feed two steep logistics, which turn the cancellation error of an FP32
-    // degree-6 polynomial into visible force error; FP64 FMA issues at the
-    // FP32 rate, and the stored rows stay in T.
-    double Q[13];
+    // thread reads back its own sub-row).
+    T Q[13];
 #pragma unroll
-    for (int m = 0; m < 13; m++) Q[m] = 0.0;
+    for (int m = 0; m < 13; m++) Q[m] = T(0);
     T fsum = T(0), cnsum = T(0);
     SlotStream sc;
     sc.init(crow, nc);
     for (int32_t j = 0; j < nc; j++) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, sc.pop());
       T dx, dy, dz;
-      const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
+      const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
       const T r = r2 * rinv;
       if (Q6) {
         T df;
         const T f = taper_w(r, a, df);
-        const double ri64 = rsqrt_fp64(r2);
-        accumulate_y(a.ycd, (double)dx * ri64, (double)dy * ri64, (double)dz * ri64, (double)f, Q);
+        accumulate_y(a.yc, dx * rinv, dy * rinv, dz * rinv, f, Q);
         fsum += f;
       }
       if (CN) {
@@ -248,15 +271,15 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
     if (CN) cnsum = group_sum(cnsum, TPA);
     if (part == 0) {
       if (Q6) {
-        double qq = 0.0;
+        T qq = T(0);
 #pragma unroll
         for (int m = 0; m < 13; m++) qq += Q[m] * Q[m];
-        const double qn = sqrt(qq);
-        const double inv = qn >= 1e-12 ? 1.0 / qn : 0.0;
+        const T qn = g_sqrt(qq);
+        const T inv = qn >= T(1e-12) ? T(1) / qn : T(0);
         T rowv[16];
 #pragma unroll
-        for (int m = 0; m < 13; m++) rowv[m] = (T)(Q[m] * inv);
-        rowv[13] = (T)qn;
+        for (int m = 0; m < 13; m++) rowv[m] = Q[m] * inv;
+        rowv[13] = qn;
         rowv[14] = T(0);
         rowv[15] = fsum;
         store_row16(a.qrow + (int64_t)ri * 16, rowv);
@@ -278,8 +301,9 @@ __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, in
   const Brick k = brick_begin(a, brick);
   stage_pos(a, k, lp);
   __syncthreads();
-  const double cn_part =
-      k.H <= a.bg.cap ? pass1_atoms<T, CN, Q6, true>(a, k, lp) : pass1_atoms<T, CN, Q6, false>(a, k, lp);
+  const double cn_part = brick_variant(a, k, [&](auto all, auto wrap) {
+    return pass1_atoms<T, CN, Q6, decltype(all)::value, decltype(wrap)::value>(a, k, lp);
+  });
   if (CN) {
     const double b = block_sum(cn_part, red);
     if (threadIdx.x == 0) (Q6 ? a.part_b : a.part_a)[blk] = b;
@@ -289,7 +313,7 @@ __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, in
 // --------------------------------------------------------------------------
 // Pass 2
 // --------------------------------------------------------------------------
-template <typename T, bool ALL>
+template <typename T, bool ALL, bool WRAP>
 __device__ __forceinline__ double pass2_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr) {
   double c_part = 0.0;
   GM_FOR_OWNED(a, k) {
@@ -302,7 +326,7 @@ __device__ __forceinline__ double pass2_atoms(const CvArgs<T>& a, const Brick& k
     T nbond = T(0);
     walk_records<ALL>(a, k, lr, a.qrow, a.cut + subrow(a.bg, k.ob, o, part), nc, [&](const vec4_t<T>& pj, const T* qj) {
       T dx, dy, dz;
-      const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
+      const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T r = g_sqrt(r2);
       T df;
       const T f = taper_w(r, a, df);
@@ -331,7 +355,9 @@ __device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, in
   const Brick k = brick_begin(a, brick);
   stage_rows(a, k, a.qrow, lr);
   __syncthreads();
-  const double c_part = k.H <= a.bg.cap ? pass2_atoms<T, true>(a, k, lr) : pass2_atoms<T, false>(a, k, lr);
+  const double c_part = brick_variant(a, k, [&](auto all, auto wrap) {
+    return pass2_atoms<T, decltype(all)::value, decltype(wrap)::value>(a, k, lr);
+  });
   const double b = block_sum(c_part, red);
   if (threadIdx.x == 0) a.part_a[blk] = b;
 }
@@ -339,7 +365,7 @@ __device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, in
 // --------------------------------------------------------------------------
 // Pass 3
 // --------------------------------------------------------------------------
-template <typename T, bool ALL>
+template <typename T, bool ALL, bool WRAP>
 __device__ __forceinline__ void pass3_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr) {
   GM_FOR_OWNED(a, k) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
@@ -355,7 +381,7 @@ __device__ __forceinline__ void pass3_atoms(const CvArgs<T>& a, const Brick& k, 
     T rx = T(0), ry = T(0), rz = T(0);
     walk_records<ALL>(a, k, lr, a.qrow, a.cut + subrow(a.bg, k.ob, o, part), nc, [&](const vec4_t<T>& pj, const T* qj) {
       T dx, dy, dz;
-      const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
+      const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
       const T r = r2 * rinv;
       T df;
@@ -409,17 +435,16 @@ __device__ __forceinline__ void pass3_body(const CvArgs<T>& a, int64_t brick, in
   const Brick k = brick_begin(a, brick);
   stage_rows(a, k, a.qrow, lr);
   __syncthreads();
-  if (k.H <= a.bg.cap)
-    pass3_atoms<T, true>(a, k, lr);
-  else
-    pass3_atoms<T, false>(a, k, lr);
+  brick_variant(a, k, [&](auto all, auto wrap) {
+    pass3_atoms<T, decltype(all)::value, decltype(wrap)::value>(a, k, lr);
+  });
 }
 
 // --------------------------------------------------------------------------
 // Pass 4: chain rule onto positions (u(r) = f(r) v(r_hat) is even in r, so
 // both ends of a pair reuse one Jacobian with g_i + g_j).
 // --------------------------------------------------------------------------
-template <typename T, bool CN, bool ALL>
+template <typename T, bool CN, bool ALL, bool WRAP>
 __device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr) {
   const T seed_q = a.seed ? (T)a.seed[a.dims - 1] : T(1);
   const T seed_cn = (CN && a.seed) ? (T)(a.seed[0] * 2.0 * a.inv_n) : T(0);
@@ -434,7 +459,7 @@ __device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, 
     T cx = T(0), cy = T(0), cz = T(0);
     walk_records<ALL>(a, k, lr, a.grow, a.cut + subrow(a.bg, k.ob, o, part), nc, [&](const vec4_t<T>& pj, const T* gj) {
       T dx, dy, dz;
-      const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
+      const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
       const T r = r2 * rinv;
       const T ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
@@ -494,16 +519,15 @@ __device__ __forceinline__ void pass4_body(const CvArgs<T>& a, int64_t brick, in
   const Brick k = brick_begin(a, brick);
   stage_rows(a, k, a.grow, lr);
   __syncthreads();
-  if (k.H <= a.bg.cap)
-    pass4_atoms<T, CN, true>(a, k, lr);
-  else
-    pass4_atoms<T, CN, false>(a, k, lr);
+  brick_variant(a, k, [&](auto all, auto wrap) {
+    pass4_atoms<T, CN, decltype(all)::value, decltype(wrap)::value>(a, k, lr);
+  });
 }
 
 // --------------------------------------------------------------------------
 // Coordination number alone: forces over the in-cutoff slots of pass 1.
 // --------------------------------------------------------------------------
-template <typename T, bool ALL>
+template <typename T, bool ALL, bool WRAP>
 __device__ __forceinline__ void cn_force_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lp) {
   const T seed = (T)((a.seed ? a.seed[0] : 1.0) * 2.0 * a.inv_n);
   GM_FOR_OWNED(a, k) {
@@ -517,7 +541,7 @@ __device__ __forceinline__ void cn_force_atoms(const CvArgs<T>& a, const Brick& 
     for (int32_t j = 0; j < nc; j++) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, st.pop());
       T dx, dy, dz;
-      const T r2 = pair_vec(pi, pj, a, dx, dy, dz);
+      const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
       const T x = r2 * rinv * a.cn_r0inv;
       const T x2 = x * x;
@@ -542,10 +566,9 @@ __device__ __forceinline__ void cn_force_body(const CvArgs<T>& a, int64_t brick,
   const Brick k = brick_begin(a, brick);
   stage_pos(a, k, lp);
   __syncthreads();
-  if (k.H <= a.bg.cap)
-    cn_force_atoms<T, true>(a, k, lp);
-  else
-    cn_force_atoms<T, false>(a, k, lp);
+  brick_variant(a, k, [&](auto all, auto wrap) {
+    cn_force_atoms<T, decltype(all)::value, decltype(wrap)::value>(a, k, lp);
+  });
 }
 
 // --------------------------------------------------------------------------

@@ -23,14 +23,6 @@ __device__ __forceinline__ void g_sincos(double x, double* s, double* c) { sinco
 __device__ __forceinline__ float g_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double g_sqrt(double x) { return sqrt(x); }
 
-// 1/sqrt(r2) in FP64 from an FP32 argument: hardware FP32 estimate, then one
-// Newton step in FP64 (relative error ~1e-14).
-__device__ __forceinline__ double rsqrt_fp64(float r2f) {
-  const double r2 = (double)r2f, y = (double)__builtin_amdgcn_rsqf(r2f);
-  return y * (1.5 - 0.5 * r2 * y * y);
-}
-__device__ __forceinline__ double rsqrt_fp64(double r2) { return 1.0 / sqrt(r2); }
-
 template <typename T>
 __device__ __forceinline__ T logistic(T x) {
   return g_rcp(T(1) + g_exp(-x));
@@ -78,12 +70,22 @@ __device__ __forceinline__ T mic(T xj, T xi, T L, T invL, T Llo) {
   return (a - b) - k * Llo;
 }
 
-template <typename T>
+// Pair vector r_j - r_i and its square.  WRAP = false is for bricks whose halo
+// holds no cell on a periodic face while every coordinate lies in [0, L): no
+// listed pair can then cross a face, and the plain difference is the minimum
+// image.
+template <bool WRAP, typename T>
 __device__ __forceinline__ T pair_vec(const vec4_t<T>& pi, const vec4_t<T>& pj, const CvArgs<T>& a,
                                       T& dx, T& dy, T& dz) {
-  dx = mic(pj.x, pi.x, a.L[0], a.invL[0], a.Llo[0]);
-  dy = mic(pj.y, pi.y, a.L[1], a.invL[1], a.Llo[1]);
-  dz = mic(pj.z, pi.z, a.L[2], a.invL[2], a.Llo[2]);
+  if constexpr (WRAP) {
+    dx = mic(pj.x, pi.x, a.L[0], a.invL[0], a.Llo[0]);
+    dy = mic(pj.y, pi.y, a.L[1], a.invL[1], a.Llo[1]);
+    dz = mic(pj.z, pi.z, a.L[2], a.invL[2], a.Llo[2]);
+  } else {
+    dx = pj.x - pi.x;
+    dy = pj.y - pi.y;
+    dz = pj.z - pi.z;
+  }
   return dx * dx + dy * dy + dz * dz;
 }
 
@@ -112,12 +114,27 @@ __device__ __forceinline__ void eval_E(const YCoef<T>& c, T z, T E[7]) {
   E[6] = c.e6;
 }
 
+// E_m from the roots: the products stay accurate near the zeros, where the
+// power form loses digits to cancellation (about 2e-6 absolute in FP32 for
+// E_0; the bond dots of pass 2 amplify that through two steep logistics).
+template <typename T>
+__device__ __forceinline__ void eval_E_roots(const YCoef<T>& c, T z, T E[7]) {
+  const T z2 = z * z;
+  E[0] = c.lead[0] * (z2 - c.t[0]) * (z2 - c.t[1]) * (z2 - c.t[2]);
+  E[1] = c.lead[1] * z * (z2 - c.t[3]) * (z2 - c.t[4]);
+  E[2] = c.lead[2] * (z2 - c.t[5]) * (z2 - c.t[6]);
+  E[3] = c.lead[3] * z * (z2 - c.t[7]);
+  E[4] = c.lead[4] * (z2 - c.t[8]);
+  E[5] = z * c.e5;
+  E[6] = c.e6;
+}
+
 // Q += f * v(u), v the real 13-vector of l = 6 harmonics:
 // v_0 = E_0, v_{2m-1} = E_m Re (ux + i uy)^m, v_{2m} = E_m Im (ux + i uy)^m.
 template <typename T>
 __device__ __forceinline__ void accumulate_y(const YCoef<T>& c, T ux, T uy, T uz, T f, T Q[13]) {
   T E[7];
-  eval_E(c, uz, E);
+  eval_E_roots(c, uz, E);
   Q[0] += f * E[0];
   T R = ux, I = uy;
 #pragma unroll

@@ -35,8 +35,11 @@ using vec4_t = typename V4<T>::type;
 // the ratios A_m / A_{m+1} that turn dE_m/dz into a multiple of E_{m+1}.
 template <typename T>
 struct YCoef {
-  T e0[4], e1[3], e2[3], e3[2], e4[2], e5, e6;
-  T rat[6];
+  T e0[4], e1[3], e2[3], e3[2], e4[2], e5, e6;  // E_m as polynomials in z^2 (times z for odd 6-m)
+  T rat[6];                                     // dE_m/dz = rat_m E_{m+1}
+  // The same E_m as lead_m z^(6-m mod 2) prod_k (z^2 - t_k): the roots t of
+  // E_0 (3), E_1 (2), E_2 (2), E_3 (1), E_4 (1), all in (0, 1).
+  T lead[5], t[9];
 };
 
 // Geometry of the cell grid (FP64: the cell ids are part of the bit-exact sort).
@@ -96,7 +99,6 @@ struct CvArgs {
   T cn_r0inv;
   double inv_n;
   YCoef<T> yc;
-  YCoef<double> ycd;  // the same coefficients in FP64 (pass 1 forms q_lm in FP64)
   T* qrow;          // [N][16] by sorted position: qhat(13), |Q|, c', sum f
   T* grow;          // [N][16]: g(13), c'
   vec4_t<T>* frad;  // [N]: sum over taper pairs of (c'_i + c'_j) b_ij f'(r) r_hat
@@ -134,7 +136,8 @@ struct GatherArgs {
   const int32_t* perm;
   int64_t n;
   void* pos_s;
-  int32_t* err;
+  int32_t* err;  // err[0]: error bits; err[1] set when a coordinate lies outside [0, L)
+  float L[3];    // box lengths
 };
 
 // ---- launchers -------------------------------------------------------------
@@ -152,8 +155,7 @@ hipError_t launch_brick_fill(const int32_t* start, const BrickGeom& g, const Bri
                              int32_t* hp, int32_t* halo_rank, int32_t* owned_slot, int32_t* owned_rank,
                              int32_t* owned_hcell, int32_t* err, hipStream_t st);
 template <typename T>
-hipError_t launch_gather(const float4* pos, const int32_t* perm, int64_t n, vec4_t<T>* pos_s,
-                         int32_t* err, hipStream_t st);
+hipError_t launch_gather(const GatherArgs& a, hipStream_t st);
 template <typename T>
 hipError_t launch_build_nbr(const vec4_t<T>* pos_s, const CellGeom& cg, const BrickGeom& g,
                             const BrickIndex& bi, double rl2, uint16_t* nbr, int32_t kmax, int32_t* cnt,
