@@ -25,7 +25,17 @@ MD_STEPS_PER_WINDOW = 10
 HBM_PEAK_GBS = 8000.0
 # FP32 vector peak without packed FP32: 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
-FLOPS_PER_PAIR_P4 = 228
+# Algorithmic flops of k_pass4 per ordered pair inside r_c (FMA = 2): pair
+# vector and r^2 8, 1/r and unit vector 5, g_i + g_j 13, E_m(z) 22, S and its
+# gradient by the complex recurrence 144, tangential projection and
+# accumulation 18.  The minimum image (bookkeeping, not arithmetic of the
+# method) and the taper terms of the pairs in the last 0.2 A are not counted.
+FLOPS_PER_PAIR_P4 = 210
+# k_pass4's HBM traffic as measured by the FETCH_SIZE / WRITE_SIZE counters
+# (scaled by a plain copy kernel of known size), with a digest of the kernel
+# sources it was taken on: reported only while those sources are unchanged.
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_pass4_wz1m_hbm_traffic.txt")
+KERNEL_SOURCES = ("gm_cv.hip", "gm_device.h", "gm_internal.h")
 # k_pass4 per owned atom: slot/rank tables 8, cutoff count 4, position 16, adjoint
 # row 64, taper term 16, permutation 4, force read + write 32
 P4_BYTES_PER_ATOM = 144
@@ -35,6 +45,45 @@ P4_BYTES_PER_ATOM = 144
 # less what is counted), plus the per-step cutoff rows (2 B per pair, written
 # once and read three times, counted as 8 B per pair) and the rebuild / 10
 STEP_BYTES_PER_ATOM = 36 + 80 + 72 + 144 + 144
+
+
+def kernel_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2510_06873_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(root, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """Bytes per k_pass4 launch from the committed counter summary, or None if
+    it is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if line.startswith(("sources_digest:", "bytes_per_launch:")))
+    except OSError:
+        return None
+    if kv.get("sources_digest", "").strip() != kernel_digest():
+        return None
+    return int(kv["bytes_per_launch"].strip())
+
+
+def copy_probe(mib):
+    """A plain device copy of known size (the calibration run for the HBM
+    byte counters): 5 launches of dst.copy_(src) over `mib` MiB."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}), flush=True)
 
 
 def parse():
@@ -52,6 +101,8 @@ def parse():
                     help="time candidate brick shapes / LDS budgets on this system first and use the fastest")
     ap.add_argument("--brick", default=None, help="force the brick shape, e.g. 3x3x4")
     ap.add_argument("--lds-kb", type=int, default=0, help="LDS staging budget per workgroup (KiB)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -83,7 +134,7 @@ def setup(wl_name, args=None):
         from paper_2510_06873_amd.autotune import autotune
 
         p4 = torch.from_numpy(W.as_float4(d["pos"], d["species"])).to(torch.device("cuda", 0))
-        prm, timings = autotune(p4, d["box"], prm, steps=3)
+        prm, timings = autotune(p4, d["box"], prm, steps=3, limit=16)
         tuned = {"brick": list(prm.brick), "lds_kb": prm.lds_kb, "ms_per_md_step": timings}
         log(f"[bench] autotune: {tuned}")
     stream = torch.cuda.Stream()
@@ -222,6 +273,9 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.serving_only:
         print(json.dumps({"serving": serving(args)}), flush=True)
         return
@@ -275,17 +329,15 @@ def main():
     mx, total_entries, cut_pairs = S["pipe"].neighbor_stats(cutoff_pairs=True)
     roofline = None
     if "apply_bias_forces" in per_call_us:
-        # Dominant launch: k_pass4 (apply_bias_forces), bound by FP32 VALU work.
-        # Algorithmic flops per ordered pair inside r_c (FMA = 2): geometry and
-        # minimum image 26, 1/r and unit vector 5, g_i + g_j 13, S and its
-        # gradient by the complex recurrence 166, tangential projection and
-        # accumulation 18: 228.  Peak: 256 CUs x 64 FP32 lanes x 2 x 2.4 GHz
+        # Dominant launch: k_pass4 (apply_bias_forces, one launch per call), bound
+        # by FP32 VALU work.  Peak: 256 CUs x 64 FP32 lanes x 2 x 2.4 GHz
         # (packed FP32 is not used).
         t_us = per_call_us["apply_bias_forces"]
         flops = FLOPS_PER_PAIR_P4 * cut_pairs
         achieved = flops / (t_us * 1e-6) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                    "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                    "traffic": measured_traffic() if args.workload == "wz1m" else None,
                     "kernel": "k_pass4 (apply_bias_forces)", "avg_launch_us": round(t_us, 2),
                     "flops_per_launch": int(flops), "pairs_in_cutoff": int(cut_pairs),
                     "hbm_bytes_per_launch": int(n * P4_BYTES_PER_ATOM + 2 * cut_pairs)}

@@ -26,7 +26,7 @@ def cells_per_axis(box: Sequence[float], r_list: float) -> Tuple[int, int, int]:
     return tuple(int(math.floor(b / r_list)) for b in box)
 
 
-def candidates(n_atoms: int, box: Sequence[float], params: Params, lds_kb: Sequence[int] = (64, 80, 96),
+def candidates(n_atoms: int, box: Sequence[float], params: Params, lds_kb: Sequence[int] = (40, 48, 56, 64),
                limit: int = 10) -> List[Tuple[Tuple[int, int, int], int]]:
     """Feasible (brick, lds_kb) pairs, most owned atoms first."""
     nc = cells_per_axis(box, params.r_c + params.skin)
@@ -40,7 +40,9 @@ def candidates(n_atoms: int, box: Sequence[float], params: Params, lds_kb: Seque
                 for bz in range(1, min(4, nc[2]) + 1):
                     halo = (bx + 2) * (by + 2) * (bz + 2) * rho
                     own = bx * by * bz * rho
-                    if halo * 1.05 > cap or own > 1.2 * 256:
+                    # slots past the LDS capacity are read from global memory,
+                    # so a halo somewhat above the capacity is still a candidate
+                    if halo > 1.25 * cap or own > 1.2 * 256:
                         continue
                     out.append(((bx, by, bz), kb, own, halo / own))
     # prefer many owned atoms per workgroup up to one 256-thread pass, then low halo re-loads
@@ -98,7 +100,10 @@ def autotune(pos4, box, params: Params, steps: int = 3, cache: Optional[str] = N
     best = None
     force4 = torch.zeros((n, 4), dtype=torch.float64 if params.precision == 1 else torch.float32,
                          device=pos4.device)
-    for b, kb in candidates(n, box, params, limit=limit):
+    # the library's own choice (brick (0, 0, 0), default LDS budget) is always timed
+    trials = [((0, 0, 0), 0)] + [c for c in candidates(n, box, params, limit=limit)
+                                 if c != (tuple(params.brick), params.lds_kb)]
+    for b, kb in trials:
         trial = replace(params, brick=b, lds_kb=kb)
         pipe = Pipeline(n, trial)
         pipe.hills_set(np.zeros((1, trial.dims)), np.zeros(1))
@@ -106,7 +111,7 @@ def autotune(pos4, box, params: Params, steps: int = 3, cache: Optional[str] = N
             ms = _time_steps(pipe, pos4, force4, box, steps)
         finally:
             pipe.close()
-        timings[f"{b[0]}x{b[1]}x{b[2]}@{kb}KiB"] = ms
+        timings["default" if kb == 0 else f"{b[0]}x{b[1]}x{b[2]}@{kb}KiB"] = ms
         if best is None or ms < best[0]:
             best = (ms, b, kb)
     if best is None:

@@ -241,6 +241,7 @@ CvArgs<T> make_args(gm_ctx* c) {
 void choose_bricks(gm_ctx* c, const int32_t nc[3]) {
   const int rec = c->fp64 ? slot_bytes<double>(c->has_q6) : slot_bytes<float>(c->has_q6);
   const int cap = c->lds_budget / rec;
+  const int blk = c->fp64 ? BrickBlock<double>::value : BrickBlock<float>::value;
   const double rho = (double)c->n / ((double)nc[0] * nc[1] * nc[2]);
   int best[3] = {1, 1, 1}, best_tpa = 1;
   double best_score = -1.0;
@@ -256,7 +257,7 @@ void choose_bricks(gm_ctx* c, const int32_t nc[3]) {
         const double own = (double)bx * by * bz * rho;
         if (!fixed && halo * 1.05 > cap) continue;
         for (int tpa = 1; tpa <= 4; tpa *= 2) {
-          if (own * tpa > 0.92 * kBlock && !(fixed && tpa == 1)) continue;
+          if (own * tpa > 0.92 * blk && !(fixed && tpa == 1)) continue;
           const double score = own * tpa * (1.0 - 0.02 * halo / own);
           if (score > best_score) {
             best_score = score;

@@ -297,7 +297,7 @@ template <typename T, bool CN, bool Q6>
 __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
   extern __shared__ __align__(16) unsigned char smem[];
   vec4_t<T>* lp = reinterpret_cast<vec4_t<T>*>(smem);
-  __shared__ double red[kBlock / 64];
+  __shared__ double red[BrickBlock<T>::value / 64];
   const Brick k = brick_begin(a, brick);
   stage_pos(a, k, lp);
   __syncthreads();
@@ -351,7 +351,7 @@ template <typename T, bool CN>
 __device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
   extern __shared__ __align__(16) unsigned char smem[];
   vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
-  __shared__ double red[kBlock / 64];
+  __shared__ double red[BrickBlock<T>::value / 64];
   const Brick k = brick_begin(a, brick);
   stage_rows(a, k, a.qrow, lr);
   __syncthreads();
@@ -595,11 +595,12 @@ __device__ __forceinline__ int64_t xcd_remap() {
 }
 
 #define GM_PASS_KERNELS(NAME, BODY, TMPL, TARGS)                                                      \
-  TMPL __global__ __launch_bounds__(kBlock) void NAME(CvArgs<T> a) {                                  \
+  TMPL __global__ __launch_bounds__(BrickBlock<T>::value) void NAME(CvArgs<T> a) {                    \
     const int64_t g = logical_brick(a.bg);                                                            \
     BODY TARGS(a, g, (int32_t)g, (int32_t)gridDim.x);                                                 \
   }                                                                                                   \
-  TMPL __global__ __launch_bounds__(kBlock) void NAME##_batch(const CvArgs<T>* __restrict__ tab,      \
+  TMPL __global__ __launch_bounds__(BrickBlock<T>::value) void NAME##_batch(                           \
+      const CvArgs<T>* __restrict__ tab,                                                              \
                                                               const int32_t* __restrict__ blk_start,  \
                                                               int32_t W) {                            \
     const int64_t g = xcd_remap();                                                                    \
@@ -647,12 +648,12 @@ template <typename T>
 hipError_t launch_q6_forward(const CvArgs<T>& a, bool with_cn, hipStream_t st) {
   const unsigned g = (unsigned)a.bg.blocks;
   if (with_cn) {
-    k_pass1<T, true, true><<<g, kBlock, lds_bytes(a, false), st>>>(a);
-    k_pass2<T, true><<<g, kBlock, lds_bytes(a, true), st>>>(a);
+    k_pass1<T, true, true><<<g, BrickBlock<T>::value, lds_bytes(a, false), st>>>(a);
+    k_pass2<T, true><<<g, BrickBlock<T>::value, lds_bytes(a, true), st>>>(a);
     k_finish<T, true, false><<<1, kBlock, 0, st>>>(a);
   } else {
-    k_pass1<T, false, true><<<g, kBlock, lds_bytes(a, false), st>>>(a);
-    k_pass2<T, false><<<g, kBlock, lds_bytes(a, true), st>>>(a);
+    k_pass1<T, false, true><<<g, BrickBlock<T>::value, lds_bytes(a, false), st>>>(a);
+    k_pass2<T, false><<<g, BrickBlock<T>::value, lds_bytes(a, true), st>>>(a);
     k_finish<T, false, false><<<1, kBlock, 0, st>>>(a);
   }
   return hipGetLastError();
@@ -660,7 +661,7 @@ hipError_t launch_q6_forward(const CvArgs<T>& a, bool with_cn, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_q6_adjoint(const CvArgs<T>& a, hipStream_t st) {
-  k_pass3<T><<<(unsigned)a.bg.blocks, kBlock, lds_bytes(a, true), st>>>(a);
+  k_pass3<T><<<(unsigned)a.bg.blocks, BrickBlock<T>::value, lds_bytes(a, true), st>>>(a);
   return hipGetLastError();
 }
 
@@ -668,22 +669,22 @@ template <typename T>
 hipError_t launch_q6_force(const CvArgs<T>& a, bool with_cn, hipStream_t st) {
   const unsigned g = (unsigned)a.bg.blocks;
   if (with_cn)
-    k_pass4<T, true><<<g, kBlock, lds_bytes(a, true), st>>>(a);
+    k_pass4<T, true><<<g, BrickBlock<T>::value, lds_bytes(a, true), st>>>(a);
   else
-    k_pass4<T, false><<<g, kBlock, lds_bytes(a, true), st>>>(a);
+    k_pass4<T, false><<<g, BrickBlock<T>::value, lds_bytes(a, true), st>>>(a);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_cn_forward(const CvArgs<T>& a, hipStream_t st) {
-  k_pass1<T, true, false><<<(unsigned)a.bg.blocks, kBlock, lds_bytes(a, false), st>>>(a);
+  k_pass1<T, true, false><<<(unsigned)a.bg.blocks, BrickBlock<T>::value, lds_bytes(a, false), st>>>(a);
   k_finish<T, false, true><<<1, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_cn_force(const CvArgs<T>& a, hipStream_t st) {
-  k_cn_force<T><<<(unsigned)a.bg.blocks, kBlock, lds_bytes(a, false), st>>>(a);
+  k_cn_force<T><<<(unsigned)a.bg.blocks, BrickBlock<T>::value, lds_bytes(a, false), st>>>(a);
   return hipGetLastError();
 }
 
@@ -702,34 +703,34 @@ hipError_t launch_pass_batch(int pass, bool with_cn, bool fp_rows, const CvArgs<
   switch (pass) {
     case 1:
       if (with_cn)
-        k_pass1_batch<T, true, true><<<g, kBlock, lds_pos, st>>>(tab, blk_start, W);
+        k_pass1_batch<T, true, true><<<g, BrickBlock<T>::value, lds_pos, st>>>(tab, blk_start, W);
       else
-        k_pass1_batch<T, false, true><<<g, kBlock, lds_pos, st>>>(tab, blk_start, W);
+        k_pass1_batch<T, false, true><<<g, BrickBlock<T>::value, lds_pos, st>>>(tab, blk_start, W);
       break;
     case 2:
       if (with_cn) {
-        k_pass2_batch<T, true><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
+        k_pass2_batch<T, true><<<g, BrickBlock<T>::value, lds_rows, st>>>(tab, blk_start, W);
         k_finish_batch<T, true, false><<<(unsigned)W, kBlock, 0, st>>>(tab);
       } else {
-        k_pass2_batch<T, false><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
+        k_pass2_batch<T, false><<<g, BrickBlock<T>::value, lds_rows, st>>>(tab, blk_start, W);
         k_finish_batch<T, false, false><<<(unsigned)W, kBlock, 0, st>>>(tab);
       }
       break;
     case 3:
-      k_pass3_batch<T><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
+      k_pass3_batch<T><<<g, BrickBlock<T>::value, lds_rows, st>>>(tab, blk_start, W);
       break;
     case 4:
       if (with_cn)
-        k_pass4_batch<T, true><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
+        k_pass4_batch<T, true><<<g, BrickBlock<T>::value, lds_rows, st>>>(tab, blk_start, W);
       else
-        k_pass4_batch<T, false><<<g, kBlock, lds_rows, st>>>(tab, blk_start, W);
+        k_pass4_batch<T, false><<<g, BrickBlock<T>::value, lds_rows, st>>>(tab, blk_start, W);
       break;
     case 5:  // coordination alone: forward
-      k_pass1_batch<T, true, false><<<g, kBlock, lds_pos, st>>>(tab, blk_start, W);
+      k_pass1_batch<T, true, false><<<g, BrickBlock<T>::value, lds_pos, st>>>(tab, blk_start, W);
       k_finish_batch<T, false, true><<<(unsigned)W, kBlock, 0, st>>>(tab);
       break;
     case 6:  // coordination alone: forces
-      k_cn_force_batch<T><<<g, kBlock, lds_pos, st>>>(tab, blk_start, W);
+      k_cn_force_batch<T><<<g, BrickBlock<T>::value, lds_pos, st>>>(tab, blk_start, W);
       break;
     default:
       return hipErrorInvalidValue;

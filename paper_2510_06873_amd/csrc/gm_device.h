@@ -89,7 +89,8 @@ __device__ __forceinline__ T pair_vec(const vec4_t<T>& pi, const vec4_t<T>& pj, 
   return dx * dx + dy * dy + dz * dz;
 }
 
-// Cosine-tapered q6 weight f(r) and f'(r).
+// Cosine-tapered q6 weight f(r) = (1 + cos(pi x))/2, x = (r - r_lo)/D on
+// (r_lo, r_c), 1 below r_lo, and f'(r).
 template <typename T>
 __device__ __forceinline__ T taper_w(T r, const CvArgs<T>& a, T& df) {
   if (r <= a.taper_lo) {
@@ -100,6 +101,37 @@ __device__ __forceinline__ T taper_w(T r, const CvArgs<T>& a, T& df) {
   g_sincos((r - a.taper_lo) * a.pi_over_D, &s, &c);
   df = -a.half_pi_over_D * s;
   return T(0.5) + T(0.5) * c;
+}
+
+// FP32: with t = pi (x - 1/2), |t| <= pi/2, cos(pi x) = -sin t and
+// sin(pi x) = cos t, taken from their Taylor series (through t^13 and t^12:
+// truncation below 7e-9) for every pair, then selected.  The library sincos
+// behind a branch costs every wave that holds one pair in the taper shell,
+// which in disordered regions is nearly every wave.
+__device__ __forceinline__ float taper_w(float r, const CvArgs<float>& a, float& df) {
+  constexpr double kF3 = 6.0, kF5 = kF3 * 20.0, kF7 = kF5 * 42.0, kF9 = kF7 * 72.0, kF11 = kF9 * 110.0,
+                   kF13 = kF11 * 156.0;
+  constexpr double kF2 = 2.0, kF4 = kF2 * 12.0, kF6 = kF4 * 30.0, kF8 = kF6 * 56.0, kF10 = kF8 * 90.0,
+                   kF12 = kF10 * 132.0;
+  const float t = fmaf(r - a.taper_lo, a.pi_over_D, -1.57079632679489662f);
+  const float t2 = t * t;
+  float sn = (float)(-1.0 / kF13);
+  sn = fmaf(sn, t2, (float)(1.0 / kF11));
+  sn = fmaf(sn, t2, (float)(-1.0 / kF9));
+  sn = fmaf(sn, t2, (float)(1.0 / kF7));
+  sn = fmaf(sn, t2, (float)(-1.0 / kF5));
+  sn = fmaf(sn, t2, (float)(1.0 / kF3));
+  sn = fmaf(sn * t2, -t, t);  // sin t
+  float cs = (float)(1.0 / kF12);
+  cs = fmaf(cs, t2, (float)(-1.0 / kF10));
+  cs = fmaf(cs, t2, (float)(1.0 / kF8));
+  cs = fmaf(cs, t2, (float)(-1.0 / kF6));
+  cs = fmaf(cs, t2, (float)(1.0 / kF4));
+  cs = fmaf(cs, t2, (float)(-1.0 / kF2));
+  cs = fmaf(cs, t2, 1.0f);  // cos t
+  const bool in = r > a.taper_lo;
+  df = in ? -a.half_pi_over_D * cs : 0.0f;
+  return in ? fmaf(-0.5f, sn, 0.5f) : 1.0f;
 }
 
 template <typename T>

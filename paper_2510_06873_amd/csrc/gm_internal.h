@@ -30,6 +30,15 @@ struct V4<double> {
 template <typename T>
 using vec4_t = typename V4<T>::type;
 
+// Threads per workgroup of the per-brick kernels.  FP32: 512, so that the two
+// workgroups whose staged halos (78 KiB each) share a CU's 160 KiB of LDS run
+// 4 waves per SIMD within 128 VGPRs.  FP64: 256 (its registers would not fit
+// 4 waves per SIMD).
+template <typename T>
+struct BrickBlock {
+  static constexpr int value = sizeof(T) == 4 ? 512 : 256;
+};
+
 // Coefficients of E_m(z) = A_m d^m P_6/dz^m (z), the z part of the real l = 6
 // harmonics (A_0 = K_0, A_m = sqrt2 (-1)^m K_m), split by parity of z, plus
 // the ratios A_m / A_{m+1} that turn dE_m/dz into a multiple of E_{m+1}.
