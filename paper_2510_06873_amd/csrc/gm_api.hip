@@ -36,7 +36,7 @@ struct gm_ctx {
   int32_t *halo_rank = nullptr, *owned_slot = nullptr, *owned_rank = nullptr, *owned_hcell = nullptr;
   // neighbour rows and the per-step in-cutoff rows (16-bit halo slots)
   uint16_t *nbr = nullptr, *cut = nullptr;
-  int32_t *cnt = nullptr, *ccnt = nullptr, *err = nullptr, *stats = nullptr;
+  int32_t *cnt = nullptr, *ccnt = nullptr, *order = nullptr, *err = nullptr, *stats = nullptr;
   void *pos_s = nullptr, *qrow = nullptr, *grow = nullptr, *frad = nullptr, *nb = nullptr, *cn_atom = nullptr;
   double *part_a = nullptr, *part_b = nullptr, *s_int = nullptr, *V_int = nullptr, *dV_int = nullptr;
   double *centres = nullptr, *heights = nullptr, *bias_part = nullptr;
@@ -194,6 +194,7 @@ CvArgs<T> make_args(gm_ctx* c) {
   a.cnt = c->cnt;
   a.cut = c->cut;
   a.ccnt = c->ccnt;
+  a.order = c->order;
   a.perm = c->perm;
   a.bg = c->bg;
   a.bi = brick_index(c);
@@ -240,7 +241,10 @@ CvArgs<T> make_args(gm_ctx* c) {
 // rarely need a second pass), discounted by the halo re-load ratio.
 void choose_bricks(gm_ctx* c, const int32_t nc[3]) {
   const int rec = c->fp64 ? slot_bytes<double>(c->has_q6) : slot_bytes<float>(c->has_q6);
-  const int cap = c->lds_budget / rec;
+  // pass 1 stages positions only and adds the rank keys; with q6 rows the
+  // row staging of passes 2-4 is the larger user
+  const int rank = c->fp64 ? rank_lds_bytes<double>() : rank_lds_bytes<float>();
+  const int cap = c->has_q6 ? c->lds_budget / rec : (c->lds_budget - rank) / rec;
   const int blk = c->fp64 ? BrickBlock<double>::value : BrickBlock<float>::value;
   const double rho = (double)c->n / ((double)nc[0] * nc[1] * nc[2]);
   int best[3] = {1, 1, 1}, best_tpa = 1;
@@ -352,6 +356,7 @@ void free_all(gm_ctx* c) {
   dfree(c->cut);
   dfree(c->cnt);
   dfree(c->ccnt);
+  dfree(c->order);
   dfree(c->err);
   dfree(c->stats);
   dfree(c->pos_s);
@@ -470,6 +475,7 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   if (rc == GM_OK) rc = dalloc(&c->owned_hcell, n * 4);
   if (rc == GM_OK) rc = dalloc(&c->cnt, n * 4);
   if (rc == GM_OK) rc = dalloc(&c->ccnt, n * 4 * 4);  // up to 4 parts per atom
+  if (rc == GM_OK) rc = dalloc(&c->order, n * 4);
   if (rc == GM_OK) rc = dalloc(&c->nbr, n * (size_t)(c->kmax + 32) * 2);  // tpa sub-rows of kpart entries
   if (rc == GM_OK) rc = dalloc(&c->cut, n * (size_t)(c->kmax + 32) * 2);
   if (rc == GM_OK) rc = dalloc(&c->pos_s, n * 4 * T);

@@ -203,17 +203,77 @@ __device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k,
   }
 }
 
-// Owned atoms of this workgroup's brick: thread -> (atom o, part).
+// Owned atoms of this workgroup's brick: thread -> (atom o, part), in cell
+// order (pass 1) or in the order pass 1 ranked them by their longest
+// in-cutoff part (passes 2-4), so that the lanes of a wave walk rows of
+// similar length (a wave loops as long as its longest lane).
 #define GM_FOR_OWNED(a, k)                                         \
   const int TPA = (a).bg.tpa;                                      \
   const int32_t part = threadIdx.x & (TPA - 1);                    \
   for (int32_t o = threadIdx.x / TPA; o < (k).O; o += blockDim.x / TPA)
 
+#define GM_FOR_RANKED(a, k)                                                 \
+  const int TPA = (a).bg.tpa;                                               \
+  const int32_t part = threadIdx.x & (TPA - 1);                             \
+  for (int32_t r_ = threadIdx.x / TPA; r_ < (k).O; r_ += blockDim.x / TPA) \
+    if (const int32_t o = (a).order[(k).ob + r_]; true)
+
+// Stable counting sort of the owned atoms by key, descending (equal keys keep
+// cell order), written as order[rank] = atom.  Thread t ranks atom t: per-wave
+// histograms in LDS, their prefix over waves and the bucket starts, then the
+// rank among equal keys in the wave from ballots over the key bits.  Bricks
+// with more owned atoms than threads keep cell order.  All threads call.
+template <typename T>
+__device__ __forceinline__ void rank_owned(const CvArgs<T>& a, const Brick& k, int32_t* keys) {
+  constexpr int B = BrickBlock<T>::value, NW = B / 64;
+  int32_t* hist = keys + B;               // [NW][kRankBins]: counts, then offsets
+  int32_t* start = hist + NW * kRankBins;  // [kRankBins]
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  for (int i = t; i < NW * kRankBins; i += B) hist[i] = 0;
+  __syncthreads();
+  if (k.O > B) {
+    for (int32_t o = t; o < k.O; o += B) a.order[k.ob + o] = o;
+    return;
+  }
+  const bool act = t < k.O;
+  const int key = act ? min(keys[t], kRankBins - 1) : 0;
+  if (act) atomicAdd(&hist[w * kRankBins + key], 1);
+  __syncthreads();
+  if (t < kRankBins) {
+    int32_t run = 0;
+    for (int v = 0; v < NW; v++) {
+      const int32_t c = hist[v * kRankBins + t];
+      hist[v * kRankBins + t] = run;
+      run += c;
+    }
+    start[t] = run;  // bucket total for now
+  }
+  __syncthreads();
+  if (t == 0) {
+    int32_t run = 0;
+    for (int v = kRankBins - 1; v >= 0; v--) {
+      const int32_t c = start[v];
+      start[v] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  uint64_t same = __ballot(act);
+  for (int b = 0; b < 7; b++) {
+    const bool bit = (key >> b) & 1;
+    const uint64_t m = __ballot(act && bit);
+    same &= bit ? m : ~m;
+  }
+  const int below = __popcll(same & ((1ull << lane) - 1ull));
+  if (act) a.order[k.ob + start[key] + hist[w * kRankBins + key] + below] = t;
+}
+
 // --------------------------------------------------------------------------
 // Pass 1
 // --------------------------------------------------------------------------
 template <typename T, bool CN, bool Q6, bool ALL, bool WRAP>
-__device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lp) {
+__device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lp,
+                                              int32_t* keys) {
   double cn_part = 0.0;
   GM_FOR_OWNED(a, k) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
@@ -237,6 +297,10 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
     wr.flush();
     const int32_t nc = wr.n;
     a.ccnt[(int64_t)(k.ob + o) * TPA + part] = nc;
+    int32_t longest = nc;
+    if (TPA >= 2) longest = max(longest, __shfl_xor(longest, 1, 64));
+    if (TPA >= 4) longest = max(longest, __shfl_xor(longest, 2, 64));
+    if (part == 0 && o < BrickBlock<T>::value) keys[o] = longest;
     // Phase 2: the weighted harmonics over the in-cutoff slots only (the
     // thread reads back its own sub-row).
     T Q[13];
@@ -301,13 +365,15 @@ __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, in
   const Brick k = brick_begin(a, brick);
   stage_pos(a, k, lp);
   __syncthreads();
+  int32_t* keys = reinterpret_cast<int32_t*>(lp + a.bg.cap);
   const double cn_part = brick_variant(a, k, [&](auto all, auto wrap) {
-    return pass1_atoms<T, CN, Q6, decltype(all)::value, decltype(wrap)::value>(a, k, lp);
+    return pass1_atoms<T, CN, Q6, decltype(all)::value, decltype(wrap)::value>(a, k, lp, keys);
   });
   if (CN) {
     const double b = block_sum(cn_part, red);
     if (threadIdx.x == 0) (Q6 ? a.part_b : a.part_a)[blk] = b;
   }
+  rank_owned(a, k, keys);
 }
 
 // --------------------------------------------------------------------------
@@ -316,7 +382,7 @@ __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, in
 template <typename T, bool ALL, bool WRAP>
 __device__ __forceinline__ double pass2_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr) {
   double c_part = 0.0;
-  GM_FOR_OWNED(a, k) {
+  GM_FOR_RANKED(a, k) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     vec4_t<T> pi;
@@ -367,7 +433,7 @@ __device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, in
 // --------------------------------------------------------------------------
 template <typename T, bool ALL, bool WRAP>
 __device__ __forceinline__ void pass3_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr) {
-  GM_FOR_OWNED(a, k) {
+  GM_FOR_RANKED(a, k) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     vec4_t<T> pi;
@@ -448,7 +514,7 @@ template <typename T, bool CN, bool ALL, bool WRAP>
 __device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr) {
   const T seed_q = a.seed ? (T)a.seed[a.dims - 1] : T(1);
   const T seed_cn = (CN && a.seed) ? (T)(a.seed[0] * 2.0 * a.inv_n) : T(0);
-  GM_FOR_OWNED(a, k) {
+  GM_FOR_RANKED(a, k) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     vec4_t<T> pi;
@@ -530,7 +596,7 @@ __device__ __forceinline__ void pass4_body(const CvArgs<T>& a, int64_t brick, in
 template <typename T, bool ALL, bool WRAP>
 __device__ __forceinline__ void cn_force_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lp) {
   const T seed = (T)((a.seed ? a.seed[0] : 1.0) * 2.0 * a.inv_n);
-  GM_FOR_OWNED(a, k) {
+  GM_FOR_RANKED(a, k) {
     const int32_t si = a.bi.owned_slot[k.ob + o];
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     const vec4_t<T> pi = fetch_pos<ALL>(a, k, lp, si);
@@ -641,7 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_atom_values(CvArgs<T> a, int what, i
 // --------------------------------------------------------------------------
 template <typename T>
 static size_t lds_bytes(const CvArgs<T>& a, bool rows) {
-  return (size_t)a.bg.cap * (size_t)slot_bytes<T>(rows);
+  return (size_t)a.bg.cap * (size_t)slot_bytes<T>(rows) + (rows ? 0 : (size_t)rank_lds_bytes<T>());
 }
 
 template <typename T>
@@ -697,7 +763,8 @@ hipError_t launch_atom_values(const CvArgs<T>& a, int what, int cv_kind, double*
 template <typename T>
 hipError_t launch_pass_batch(int pass, bool with_cn, bool fp_rows, const CvArgs<T>* tab, const int32_t* blk_start,
                              int32_t W, int32_t blocks, int32_t cap, hipStream_t st) {
-  const size_t lds_pos = (size_t)cap * slot_bytes<T>(false), lds_rows = (size_t)cap * slot_bytes<T>(true);
+  const size_t lds_pos = (size_t)cap * slot_bytes<T>(false) + (size_t)rank_lds_bytes<T>(),
+               lds_rows = (size_t)cap * slot_bytes<T>(true);
   (void)fp_rows;
   const unsigned g = (unsigned)blocks;
   switch (pass) {

@@ -107,12 +107,18 @@ __device__ __forceinline__ T taper_w(T r, const CvArgs<T>& a, T& df) {
 // sin(pi x) = cos t, taken from their Taylor series (through t^13 and t^12:
 // truncation below 7e-9) for every pair, then selected.  The library sincos
 // behind a branch costs every wave that holds one pair in the taper shell,
-// which in disordered regions is nearly every wave.
+// which in disordered regions is nearly every wave; a wave with no lane in
+// the shell (ordered regions) skips the series.
 __device__ __forceinline__ float taper_w(float r, const CvArgs<float>& a, float& df) {
   constexpr double kF3 = 6.0, kF5 = kF3 * 20.0, kF7 = kF5 * 42.0, kF9 = kF7 * 72.0, kF11 = kF9 * 110.0,
                    kF13 = kF11 * 156.0;
   constexpr double kF2 = 2.0, kF4 = kF2 * 12.0, kF6 = kF4 * 30.0, kF8 = kF6 * 56.0, kF10 = kF8 * 90.0,
                    kF12 = kF10 * 132.0;
+  const bool in = r > a.taper_lo;
+  if (__ballot(in) == 0) {  // no lane of the wave in the taper shell
+    df = 0.0f;
+    return 1.0f;
+  }
   const float t = fmaf(r - a.taper_lo, a.pi_over_D, -1.57079632679489662f);
   const float t2 = t * t;
   float sn = (float)(-1.0 / kF13);
@@ -129,7 +135,6 @@ __device__ __forceinline__ float taper_w(float r, const CvArgs<float>& a, float&
   cs = fmaf(cs, t2, (float)(1.0 / kF4));
   cs = fmaf(cs, t2, (float)(-1.0 / kF2));
   cs = fmaf(cs, t2, 1.0f);  // cos t
-  const bool in = r > a.taper_lo;
   df = in ? -a.half_pi_over_D * cs : 0.0f;
   return in ? fmaf(-0.5f, sn, 0.5f) : 1.0f;
 }
@@ -293,8 +298,11 @@ __device__ __forceinline__ int64_t subrow(const BrickGeom& g, int32_t ob, int32_
 }
 
 // Sequential reader of one sub-row of 16-bit slots: 8 entries per 16-byte
-// load, the next 8 prefetched, entries popped from registers by funnel
-// shifts (no dynamic register indexing).  All lanes pop in lockstep.
+// load, entries popped from registers by funnel shifts (no dynamic register
+// indexing).  All lanes pop in lockstep.  The next 8 are loaded halfway
+// through the current 8, so the wait before they are used covers a load
+// issued several pairs earlier (the compiler's wait at that point is for all
+// outstanding loads).
 struct SlotStream {
   const uint4* src;
   uint4 cur, nxt;
@@ -307,7 +315,6 @@ struct SlotStream {
     cur = make_uint4(0, 0, 0, 0);
     nxt = cur;
     if (n > 0) cur = src[0];
-    if (n > 8) nxt = src[1];
   }
 
   __device__ __forceinline__ int32_t pop() {
@@ -317,10 +324,8 @@ struct SlotStream {
     cur.z = __builtin_amdgcn_alignbit(cur.w, cur.z, 16);
     cur.w = cur.w >> 16;
     j++;
-    if ((j & 7) == 0) {
-      cur = nxt;
-      if (j + 8 < n) nxt = src[(j >> 3) + 1];
-    }
+    if ((j & 7) == 4 && j + 4 < n) nxt = src[(j >> 3) + 1];
+    if ((j & 7) == 0) cur = nxt;
     return s;
   }
 };

@@ -39,6 +39,15 @@ struct BrickBlock {
   static constexpr int value = sizeof(T) == 4 ? 512 : 256;
 };
 
+// Pass 1 ranks the owned atoms of a brick by their longest in-cutoff part
+// (keys clamped to kRankBins buckets); its LDS scratch after the staged
+// positions: one key per thread, a histogram per wave, the bucket starts.
+constexpr int kRankBins = 128;
+template <typename T>
+constexpr int rank_lds_bytes() {
+  return (BrickBlock<T>::value * (1 + kRankBins / 64) + kRankBins) * 4;
+}
+
 // Coefficients of E_m(z) = A_m d^m P_6/dz^m (z), the z part of the real l = 6
 // harmonics (A_0 = K_0, A_m = sqrt2 (-1)^m K_m), split by parity of z, plus
 // the ratios A_m / A_{m+1} that turn dE_m/dz into a multiple of E_{m+1}.
@@ -96,6 +105,7 @@ struct CvArgs {
   const int32_t* cnt;      // [N] row lengths, brick order
   uint16_t* cut;           // in-cutoff slots of the current step, same layout as nbr
   int32_t* ccnt;           // [N][tpa] in-cutoff counts per part, brick order
+  int32_t* order;          // [N] per brick: owned atoms ranked by longest in-cutoff part (pass 1)
   const int32_t* perm;     // sorted position -> caller's atom id
   BrickGeom bg;
   BrickIndex bi;
