@@ -267,18 +267,120 @@ __global__ __launch_bounds__(kBlock) void k_brick_fill(const int32_t* __restrict
   }
 }
 
-// Full neighbour rows as halo slots.  The pair test is FP64 on the FP32
-// coordinates, no contraction: d = x_j - x_i, d -= L rint(d/L),
+// Full neighbour rows as halo slots.  The decision is the FP64 test on the
+// FP32 coordinates, no contraction: d = x_j - x_i, d -= L rint(d/L),
 // r^2 = (dx dx + dy dy) + dz dz < r_list^2.  (rint(d * (1/L)) picks the same
 // image as rint(d / L) for every pair that can pass the test, since such pairs
-// have |d/L| far from a half integer.)  Candidates are the atoms of the 27
-// cells around the atom's own cell, visited in a fixed order.
+// have |d/L| far from a half integer.)  It is taken in FP32 first: r^2 in
+// FP32 is within 4e-7 (relative) of the FP64 value (pair difference, three
+// squares and two sums, each rounded once), so outside a band of 4e-6 around
+// r_list^2 the FP32 answer is the FP64 one, and only pairs inside the band
+// are tested in FP64.  The bound needs coordinates inside [0, L) (then the
+// minimum image rounds once, at the pair's magnitude); if the gather flagged
+// any outside, every pair takes the FP64 test.  Candidates are the atoms of the 27 cells around the
+// atom's own cell: nine runs of three x-adjacent halo cells, whose slots are
+// contiguous, visited in a fixed order.
+// MODE 0: FP32 plain differences (halo off the faces), 1: FP32 minimum image,
+// 2: FP64 only (coordinates outside the box).
+template <int MODE, typename T>
+__device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, const CellGeom& cg,
+                                           const BrickGeom& g, const BrickIndex& bi, double rl2, uint16_t* nbr,
+                                           int32_t kmax, int32_t* cnt, int32_t* err, const float4* hpos,
+                                           const int32_t* hp, int32_t hb, int32_t ob, int32_t O, int32_t hx,
+                                           int32_t hxy, int32_t& mymax, double& mysum) {
+#pragma clang fp contract(off)
+  float Lf[3], iLf[3], Llo[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    Lf[d] = (float)cg.L[d];
+    iLf[d] = (float)cg.invL[d];
+    Llo[d] = (float)(cg.L[d] - (double)Lf[d]);
+  }
+  const float lo2 = (float)(rl2 * (1.0 - 4e-6)), hi2 = (float)(rl2 * (1.0 + 4e-6));
+  for (int32_t k = threadIdx.x; k < O; k += blockDim.x) {
+    const int32_t si = bi.owned_slot[ob + k];
+    const int32_t hc = bi.owned_hcell[ob + k];
+    float4 pi;
+    if (si < g.cap) {
+      pi = hpos[si];
+    } else {
+      const vec4_t<T> p = pos_s[bi.halo_rank[hb + si]];
+      pi = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
+    }
+    int32_t count = 0;
+    // entry e of the row goes to sub-row e % tpa; each sub-row is written in
+    // 16-byte pieces
+    SlotWriter w0, w1, w2, w3;
+    w0.init(nbr + subrow(g, ob, k, 0));
+    w1.init(nbr + subrow(g, ob, k, g.tpa > 1 ? 1 : 0));
+    w2.init(nbr + subrow(g, ob, k, g.tpa > 2 ? 2 : 0));
+    w3.init(nbr + subrow(g, ob, k, g.tpa > 3 ? 3 : 0));
+    for (int cz = -1; cz <= 1; cz++)
+      for (int cy = -1; cy <= 1; cy++) {
+        const int h = hc + cz * hxy + cy * hx;  // middle cell of the x-run
+        const int32_t se = hp[h + 2];
+        for (int32_t sl = hp[h - 1]; sl < se; sl++) {
+          if (sl == si) continue;
+          float4 pj;
+          if (sl < g.cap) {
+            pj = hpos[sl];
+          } else {
+            const vec4_t<T> p = pos_s[bi.halo_rank[hb + sl]];
+            pj = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
+          }
+          float ex, ey, ez;
+          if constexpr (MODE == 1) {
+            ex = mic(pj.x, pi.x, Lf[0], iLf[0], Llo[0]);
+            ey = mic(pj.y, pi.y, Lf[1], iLf[1], Llo[1]);
+            ez = mic(pj.z, pi.z, Lf[2], iLf[2], Llo[2]);
+          } else {
+            ex = pj.x - pi.x;
+            ey = pj.y - pi.y;
+            ez = pj.z - pi.z;
+          }
+          const float r2f = (ex * ex + ey * ey) + ez * ez;
+          bool in = MODE != 2 && r2f < lo2;
+          if (MODE == 2 || (!in && r2f <= hi2)) {
+            double d0 = (double)pj.x - (double)pi.x;
+            double d1 = (double)pj.y - (double)pi.y;
+            double d2 = (double)pj.z - (double)pi.z;
+            d0 = d0 - cg.L[0] * rint(d0 * cg.invL[0]);
+            d1 = d1 - cg.L[1] * rint(d1 * cg.invL[1]);
+            d2 = d2 - cg.L[2] * rint(d2 * cg.invL[2]);
+            in = d0 * d0 + d1 * d1 + d2 * d2 < rl2;
+          }
+          if (in) {
+            if (count < kmax) {
+              const int prt = count & (g.tpa - 1);
+              if (prt == 0)
+                w0.push(sl);
+              else if (prt == 1)
+                w1.push(sl);
+              else if (prt == 2)
+                w2.push(sl);
+              else
+                w3.push(sl);
+            }
+            count++;
+          }
+        }
+      }
+    w0.flush();
+    if (g.tpa > 1) w1.flush();
+    if (g.tpa > 2) w2.flush();
+    if (g.tpa > 3) w3.flush();
+    cnt[ob + k] = count;
+    if (count > kmax) atomicOr(err, kErrOverflow);
+    mymax = count > mymax ? count : mymax;
+    mysum += (double)count;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_build_nbr(const vec4_t<T>* __restrict__ pos_s, CellGeom cg, BrickGeom g,
                                                       BrickIndex bi, double rl2, uint16_t* __restrict__ nbr,
                                                       int32_t kmax, int32_t* __restrict__ cnt, int32_t* err,
                                                       int32_t* stats) {
-#pragma clang fp contract(off)
   extern __shared__ __align__(16) unsigned char smem[];
   float4* hpos = reinterpret_cast<float4*>(smem);
   __shared__ int32_t hp[kHaloCells + 1];
@@ -287,6 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_build_nbr(const vec4_t<T>* __restric
   const int64_t b = logical_brick(g);
   const bool live = b < g.nbricks;
   int32_t hb = 0, H = 0, ob = 0, O = 0, hx = 0, hxy = 0;
+  int mode = 2;
   if (live) {
     const BrickShape s = brick_shape(b, g);
     hx = s.h[0];
@@ -295,6 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_build_nbr(const vec4_t<T>* __restric
     H = bi.hb[b + 1] - hb;
     ob = bi.ob[b];
     O = bi.ob[b + 1] - ob;
+    mode = err[1] != 0 ? 2 : (halo_touches_face(s, g) ? 1 : 0);
     const int nh = s.h[0] * s.h[1] * s.h[2];
     for (int h = threadIdx.x; h <= nh; h += blockDim.x) hp[h] = bi.hp[b * (kHaloCells + 1) + h];
     const int32_t ns = H < g.cap ? H : g.cap;
@@ -306,71 +410,12 @@ __global__ __launch_bounds__(kBlock) void k_build_nbr(const vec4_t<T>* __restric
   __syncthreads();
   int32_t mymax = 0;
   double mysum = 0.0;
-  for (int32_t k = threadIdx.x; k < O; k += blockDim.x) {
-    const int32_t si = bi.owned_slot[ob + k];
-    const int32_t hc = bi.owned_hcell[ob + k];
-    float4 pi;
-    if (si < g.cap) {
-      pi = hpos[si];
-    } else {
-      const vec4_t<T> p = pos_s[bi.halo_rank[hb + si]];
-      pi = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
-    }
-    const double xi = (double)pi.x, yi = (double)pi.y, zi = (double)pi.z;
-    int32_t count = 0;
-    // entry e of the row goes to sub-row e % tpa; each sub-row is written in
-    // 16-byte pieces
-    SlotWriter w0, w1, w2, w3;
-    w0.init(nbr + subrow(g, ob, k, 0));
-    w1.init(nbr + subrow(g, ob, k, g.tpa > 1 ? 1 : 0));
-    w2.init(nbr + subrow(g, ob, k, g.tpa > 2 ? 2 : 0));
-    w3.init(nbr + subrow(g, ob, k, g.tpa > 3 ? 3 : 0));
-    for (int dz = -1; dz <= 1; dz++)
-      for (int dy = -1; dy <= 1; dy++)
-        for (int dx = -1; dx <= 1; dx++) {
-          const int h = hc + dz * hxy + dy * hx + dx;
-          const int32_t se = hp[h + 1];
-          for (int32_t sl = hp[h]; sl < se; sl++) {
-            if (sl == si) continue;
-            float4 pj;
-            if (sl < g.cap) {
-              pj = hpos[sl];
-            } else {
-              const vec4_t<T> p = pos_s[bi.halo_rank[hb + sl]];
-              pj = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
-            }
-            double d0 = (double)pj.x - xi;
-            double d1 = (double)pj.y - yi;
-            double d2 = (double)pj.z - zi;
-            d0 = d0 - cg.L[0] * rint(d0 * cg.invL[0]);
-            d1 = d1 - cg.L[1] * rint(d1 * cg.invL[1]);
-            d2 = d2 - cg.L[2] * rint(d2 * cg.invL[2]);
-            const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            if (r2 < rl2) {
-              if (count < kmax) {
-                const int prt = count & (g.tpa - 1);
-                if (prt == 0)
-                  w0.push(sl);
-                else if (prt == 1)
-                  w1.push(sl);
-                else if (prt == 2)
-                  w2.push(sl);
-                else
-                  w3.push(sl);
-              }
-              count++;
-            }
-          }
-        }
-    w0.flush();
-    if (g.tpa > 1) w1.flush();
-    if (g.tpa > 2) w2.flush();
-    if (g.tpa > 3) w3.flush();
-    cnt[ob + k] = count;
-    if (count > kmax) atomicOr(err, kErrOverflow);
-    mymax = count > mymax ? count : mymax;
-    mysum += (double)count;
-  }
+  if (mode == 0)
+    build_rows<0, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, hx, hxy, mymax, mysum);
+  else if (mode == 1)
+    build_rows<1, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, hx, hxy, mymax, mysum);
+  else
+    build_rows<2, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, hx, hxy, mymax, mysum);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const int32_t v = __shfl_down(mymax, o, 64);

@@ -34,20 +34,9 @@ __device__ __forceinline__ Brick brick_begin(const CvArgs<T>& a, int64_t brick) 
     k.ob = a.bi.ob[k.b];
     k.O = a.bi.ob[k.b + 1] - k.ob;
     k.ns = k.H < a.bg.cap ? k.H : a.bg.cap;
-    // The halo window of a brick is cells [o-1, o+e] on each axis.  If it
-    // keeps off cells 0 and nc-1 on every axis, its atoms sat at least one
-    // cell (> the skin) from every face at the rebuild, so with coordinates
-    // inside the box (the gather flags any that are not) no pair wraps.
-    int64_t r = k.b;
-    bool edge = false;
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-      const int32_t ib = (int32_t)(r % a.bg.nb[d]);
-      r /= a.bg.nb[d];
-      const int32_t o = ib * a.bg.b[d], e = min(a.bg.b[d], a.bg.nc[d] - o);
-      edge = edge || o < 2 || o + e > a.bg.nc[d] - 2;
-    }
-    k.wrap = edge || a.err[1] != 0;
+    // plain pair differences unless the halo touches a face or the gather
+    // flagged a coordinate outside the box
+    k.wrap = halo_touches_face(brick_shape(k.b, a.bg), a.bg) || a.err[1] != 0;
   }
   return k;
 }

@@ -274,6 +274,17 @@ __device__ __forceinline__ BrickShape brick_shape(int64_t b, const BrickGeom& g)
   return s;
 }
 
+// A brick's halo window is cells [o-1, o+e] on each axis.  If it keeps off
+// cells 0 and nc-1 on every axis, its atoms sat at least one cell (more than
+// half the skin) from every face at the rebuild, so while all coordinates lie
+// inside the box no pair of its halo crosses a face.
+__device__ __forceinline__ bool halo_touches_face(const BrickShape& s, const BrickGeom& g) {
+  bool edge = false;
+#pragma unroll
+  for (int d = 0; d < 3; d++) edge = edge || s.o[d] < 2 || s.o[d] + s.e[d] > g.nc[d] - 2;
+  return edge;
+}
+
 // Global cell id of halo cell (hx, hy, hz) of a brick (halo coordinates start at -1).
 __device__ __forceinline__ int32_t halo_cell_id(const BrickShape& s, const BrickGeom& g, int hx, int hy, int hz) {
   const int32_t cx = wrap_cell(s.o[0] - 1 + hx, g.nc[0]);

@@ -91,6 +91,30 @@ def test_neighbors_random_boxes_edge(orc):
             assert np.array_equal(rows[i], nb[off[i]:off[i + 1]])
 
 
+def test_neighbors_pairs_at_the_cutoff(orc):
+    """Simple-cubic lattice with spacing r_list (4 A), jittered by about one
+    FP32 ulp: every nearest pair lies within a few ulps of r_list, where the
+    build's FP32 test defers to the FP64 one; pairs across the faces included."""
+    from paper_2510_06873_amd import Params, Pipeline
+
+    rng = np.random.default_rng(11)
+    m = 7
+    box = np.full(3, 4.0 * m)
+    idx = np.stack(np.meshgrid(*[np.arange(m)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    pos = (idx * 4.0 + rng.normal(0.0, 2e-6, idx.shape)) % box
+    pos = pos.astype(np.float32)
+    n = len(pos)
+    pipe = Pipeline(n, Params(cv_kind=2, r_c=4.0, skin=0.0, sigma=[1.0], hill_capacity=4, max_neighbors=64))
+    pipe.build_neighbors(to_dev(W.as_float4(pos)), box)
+    assert pipe.status(True) == 0
+    off, nb = orc.neighbors(pos, box, 4.0, method="brute")
+    counts = np.diff(off)
+    assert 0 < counts.sum() < 6 * n  # some of the nearest pairs fall inside, some outside
+    rows = gpu_neighbor_sets(pipe)
+    for i in range(n):
+        assert np.array_equal(rows[i], nb[off[i]:off[i + 1]]), i
+
+
 # ---------------------------------------------------------------------------
 # q6 count: CV, per-atom values, gradient and forces
 # ---------------------------------------------------------------------------
@@ -198,6 +222,10 @@ def test_q6_coordinates_outside_the_box(orc):
         assert abs(s - refs[tag][0]) <= 1e-5 * abs(refs[tag][0]), tag
         assert rel_force_err(F, refs[tag][1]) <= 1e-4, tag
     pipe.build_neighbors_checked(to_dev(W.as_float4(pos_u, sp)), box)  # lists from the shifted ones
+    off_u, nb_u = orc.neighbors(pos_u, box, 4.0)
+    rows = gpu_neighbor_sets(pipe)
+    for i in np.random.default_rng(6).choice(n, 500, replace=False):
+        assert np.array_equal(rows[i], nb_u[off_u[i]:off_u[i + 1]]), i
     for tag, p in (("out", pos_u), ("in", pos)):
         s, F = step(p)
         assert abs(s - refs[tag][0]) <= 1e-5 * abs(refs[tag][0]), tag
