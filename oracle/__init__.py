@@ -62,10 +62,15 @@ def _load():
     lib.gmo_q6_forward.argtypes = [dp, C.c_int64, dp, ip64, ip32, C.POINTER(Q6Params)] + [dp] * 7
     lib.gmo_q6_forward.restype = C.c_double
     lib.gmo_q6_gradient.argtypes = [dp, C.c_int64, dp, ip64, ip32, C.POINTER(Q6Params), dp]
-    lib.gmo_bias.argtypes = [dp, dp, C.c_int64, C.c_int, dp, dp, dp, dp]
+    lib.gmo_bias.argtypes = [dp, dp, C.c_int64, C.c_int, dp, dp, dp, dp, dp]
     lib.gmo_wt_height.argtypes = [C.c_double] * 4
     lib.gmo_wt_height.restype = C.c_double
-    lib.gmo_deposit_sequence.argtypes = [dp, C.c_int64, C.c_int, dp, C.c_double, C.c_double, C.c_double, dp]
+    lib.gmo_deposit_sequence.argtypes = [dp, C.c_int64, C.c_int, dp, dp, C.c_double, C.c_double, C.c_double, dp]
+    lib.gmo_torsions.argtypes = [dp, dp, ip32, C.c_int64, dp, dp]
+    lib.gmo_nearest_distance.argtypes = [dp, dp, C.c_int32, ip32, C.c_int64, ip32, dp]
+    lib.gmo_nearest_distance.restype = C.c_double
+    lib.gmo_fes_reweight.argtypes = [dp, dp, C.c_int64, C.c_int, dp, dp, ip32, C.c_double, dp]
+    lib.gmo_fes_hills.argtypes = [dp, dp, C.c_int64, C.c_int, dp, dp, C.c_double, dp, dp, ip32, dp]
     _lib = lib
     return lib
 
@@ -208,8 +213,13 @@ def q6_gradient(pos, box, nl, prm: Q6Params):
 # --------------------------------------------------------------------------
 # Bias and hills
 # --------------------------------------------------------------------------
-def bias(centres, heights, sigma, s):
-    """(V, dV/ds) of the Gaussian-hill sum at CV value s."""
+def _period(period, dims):
+    return None if period is None else _d(np.broadcast_to(np.asarray(period, np.float64), (dims,)))
+
+
+def bias(centres, heights, sigma, s, period=None):
+    """(V, dV/ds) of the Gaussian-hill sum at CV value s; period[d] > 0 makes
+    dimension d periodic (nearest image of s - c)."""
     lib = _load()
     s = _d(np.atleast_1d(s))
     dims = s.shape[0]
@@ -217,7 +227,9 @@ def bias(centres, heights, sigma, s):
     h = _d(heights)
     V = np.zeros(1)
     g = np.zeros(dims)
-    lib.gmo_bias(_p(c), _p(h), h.shape[0], dims, _p(_d(np.atleast_1d(sigma))), _p(s), _p(V), _p(g))
+    per = _period(period, dims)
+    lib.gmo_bias(_p(c), _p(h), h.shape[0], dims, _p(_d(np.atleast_1d(sigma))), _p(per) if per is not None else None,
+                 _p(s), _p(V), _p(g))
     return float(V[0]), g
 
 
@@ -225,15 +237,71 @@ def wt_height(w0, gamma, kBT, V):
     return _load().gmo_wt_height(float(w0), float(gamma), float(kBT), float(V))
 
 
-def deposit_sequence(centres, sigma, w0, gamma, kBT):
+def deposit_sequence(centres, sigma, w0, gamma, kBT, period=None):
     """Heights of hills deposited in index order at the given centres."""
     lib = _load()
     sigma = _d(np.atleast_1d(sigma))
     dims = sigma.shape[0]
     c = _d(np.asarray(centres).reshape(-1, dims))
     h = np.zeros(c.shape[0])
-    lib.gmo_deposit_sequence(_p(c), c.shape[0], dims, _p(sigma), float(w0), float(gamma), float(kBT), _p(h))
+    per = _period(period, dims)
+    lib.gmo_deposit_sequence(_p(c), c.shape[0], dims, _p(sigma), _p(per) if per is not None else None,
+                             float(w0), float(gamma), float(kBT), _p(h))
     return h
+
+
+def torsions(pos, box, quads):
+    """(phi[m], grad[m][4][3]) of the torsion angles of the atom quadruples
+    (IUPAC sign, minimum images)."""
+    lib = _load()
+    x = _d(np.asarray(pos)[:, :3])
+    q = np.ascontiguousarray(np.asarray(quads, np.int32).reshape(-1, 4))
+    phi = np.zeros(q.shape[0])
+    g = np.zeros((q.shape[0], 4, 3))
+    lib.gmo_torsions(_p(x), _p(_d(box)), q.ctypes.data_as(C.POINTER(C.c_int32)), q.shape[0], _p(phi), _p(g))
+    return phi, g
+
+
+def nearest_distance(pos, box, centre, members):
+    """(s, nearest atom, unit vector centre -> nearest) over the member set."""
+    lib = _load()
+    x = _d(np.asarray(pos)[:, :3])
+    m = np.ascontiguousarray(np.asarray(members, np.int32))
+    arg = np.zeros(1, np.int32)
+    u = np.zeros(3)
+    s = lib.gmo_nearest_distance(_p(x), _p(_d(box)), int(centre), m.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 m.shape[0], arg.ctypes.data_as(C.POINTER(C.c_int32)), _p(u))
+    return float(s), int(arg[0]), u
+
+
+def fes_reweight(s, V, lo, hi, nbins, kBT):
+    """F per bin (bin id i0 + nb0 i1) from samples (s_t, V_t) of a biased run."""
+    lib = _load()
+    s = np.asarray(s, np.float64)
+    dims = 1 if s.ndim == 1 else s.shape[1]
+    s = _d(s.reshape(-1, dims))
+    V = _d(V)
+    nb = np.ascontiguousarray(np.atleast_1d(nbins).astype(np.int32))
+    F = np.zeros(int(np.prod(nb)))
+    lib.gmo_fes_reweight(_p(s), _p(V), s.shape[0], dims, _p(_d(np.atleast_1d(lo))), _p(_d(np.atleast_1d(hi))),
+                         nb.ctypes.data_as(C.POINTER(C.c_int32)), float(kBT), _p(F))
+    return F
+
+
+def fes_hills(centres, heights, sigma, lo, hi, nbins, gamma=0.0, period=None):
+    """F = -V (or -gamma/(gamma-1) V, well-tempered) on the grid of bin centres."""
+    lib = _load()
+    sigma = _d(np.atleast_1d(sigma))
+    dims = sigma.shape[0]
+    c = _d(np.asarray(centres).reshape(-1, dims))
+    h = _d(heights)
+    nb = np.ascontiguousarray(np.atleast_1d(nbins).astype(np.int32))
+    F = np.zeros(int(np.prod(nb)))
+    per = _period(period, dims)
+    lib.gmo_fes_hills(_p(c), _p(h), h.shape[0], dims, _p(sigma), _p(per) if per is not None else None,
+                      float(gamma), _p(_d(np.atleast_1d(lo))), _p(_d(np.atleast_1d(hi))),
+                      nb.ctypes.data_as(C.POINTER(C.c_int32)), _p(F))
+    return F
 
 
 # --------------------------------------------------------------------------

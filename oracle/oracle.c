@@ -535,20 +535,31 @@ void gmo_q6_gradient(const double *pos, int64_t n, const double box[3],
 /*   dV/ds_d = -sum_k h_k exp(...) (s_d - c_kd) / sigma_d^2                  */
 /* Sums run in hill index order.                                             */
 /* ------------------------------------------------------------------------ */
+/* The distance of a CV value from a hill centre along dimension d.  A
+ * periodic CV (period[d] > 0, e.g. a torsion angle with period 2 pi) uses the
+ * nearest periodic image of the difference.                                 */
+static double cv_delta(double s, double c, const double *period, int d) {
+  double x = s - c;
+  if (period && period[d] > 0.0) x -= period[d] * rint(x / period[d]);
+  return x;
+}
+
 void gmo_bias(const double *centres, const double *heights, int64_t K, int dims,
-              const double *sigma, const double *s, double *V, double *dVds) {
+              const double *sigma, const double *period, const double *s,
+              double *V, double *dVds) {
   double v = 0.0;
   double g[8] = {0};
   for (int64_t k = 0; k < K; k++) {
     double arg = 0.0;
     for (int d = 0; d < dims; d++) {
-      double x = s[d] - centres[k * dims + d];
+      double x = cv_delta(s[d], centres[k * dims + d], period, d);
       arg += x * x / (2.0 * sigma[d] * sigma[d]);
     }
     double e = heights[k] * exp(-arg);
     v += e;
     for (int d = 0; d < dims; d++)
-      g[d] += -e * (s[d] - centres[k * dims + d]) / (sigma[d] * sigma[d]);
+      g[d] += -e * cv_delta(s[d], centres[k * dims + d], period, d) /
+              (sigma[d] * sigma[d]);
   }
   *V = v;
   if (dVds)
@@ -565,11 +576,149 @@ double gmo_wt_height(double w0, double gamma, double kBT, double V) {
 
 /* Deposit a sequence of hills in index order: height k uses hills 0..k-1.   */
 void gmo_deposit_sequence(const double *centres, int64_t K, int dims,
-                          const double *sigma, double w0, double gamma,
-                          double kBT, double *heights) {
+                          const double *sigma, const double *period, double w0,
+                          double gamma, double kBT, double *heights) {
   for (int64_t k = 0; k < K; k++) {
     double V;
-    gmo_bias(centres, heights, k, dims, sigma, &centres[k * dims], &V, NULL);
+    gmo_bias(centres, heights, k, dims, sigma, period, &centres[k * dims], &V,
+             NULL);
     heights[k] = gmo_wt_height(w0, gamma, kBT, V);
   }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Torsion angle of four atoms, the CV pair (Phi, Psi) of the paper's        */
+/* alanine dipeptide study (Results, "Alanine dipeptide torsion"), IUPAC     */
+/* sign.  b1 = x2 - x1, b2 = x3 - x2, b3 = x4 - x3 (minimum images),          */
+/* n1 = b1 x b2, n2 = b2 x b3:                                                */
+/*   phi = atan2(|b2| b1.n2, n1.n2)   in (-pi, pi].                           */
+/* Gradient: the end atoms move phi along the plane normals,                  */
+/*   dphi/dx1 = -|b2|/|n1|^2 n1,   dphi/dx4 = |b2|/|n2|^2 n2,                 */
+/* and with p = b1.b2/|b2|^2, q = b3.b2/|b2|^2 the middle atoms take          */
+/*   dphi/dx2 = -(1 + p) dphi/dx1 + q dphi/dx4,                               */
+/*   dphi/dx3 = -(1 + q) dphi/dx4 + p dphi/dx1                                */
+/* (the four sum to zero: phi is invariant under translation).               */
+/* ------------------------------------------------------------------------ */
+static void cross3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+void gmo_torsions(const double *pos, const double box[3], const int32_t *quads,
+                  int64_t count, double *phi, double *grad) {
+  for (int64_t t = 0; t < count; t++) {
+    const int32_t *q = &quads[4 * t];
+    double b1[3], b2[3], b3[3], n1[3], n2[3];
+    min_image(&pos[3 * q[0]], &pos[3 * q[1]], box, b1);
+    min_image(&pos[3 * q[1]], &pos[3 * q[2]], box, b2);
+    min_image(&pos[3 * q[2]], &pos[3 * q[3]], box, b3);
+    cross3(b1, b2, n1);
+    cross3(b2, b3, n2);
+    const double lb2 = sqrt(dot3(b2, b2));
+    phi[t] = atan2(lb2 * dot3(b1, n2), dot3(n1, n2));
+    if (!grad) continue;
+    double *g = &grad[12 * t];
+    const double n1n1 = dot3(n1, n1), n2n2 = dot3(n2, n2), b2b2 = lb2 * lb2;
+    const double p = dot3(b1, b2) / b2b2, qq = dot3(b3, b2) / b2b2;
+    for (int a = 0; a < 3; a++) {
+      const double g1 = -lb2 / n1n1 * n1[a], g4 = lb2 / n2n2 * n2[a];
+      g[0 + a] = g1;
+      g[3 + a] = -(1.0 + p) * g1 + qq * g4;
+      g[6 + a] = -(1.0 + qq) * g4 + p * g1;
+      g[9 + a] = g4;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Distance from one atom to the nearest atom of a set (minimum image), the  */
+/* CV of the paper's rutile study (Results, "Water dissociation on rutile    */
+/* (110) surface": a surface oxygen and its nearest hydrogen).  Ties go to   */
+/* the earliest member of the set; the centre itself is skipped.  The CV is  */
+/* the distance of that pair, so ds/dx_centre = -u and ds/dx_nearest = u,    */
+/* u the unit vector from the centre to the nearest atom.                    */
+/* ------------------------------------------------------------------------ */
+double gmo_nearest_distance(const double *pos, const double box[3],
+                            int32_t centre, const int32_t *set, int64_t count,
+                            int32_t *nearest, double *u) {
+  double best = INFINITY;
+  int32_t arg = -1;
+  for (int64_t k = 0; k < count; k++) {
+    if (set[k] == centre) continue;
+    double d[3];
+    min_image(&pos[3 * centre], &pos[3 * set[k]], box, d);
+    const double r = sqrt(sq_dist(d));
+    if (r < best) {
+      best = r;
+      arg = set[k];
+      if (u)
+        for (int a = 0; a < 3; a++) u[a] = d[a] / r;
+    }
+  }
+  if (nearest) *nearest = arg;
+  return best;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Free energy from a biased trajectory by reweighting (paper, Methods: the  */
+/* unbiased probability is the biased average of delta(s - s(R)) e^{beta V}  */
+/* over the biased average of e^{beta V}, and F = -(1/beta) log P).  Samples */
+/* (s_t, V_t), t = 0..T-1, with s_t of dims <= 2 components; bin i_d =       */
+/* floor((s_d - lo_d) / w_d), w_d = (hi_d - lo_d) / nb_d, bin id i_0 +        */
+/* nb_0 i_1.  Samples outside the grid count in the denominator only.  The   */
+/* weights exp((V_t - V_max)/kBT) share one factor that cancels in P, and    */
+/* each sum runs in sample order.  F = -kBT log P per bin; +inf where no     */
+/* sample fell.                                                               */
+/* ------------------------------------------------------------------------ */
+void gmo_fes_reweight(const double *s, const double *V, int64_t T, int dims,
+                      const double *lo, const double *hi, const int32_t *nb,
+                      double kBT, double *F) {
+  int64_t nbins = 1;
+  for (int d = 0; d < dims; d++) nbins *= nb[d];
+  double vmax = -INFINITY;
+  for (int64_t t = 0; t < T; t++)
+    if (V[t] > vmax) vmax = V[t];
+  double *num = (double *)calloc((size_t)nbins, sizeof(double));
+  double den = 0.0;
+  for (int64_t t = 0; t < T; t++) {
+    const double w = exp((V[t] - vmax) / kBT);
+    den += w;
+    int64_t bin = 0, stride = 1, inside = 1;
+    for (int d = 0; d < dims; d++) {
+      const double width = (hi[d] - lo[d]) / nb[d];
+      const double x = floor((s[t * dims + d] - lo[d]) / width);
+      if (!(x >= 0.0 && x < nb[d])) inside = 0;
+      else bin += (int64_t)x * stride;
+      stride *= nb[d];
+    }
+    if (inside) num[bin] += w;
+  }
+  for (int64_t b = 0; b < nbins; b++)
+    F[b] = num[b] > 0.0 ? -kBT * log(num[b] / den) : INFINITY;
+  free(num);
+}
+
+/* Free energy from the deposited bias itself on the grid of bin centres:
+ * F = -V (plain metadynamics) or F = -gamma/(gamma - 1) V (well-tempered,
+ * Barducci, Bussi and Parrinello 2008), up to a constant.                   */
+void gmo_fes_hills(const double *centres, const double *heights, int64_t K,
+                   int dims, const double *sigma, const double *period,
+                   double gamma, const double *lo, const double *hi,
+                   const int32_t *nb, double *F) {
+  const int32_t n1 = dims > 1 ? nb[1] : 1;
+  const double scale = gamma > 1.0 ? gamma / (gamma - 1.0) : 1.0;
+  for (int32_t i1 = 0; i1 < n1; i1++)
+    for (int32_t i0 = 0; i0 < nb[0]; i0++) {
+      double g[2];
+      g[0] = lo[0] + (i0 + 0.5) * ((hi[0] - lo[0]) / nb[0]);
+      if (dims > 1) g[1] = lo[1] + (i1 + 0.5) * ((hi[1] - lo[1]) / nb[1]);
+      double v;
+      gmo_bias(centres, heights, K, dims, sigma, period, g, &v, NULL);
+      F[(int64_t)i1 * nb[0] + i0] = -scale * v;
+    }
 }
