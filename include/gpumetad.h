@@ -68,10 +68,16 @@ extern "C" {
  *                 n_i  = sum_j f(r_ij) / (1 + exp(-(d_ij - bond_d0)/bond_w))
  *                 c_i  = 1 / (1 + exp(-(n_i - count_n0)/count_w))
  *               with f = 1 below r_c - taper and a cosine taper to 0 at r_c.
- * GM_CV_COORD_Q6 the 2-D CV s = (s_COORD, s_Q6COUNT) over the same r_c.      */
+ * GM_CV_COORD_Q6 the 2-D CV s = (s_COORD, s_Q6COUNT) over the same r_c.
+ * GM_CV_EXTERNAL a context that holds only the hills of a CV the caller
+ *               computes (params.dims components, e.g. the torsions or the
+ *               nearest distance below): gm_bias_eval and gm_deposit_hill
+ *               with an explicit s_dev, gm_hills_*, gm_fes_hills; the atom
+ *               calls return GM_ERR_STATE and n_atoms may be 0.             */
 #define GM_CV_COORD 1
 #define GM_CV_Q6COUNT 2
 #define GM_CV_COORD_Q6 3
+#define GM_CV_EXTERNAL 4
 
 #define GM_FP32 0
 #define GM_FP64 1
@@ -94,6 +100,11 @@ typedef struct gm_params {
   int32_t max_neighbors; /* neighbour-list row width (rounded up to 4)        */
   int32_t brick[3];      /* cells per brick and axis (1..4); 0 = chosen per build */
   int32_t lds_kb;        /* LDS staging budget per workgroup in KiB; 0 = auto */
+  double period[2];      /* period of each CV dimension (e.g. 2 pi for an angle);
+                            hill distances use the nearest periodic image;
+                            0 = not periodic                                  */
+  int32_t dims;          /* CV dimensions of a GM_CV_EXTERNAL context (1 or 2);
+                            ignored by the other kinds                        */
 } gm_params;
 
 typedef struct gm_ctx gm_ctx;
@@ -242,6 +253,73 @@ int gm_batch_deposit(gm_batch* batch);
 int gm_batch_values(gm_batch* batch, double* s_dev, double* V_dev);
 
 /* Library version string. */
+/* ---- CVs of a few atoms ----------------------------------------------------
+ * Context-free calls enqueued on hip_stream (NULL = the null stream), FP64 on
+ * the FP32 coordinates pos4 (dev float32 [n_atoms][4]) with the minimum image
+ * in the orthorhombic box (host double[3]).  Index arrays live on the device;
+ * an index outside [0, n_atoms) makes the CV it belongs to NaN and adds no
+ * force (it is never dereferenced).  force4 is dev [n_atoms][4] of the given
+ * precision (GM_FP32 / GM_FP64), caller's atom order, updated in place with
+ *   F_i <- F_i - sum dV/ds . ds/dx_i
+ * The CV values feed a GM_CV_EXTERNAL context (gm_bias_eval, gm_deposit_hill
+ * with explicit s_dev; period 2 pi for an angle). */
+
+/* Torsion angles of count atom quadruples (paper, Results, "Alanine
+ * dipeptide torsion": Phi(C-N-CA-C) and Psi(N-CA-C-N)), IUPAC sign:
+ *   b1 = x2 - x1, b2 = x3 - x2, b3 = x4 - x3,
+ *   phi = atan2(|b2| b1.(b2 x b3), (b1 x b2).(b2 x b3))  in (-pi, pi].
+ * quads_dev: dev int32[count][4]; phi_dev: dev double[count] (written).
+ * 0 <= count <= 65536. */
+int gm_torsions(const float* pos4, int64_t n_atoms, const int32_t* quads_dev, int32_t count, const double* box,
+                double* phi_dev, void* hip_stream);
+
+/* Torsion bias forces with dVdphi_dev (dev double[count]); the torsions are
+ * summed one after another, so atoms shared by several torsions get a fixed
+ * order. */
+int gm_torsion_forces(const float* pos4, int64_t n_atoms, const int32_t* quads_dev, int32_t count, const double* box,
+                      const double* dVdphi_dev, void* force4, int32_t precision, void* hip_stream);
+
+/* Distance from atom centre to the nearest atom of a set (paper, Results,
+ * "Water dissociation on rutile (110) surface": a surface oxygen and its
+ * nearest hydrogen):  s = min_{j in set, j != centre} |mic(x_j - x_centre)|,
+ * ties to the earliest member.  members_dev: dev int32[count], count >= 1;
+ * s_dev: dev double[1]; nearest_dev: dev int32[1] or NULL (the atom). */
+int gm_nearest_distance(const float* pos4, int64_t n_atoms, int32_t centre, const int32_t* members_dev,
+                        int32_t count, const double* box, double* s_dev, int32_t* nearest_dev, void* hip_stream);
+
+/* Its bias force: F_centre += dV/ds u, F_nearest -= dV/ds u, u the unit
+ * vector from the centre to the nearest atom (dVds_dev: dev double[1]). */
+int gm_nearest_distance_forces(const float* pos4, int64_t n_atoms, int32_t centre, const int32_t* members_dev,
+                               int32_t count, const double* box, const double* dVds_dev, void* force4,
+                               int32_t precision, void* hip_stream);
+
+/* Lattice parameters as CVs (paper, Results, "B4-B1 phase transition":
+ * the triaxial lattice parameters of an NPT run): s = (L_x, L_y, L_z)[:dims]
+ * need no kernel; the bias acts on the cell through the virial the barostat
+ * adds, W_aa = -L_a dV/dL_a (host arrays of dims <= 3 values). */
+int gm_lattice_virial(const double* box, const double* dVdL, int32_t dims, double* virial);
+
+/* ---- free energy ------------------------------------------------------------
+ * Reweighting of a biased run (paper, Methods: P(s) = <delta(s - s(R))
+ * e^{beta V}> / <e^{beta V}> over the biased ensemble, F = -(1/beta) log P).
+ * Samples s_dev dev double[T][dims] and V_dev dev double[T] (the bias at each
+ * sample); bins i_d = floor((s_d - lo_d) / w_d), w_d = (hi_d - lo_d)/nbins_d,
+ * bin id i_0 + nbins_0 i_1; samples off the grid count in the denominator
+ * only.  F_dev: dev double[prod nbins] (written), -kBT log P per bin, +inf
+ * where no sample fell.  The per-bin sums use FP64 atomics: reproducible to
+ * about 1e-15 relative, not bit for bit.  Host lo, hi (double[dims]), nbins
+ * (int32[dims]); dims 1 or 2; at most 2^24 bins.  Temporary device memory
+ * comes from the stream-ordered allocator. */
+int gm_fes_reweight(const double* s_dev, const double* V_dev, int64_t T, int32_t dims, const double* lo,
+                    const double* hi, const int32_t* nbins, double kBT, double* F_dev, void* hip_stream);
+
+/* The free energy from the context's hills on the grid of bin centres
+ * (lo_d + (i_d + 1/2) w_d): F = -V (plain metadynamics) or
+ * F = -gamma/(gamma - 1) V (well-tempered), hills summed in index order.
+ * Same grid arguments and F_dev layout as gm_fes_reweight (dims = the
+ * context's). */
+int gm_fes_hills(gm_ctx* ctx, const double* lo, const double* hi, const int32_t* nbins, double* F_dev);
+
 const char* gm_version(void);
 
 #ifdef __cplusplus

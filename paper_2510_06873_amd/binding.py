@@ -20,7 +20,7 @@ ERRORS = {
     -1: "GM_ERR_INVALID_ARG", -2: "GM_ERR_OOM", -3: "GM_ERR_HIP", -4: "GM_ERR_BOX_TOO_SMALL",
     -5: "GM_ERR_NEIGHBOR_OVERFLOW", -6: "GM_ERR_HILL_CAPACITY", -7: "GM_ERR_NONFINITE", -8: "GM_ERR_STATE",
 }
-CV_COORD, CV_Q6COUNT, CV_COORD_Q6 = 1, 2, 3
+CV_COORD, CV_Q6COUNT, CV_COORD_Q6, CV_EXTERNAL = 1, 2, 3, 4
 FP32, FP64 = 0, 1
 ATOM_Q6, ATOM_NB, ATOM_C, ATOM_CN = 1, 2, 3, 4
 
@@ -30,7 +30,8 @@ EXPORTS = (
     "gm_cv_backward", "gm_apply_bias_forces", "gm_deposit_hill", "gm_hills_get", "gm_hills_set", "gm_status",
     "gm_strerror", "gm_neighbor_stats", "gm_reserve_neighbors", "gm_copy_cell_list", "gm_copy_neighbors",
     "gm_atom_values", "gm_version", "gm_batch_create", "gm_batch_destroy", "gm_batch_build", "gm_batch_step",
-    "gm_batch_deposit", "gm_batch_values",
+    "gm_batch_deposit", "gm_batch_values", "gm_torsions", "gm_torsion_forces", "gm_nearest_distance",
+    "gm_nearest_distance_forces", "gm_lattice_virial", "gm_fes_reweight", "gm_fes_hills",
 )
 
 
@@ -48,6 +49,7 @@ class GmParams(C.Structure):
         ("bond_d0", C.c_double), ("bond_w", C.c_double), ("count_n0", C.c_double), ("count_w", C.c_double),
         ("sigma", C.c_double * 2), ("w0", C.c_double), ("gamma", C.c_double), ("kBT", C.c_double),
         ("hill_capacity", C.c_int64), ("max_neighbors", C.c_int32), ("brick", C.c_int32 * 3), ("lds_kb", C.c_int32),
+        ("period", C.c_double * 2), ("dims", C.c_int32),
     ]
 
 
@@ -84,6 +86,14 @@ def _load() -> C.CDLL:
         "gm_batch_step": ([vp], C.c_int),
         "gm_batch_deposit": ([vp], C.c_int),
         "gm_batch_values": ([vp, vp, vp], C.c_int),
+        "gm_torsions": ([vp, C.c_int64, vp, C.c_int32, dp, vp, vp], C.c_int),
+        "gm_torsion_forces": ([vp, C.c_int64, vp, C.c_int32, dp, vp, vp, C.c_int32, vp], C.c_int),
+        "gm_nearest_distance": ([vp, C.c_int64, C.c_int32, vp, C.c_int32, dp, vp, vp, vp], C.c_int),
+        "gm_nearest_distance_forces": ([vp, C.c_int64, C.c_int32, vp, C.c_int32, dp, vp, vp, C.c_int32, vp],
+                                       C.c_int),
+        "gm_lattice_virial": ([dp, dp, C.c_int32, dp], C.c_int),
+        "gm_fes_reweight": ([vp, vp, C.c_int64, C.c_int32, dp, dp, ip32, C.c_double, vp, vp], C.c_int),
+        "gm_fes_hills": ([vp, dp, dp, ip32, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -140,17 +150,23 @@ class Params:
     max_neighbors: int = 64
     brick: Sequence[int] = (0, 0, 0)  # cells per brick and axis; 0 = chosen per build
     lds_kb: int = 0                   # LDS staging budget per workgroup; 0 = auto
+    period: Sequence[float] = (0.0, 0.0)  # per CV dimension; 0 = not periodic (2 pi for an angle)
+    external_dims: int = 1            # CV dimensions of a CV_EXTERNAL context
 
     @property
     def dims(self) -> int:
+        if self.cv_kind == CV_EXTERNAL:
+            return int(self.external_dims)
         return 2 if self.cv_kind == CV_COORD_Q6 else 1
 
     def to_c(self) -> GmParams:
         sig = list(self.sigma) + [0.0] * (2 - len(self.sigma))
+        per = list(self.period) + [0.0] * (2 - len(self.period))
         return GmParams(self.cv_kind, self.precision, self.r_c, self.skin, self.taper, self.cn_r0,
                         self.bond_d0, self.bond_w, self.count_n0, self.count_w, (C.c_double * 2)(*sig[:2]),
                         self.w0, self.gamma, self.kBT, self.hill_capacity, self.max_neighbors,
-                        (C.c_int32 * 3)(*[int(b) for b in self.brick]), int(self.lds_kb))
+                        (C.c_int32 * 3)(*[int(b) for b in self.brick]), int(self.lds_kb),
+                        (C.c_double * 2)(*[float(x) for x in per[:2]]), int(self.external_dims))
 
 
 class Pipeline:
@@ -260,6 +276,16 @@ class Pipeline:
         _check(_lib.gm_hills_get(self.h, cen.ctypes.data_as(C.POINTER(C.c_double)),
                                  hts.ctypes.data_as(C.POINTER(C.c_double)), max(K, 1), C.byref(k)), "gm_hills_get")
         return cen[:K], hts[:K]
+
+    def fes_hills(self, lo, hi, nbins, F=None):
+        """F = -V (or -gamma/(gamma-1) V) on the grid of bin centres, bin id i0 + nb0 i1."""
+        lo, hi, nb = _grid(lo, hi, nbins, self.dims)
+        total = 1
+        for x in nb:
+            total *= x
+        F = self.torch.empty(total, dtype=self.torch.float64, device=self.s.device) if F is None else F
+        _check(_lib.gm_fes_hills(self.h, lo, hi, nb, _ptr(F, total, self.torch.float64, "F")), "gm_fes_hills")
+        return F
 
     def hills_set(self, centres, heights):
         import numpy as np
@@ -406,3 +432,107 @@ class Batch:
 
 def version() -> str:
     return _lib.gm_version().decode()
+
+
+# ---- CVs of a few atoms, lattice parameters, free energy ---------------------
+def _grid(lo, hi, nbins, dims):
+    lo = [float(x) for x in (lo if hasattr(lo, "__len__") else [lo])]
+    hi = [float(x) for x in (hi if hasattr(hi, "__len__") else [hi])]
+    nb = [int(x) for x in (nbins if hasattr(nbins, "__len__") else [nbins])]
+    if not (len(lo) == len(hi) == len(nb) == dims):
+        raise ValueError(f"expected {dims} grid dimensions")
+    return (C.c_double * dims)(*lo), (C.c_double * dims)(*hi), (C.c_int32 * dims)(*nb)
+
+
+def _stream(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _box(box):
+    return (C.c_double * 3)(*[float(b) for b in box])
+
+
+def _force(force4, n):
+    import torch
+
+    if force4.dtype not in (torch.float32, torch.float64):
+        raise ValueError("force4: expected float32 or float64")
+    return _ptr(force4, 4 * n, None, "force4"), (FP64 if force4.dtype == torch.float64 else FP32)
+
+
+def torsions(pos4, quads, box, phi=None, stream=None):
+    """Torsion angles (IUPAC sign) of the atom quadruples quads (dev int32 [m][4])."""
+    import torch
+
+    n, m = pos4.shape[0], quads.shape[0]
+    phi = torch.empty(m, dtype=torch.float64, device=pos4.device) if phi is None else phi
+    _check(_lib.gm_torsions(_ptr(pos4, 4 * n, torch.float32, "pos4"), n, _ptr(quads, 4 * m, torch.int32, "quads"),
+                            m, _box(box), _ptr(phi, m, torch.float64, "phi"), _stream(stream)), "gm_torsions")
+    return phi
+
+
+def torsion_forces(pos4, quads, box, dVdphi, force4, stream=None):
+    """force4 -= sum_t dV/dphi_t dphi_t/dx (in place)."""
+    import torch
+
+    n, m = pos4.shape[0], quads.shape[0]
+    fp, prec = _force(force4, n)
+    _check(_lib.gm_torsion_forces(_ptr(pos4, 4 * n, torch.float32, "pos4"), n,
+                                  _ptr(quads, 4 * m, torch.int32, "quads"), m, _box(box),
+                                  _ptr(dVdphi, m, torch.float64, "dVdphi"), fp, prec, _stream(stream)),
+           "gm_torsion_forces")
+    return force4
+
+
+def nearest_distance(pos4, centre, members, box, s=None, nearest=None, stream=None):
+    """Distance from atom centre to the nearest atom of members (dev int32 [k])."""
+    import torch
+
+    n, k = pos4.shape[0], members.shape[0]
+    s = torch.empty(1, dtype=torch.float64, device=pos4.device) if s is None else s
+    _check(_lib.gm_nearest_distance(_ptr(pos4, 4 * n, torch.float32, "pos4"), n, int(centre),
+                                    _ptr(members, k, torch.int32, "members"), k, _box(box),
+                                    _ptr(s, 1, torch.float64, "s"), _ptr(nearest, 1, torch.int32, "nearest"),
+                                    _stream(stream)), "gm_nearest_distance")
+    return s
+
+
+def nearest_distance_forces(pos4, centre, members, box, dVds, force4, stream=None):
+    import torch
+
+    n, k = pos4.shape[0], members.shape[0]
+    fp, prec = _force(force4, n)
+    _check(_lib.gm_nearest_distance_forces(_ptr(pos4, 4 * n, torch.float32, "pos4"), n, int(centre),
+                                           _ptr(members, k, torch.int32, "members"), k, _box(box),
+                                           _ptr(dVds, 1, torch.float64, "dVds"), fp, prec, _stream(stream)),
+           "gm_nearest_distance_forces")
+    return force4
+
+
+def lattice_virial(box, dVdL):
+    """W_aa = -L_a dV/dL_a for lattice-parameter CVs (host values)."""
+    d = len(dVdL)
+    out = (C.c_double * d)()
+    _check(_lib.gm_lattice_virial((C.c_double * 3)(*[float(b) for b in box]),
+                                  (C.c_double * d)(*[float(x) for x in dVdL]), d, out), "gm_lattice_virial")
+    return list(out)
+
+
+def fes_reweight(s, V, lo, hi, nbins, kBT, F=None, stream=None):
+    """F per bin from samples s (dev double [T] or [T][dims]) and their bias V (dev double [T])."""
+    import torch
+
+    T = V.shape[0]
+    dims = 1 if s.dim() == 1 else s.shape[1]
+    lo_c, hi_c, nb_c = _grid(lo, hi, nbins, dims)
+    total = 1
+    for i in range(dims):
+        total *= nb_c[i]
+    F = torch.empty(total, dtype=torch.float64, device=V.device) if F is None else F
+    _check(_lib.gm_fes_reweight(_ptr(s, T * dims, torch.float64, "s"), _ptr(V, T, torch.float64, "V"), T, dims,
+                                lo_c, hi_c, nb_c, float(kBT), _ptr(F, total, torch.float64, "F"), _stream(stream)),
+           "gm_fes_reweight")
+    return F

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgpumetad.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("gm_build.hip", "gm_cv.hip", "gm_bias.hip", "gm_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("gm_build.hip", "gm_cv.hip", "gm_bias.hip", "gm_cvs.hip", "gm_api.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

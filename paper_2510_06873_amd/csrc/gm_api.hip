@@ -18,6 +18,7 @@ struct gm_ctx {
   int dims = 1;
   bool fp64 = false;
   bool has_q6 = false, has_cn = false;
+  bool external = false;  // GM_CV_EXTERNAL: hills only
   double r_list = 0.0;
   double box[3] = {0, 0, 0};
   CellGeom geom;
@@ -152,9 +153,19 @@ void make_ycoef(YCoef<T>& c) {
 }
 
 int validate(const gm_params* p, int64_t n) {
-  if (!p || n < 1 || n > (int64_t)INT32_MAX / 2) return GM_ERR_INVALID_ARG;
-  if (p->cv_kind < GM_CV_COORD || p->cv_kind > GM_CV_COORD_Q6) return GM_ERR_INVALID_ARG;
+  if (!p || p->cv_kind < GM_CV_COORD || p->cv_kind > GM_CV_EXTERNAL) return GM_ERR_INVALID_ARG;
   if (p->precision != GM_FP32 && p->precision != GM_FP64) return GM_ERR_INVALID_ARG;
+  for (int d = 0; d < 2; d++)
+    if (!(p->period[d] >= 0.0) || !isfinite(p->period[d])) return GM_ERR_INVALID_ARG;
+  if (p->cv_kind == GM_CV_EXTERNAL) {
+    if (n < 0 || (p->dims != 1 && p->dims != 2)) return GM_ERR_INVALID_ARG;
+    for (int d = 0; d < p->dims; d++)
+      if (!(p->sigma[d] > 0.0)) return GM_ERR_INVALID_ARG;
+    if (!(p->w0 >= 0.0) || !(p->gamma == 0.0 || p->gamma > 1.0)) return GM_ERR_INVALID_ARG;
+    if (p->gamma > 1.0 && !(p->kBT > 0.0)) return GM_ERR_INVALID_ARG;
+    return p->hill_capacity < 0 ? GM_ERR_INVALID_ARG : GM_OK;
+  }
+  if (n < 1 || n > (int64_t)INT32_MAX / 2) return GM_ERR_INVALID_ARG;
   if (!(p->r_c > 0.0) || !(p->skin >= 0.0) || !isfinite(p->r_c + p->skin)) return GM_ERR_INVALID_ARG;
   const bool q6 = p->cv_kind != GM_CV_COORD, cn = p->cv_kind != GM_CV_Q6COUNT;
   if (q6 && (!(p->taper > 0.0) || p->taper > p->r_c || !(p->bond_w > 0.0) || !(p->count_w > 0.0)))
@@ -331,6 +342,7 @@ BiasArgs make_bias(gm_ctx* c, const double* s, int deposit) {
   }
   b.w0 = c->p.w0;
   b.wt_scale = c->p.gamma == 0.0 ? 0.0 : 1.0 / (c->p.kBT * (c->p.gamma - 1.0));
+  for (int d = 0; d < 2; d++) b.period[d] = d < c->dims ? c->p.period[d] : 0.0;
   b.part = c->bias_part;
   b.err = c->err;
   return b;
@@ -439,10 +451,11 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   c->p = *params;
   c->n = n_atoms;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  c->dims = params->cv_kind == GM_CV_COORD_Q6 ? 2 : 1;
+  c->external = params->cv_kind == GM_CV_EXTERNAL;
+  c->dims = c->external ? params->dims : (params->cv_kind == GM_CV_COORD_Q6 ? 2 : 1);
   c->fp64 = params->precision == GM_FP64;
-  c->has_q6 = params->cv_kind != GM_CV_COORD;
-  c->has_cn = params->cv_kind != GM_CV_Q6COUNT;
+  c->has_q6 = !c->external && params->cv_kind != GM_CV_COORD;
+  c->has_cn = !c->external && params->cv_kind != GM_CV_Q6COUNT;
   c->r_list = params->r_c + params->skin;
   int32_t km = params->max_neighbors > 0 ? params->max_neighbors : 64;
   c->kmax = (km + 3) / 4 * 4;
@@ -465,7 +478,7 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
     allow_build_lds(c->lds_budget);
   }
 
-  const size_t n = (size_t)n_atoms, T = c->fp64 ? 8 : 4;
+  const size_t n = c->external ? 1 : (size_t)n_atoms, T = c->fp64 ? 8 : 4;  // no atom buffers for external CVs
   const size_t cap = (size_t)(params->hill_capacity > 0 ? params->hill_capacity : 1);
   int rc = GM_OK;
   if (rc == GM_OK) rc = dalloc(&c->cell, n * 4);
@@ -563,6 +576,7 @@ static int reserve_bricks(gm_ctx* c) {
 }
 
 int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
+  if (c && c->external) return GM_ERR_STATE;
   if (!c || !pos4 || !box || !aligned(pos4, 16)) return GM_ERR_INVALID_ARG;
   int32_t nc[3];
   for (int a = 0; a < 3; a++) {
@@ -753,6 +767,7 @@ int gm_neighbor_stats(gm_ctx* c, int32_t* max_count, int64_t* total, int64_t* cu
 }
 
 int gm_reserve_neighbors(gm_ctx* c, int32_t max_neighbors) {
+  if (c && c->external) return GM_ERR_STATE;
   if (!c || max_neighbors < 1 || max_neighbors > 4096) return GM_ERR_INVALID_ARG;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
   dfree(c->nbr);
@@ -765,6 +780,7 @@ int gm_reserve_neighbors(gm_ctx* c, int32_t max_neighbors) {
 }
 
 int gm_copy_cell_list(gm_ctx* c, int32_t* perm_dev, int32_t* cell_start_dev, int32_t* ncell) {
+  if (c && c->external) return GM_ERR_STATE;
   if (!c || !perm_dev) return GM_ERR_INVALID_ARG;
   if (!c->built) return GM_ERR_STATE;
   if (hipMemcpyAsync(perm_dev, c->perm, (size_t)c->n * 4, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
@@ -778,6 +794,7 @@ int gm_copy_cell_list(gm_ctx* c, int32_t* perm_dev, int32_t* cell_start_dev, int
 }
 
 int gm_copy_neighbors(gm_ctx* c, int32_t* nbr_dev, int32_t* cnt_dev, int32_t* row_width) {
+  if (c && c->external) return GM_ERR_STATE;
   if (!c) return GM_ERR_INVALID_ARG;
   if (!c->built) return GM_ERR_STATE;
   if (row_width) *row_width = c->kmax;
@@ -787,6 +804,7 @@ int gm_copy_neighbors(gm_ctx* c, int32_t* nbr_dev, int32_t* cnt_dev, int32_t* ro
 }
 
 int gm_atom_values(gm_ctx* c, int what, double* dst_dev) {
+  if (c && c->external) return GM_ERR_STATE;
   if (!c || !dst_dev || what < GM_ATOM_Q6 || what > GM_ATOM_CN) return GM_ERR_INVALID_ARG;
   if (!c->fwd) return GM_ERR_STATE;
   if ((what != GM_ATOM_CN && !c->has_q6) || (what == GM_ATOM_CN && !c->has_cn)) return GM_ERR_INVALID_ARG;
@@ -938,6 +956,99 @@ void free_batch(gm_batch* B) {
 
 extern "C" {
 
+// ---- CVs of a few atoms, lattice parameters, free energy --------------------
+namespace {
+bool box_ok(const double* b) {
+  return b && b[0] > 0.0 && b[1] > 0.0 && b[2] > 0.0 && isfinite(b[0]) && isfinite(b[1]) && isfinite(b[2]);
+}
+bool force_ok(const void* f, int32_t precision) {
+  return f && (precision == GM_FP32 || precision == GM_FP64) && aligned(f, precision == GM_FP64 ? 32 : 16);
+}
+}  // namespace
+
+int gm_torsions(const float* pos4, int64_t n_atoms, const int32_t* quads_dev, int32_t count, const double* box,
+                double* phi_dev, void* hip_stream) {
+  if (count < 0 || count > kMaxTorsions) return GM_ERR_INVALID_ARG;
+  if (count == 0) return GM_OK;
+  if (!pos4 || !aligned(pos4, 16) || n_atoms < 1 || !quads_dev || !aligned(quads_dev, 4) || !phi_dev ||
+      !aligned(phi_dev, 8) || !box_ok(box))
+    return GM_ERR_INVALID_ARG;
+  return hip_rc(launch_torsions(reinterpret_cast<const float4*>(pos4), n_atoms, quads_dev, count, box, phi_dev,
+                                reinterpret_cast<hipStream_t>(hip_stream)));
+}
+
+int gm_torsion_forces(const float* pos4, int64_t n_atoms, const int32_t* quads_dev, int32_t count, const double* box,
+                      const double* dVdphi_dev, void* force4, int32_t precision, void* hip_stream) {
+  if (count < 0 || count > kMaxTorsions) return GM_ERR_INVALID_ARG;
+  if (count == 0) return GM_OK;
+  if (!pos4 || !aligned(pos4, 16) || n_atoms < 1 || !quads_dev || !aligned(quads_dev, 4) || !dVdphi_dev ||
+      !aligned(dVdphi_dev, 8) || !force_ok(force4, precision) || !box_ok(box))
+    return GM_ERR_INVALID_ARG;
+  return hip_rc(launch_torsion_forces(reinterpret_cast<const float4*>(pos4), n_atoms, quads_dev, count, box,
+                                      dVdphi_dev, force4, precision == GM_FP64,
+                                      reinterpret_cast<hipStream_t>(hip_stream)));
+}
+
+int gm_nearest_distance(const float* pos4, int64_t n_atoms, int32_t centre, const int32_t* members_dev,
+                        int32_t count, const double* box, double* s_dev, int32_t* nearest_dev, void* hip_stream) {
+  if (!pos4 || !aligned(pos4, 16) || n_atoms < 1 || centre < 0 || centre >= n_atoms || !members_dev ||
+      !aligned(members_dev, 4) || count < 1 || !s_dev || !aligned(s_dev, 8) ||
+      (nearest_dev && !aligned(nearest_dev, 4)) || !box_ok(box))
+    return GM_ERR_INVALID_ARG;
+  return hip_rc(launch_nearest(reinterpret_cast<const float4*>(pos4), n_atoms, centre, members_dev, count, box, s_dev,
+                               nearest_dev, nullptr, nullptr, false, reinterpret_cast<hipStream_t>(hip_stream)));
+}
+
+int gm_nearest_distance_forces(const float* pos4, int64_t n_atoms, int32_t centre, const int32_t* members_dev,
+                               int32_t count, const double* box, const double* dVds_dev, void* force4,
+                               int32_t precision, void* hip_stream) {
+  if (!pos4 || !aligned(pos4, 16) || n_atoms < 1 || centre < 0 || centre >= n_atoms || !members_dev ||
+      !aligned(members_dev, 4) || count < 1 || !dVds_dev || !aligned(dVds_dev, 8) || !force_ok(force4, precision) ||
+      !box_ok(box))
+    return GM_ERR_INVALID_ARG;
+  return hip_rc(launch_nearest(reinterpret_cast<const float4*>(pos4), n_atoms, centre, members_dev, count, box,
+                               nullptr, nullptr, dVds_dev, force4, precision == GM_FP64,
+                               reinterpret_cast<hipStream_t>(hip_stream)));
+}
+
+int gm_lattice_virial(const double* box, const double* dVdL, int32_t dims, double* virial) {
+  if (!box || !dVdL || !virial || dims < 1 || dims > 3) return GM_ERR_INVALID_ARG;
+  for (int a = 0; a < dims; a++) virial[a] = -box[a] * dVdL[a];
+  return GM_OK;
+}
+
+int gm_fes_reweight(const double* s_dev, const double* V_dev, int64_t T, int32_t dims, const double* lo,
+                    const double* hi, const int32_t* nbins, double kBT, double* F_dev, void* hip_stream) {
+  if (!s_dev || !V_dev || !F_dev || !lo || !hi || !nbins || T < 1 || (dims != 1 && dims != 2) || !(kBT > 0.0) ||
+      !aligned(s_dev, 8) || !aligned(V_dev, 8) || !aligned(F_dev, 8))
+    return GM_ERR_INVALID_ARG;
+  int64_t total = 1;
+  for (int d = 0; d < dims; d++) {
+    if (nbins[d] < 1 || !(hi[d] > lo[d]) || !isfinite(lo[d]) || !isfinite(hi[d])) return GM_ERR_INVALID_ARG;
+    total *= nbins[d];
+  }
+  if (total > kMaxFesBins) return GM_ERR_INVALID_ARG;
+  static bool lds_ready = false;
+  if (!lds_ready) {
+    allow_fes_lds();
+    lds_ready = true;
+  }
+  return hip_rc(launch_fes_reweight(s_dev, V_dev, T, dims, lo, hi, nbins, kBT, F_dev,
+                                    reinterpret_cast<hipStream_t>(hip_stream)));
+}
+
+int gm_fes_hills(gm_ctx* c, const double* lo, const double* hi, const int32_t* nbins, double* F_dev) {
+  if (!c || !lo || !hi || !nbins || !F_dev || !aligned(F_dev, 8)) return GM_ERR_INVALID_ARG;
+  int64_t total = 1;
+  for (int d = 0; d < c->dims; d++) {
+    if (nbins[d] < 1 || !(hi[d] > lo[d]) || !isfinite(lo[d]) || !isfinite(hi[d])) return GM_ERR_INVALID_ARG;
+    total *= nbins[d];
+  }
+  if (total > kMaxFesBins) return GM_ERR_INVALID_ARG;
+  const double scale = c->p.gamma > 1.0 ? c->p.gamma / (c->p.gamma - 1.0) : 1.0;
+  return hip_rc(launch_fes_hills(make_bias(c, nullptr, 0), lo, hi, nbins, scale, F_dev, c->stream));
+}
+
 int gm_batch_create(gm_batch** out, gm_ctx* const* walkers, int32_t count, const float* const* pos4,
                     void* const* force4, void* hip_stream) {
   if (!out) return GM_ERR_INVALID_ARG;
@@ -950,7 +1061,8 @@ int gm_batch_create(gm_batch** out, gm_ctx* const* walkers, int32_t count, const
   for (int32_t i = 0; i < count; i++) {
     gm_ctx* c = walkers[i];
     const size_t vs = B->fp64 ? 32 : 16;
-    if (!c || !pos4[i] || !force4[i] || c->fp64 != B->fp64 || !aligned(pos4[i], 16) || !aligned(force4[i], vs)) {
+    if (!c || c->external || !pos4[i] || !force4[i] || c->fp64 != B->fp64 || !aligned(pos4[i], 16) ||
+        !aligned(force4[i], vs)) {
       delete B;
       return GM_ERR_INVALID_ARG;
     }

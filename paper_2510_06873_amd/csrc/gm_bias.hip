@@ -8,6 +8,12 @@ namespace gm {
 // --------------------------------------------------------------------------
 // Gaussian-hill bias (FP64): evaluation, or deposition of one hill.
 // --------------------------------------------------------------------------
+// s - c, or its nearest periodic image for a periodic dimension.
+__device__ __forceinline__ double cv_delta(double s, double c, double period) {
+  const double x = s - c;
+  return period > 0.0 ? x - period * rint(x / period) : x;
+}
+
 __device__ __forceinline__ void bias_body(const BiasArgs& a, int32_t blk, int32_t nblk) {
   __shared__ double red[kBlock / 64];
   const int64_t K = *a.count;
@@ -15,11 +21,11 @@ __device__ __forceinline__ void bias_body(const BiasArgs& a, int32_t blk, int32_
   double v = 0.0, g0 = 0.0, g1 = 0.0;
   const int64_t stride = (int64_t)nblk * blockDim.x;
   for (int64_t k = (int64_t)blk * blockDim.x + threadIdx.x; k < K; k += stride) {
-    const double x0 = s[0] - a.centres[k * a.dims];
+    const double x0 = cv_delta(s[0], a.centres[k * a.dims], a.period[0]);
     double arg = x0 * x0 * a.inv2s2[0];
     double x1 = 0.0;
     if (a.dims > 1) {
-      x1 = s[1] - a.centres[k * a.dims + 1];
+      x1 = cv_delta(s[1], a.centres[k * a.dims + 1], a.period[1]);
       arg += x1 * x1 * a.inv2s2[1];
     }
     const double e = a.heights[k] * exp(-arg);

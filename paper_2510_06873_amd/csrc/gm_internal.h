@@ -11,6 +11,8 @@ namespace gm {
 
 constexpr int kBlock = 256;  // threads per block of the per-atom kernels (4 waves)
 constexpr int kXcd = 8;      // workgroups are dealt to the 8 XCDs round-robin
+constexpr int32_t kMaxTorsions = 1 << 16;   // torsion forces are summed by one thread in order
+constexpr int64_t kMaxFesBins = 1 << 24;
 
 // Sticky device error bits (read by gm_status).
 constexpr int32_t kErrOverflow = 1;
@@ -144,6 +146,7 @@ struct BiasArgs {
   double inv2s2[2];        // 1 / (2 sigma_d^2)
   double invs2[2];         // 1 / sigma_d^2
   double w0, wt_scale;     // wt_scale = 1/(kBT (gamma-1)), 0 for plain metad
+  double period[2];        // > 0: periodic dimension (nearest image of s - c)
   double* part;            // [blocks][3]
   double* V_out;
   double* dV_out;
@@ -196,6 +199,18 @@ hipError_t launch_neighbor_ranks(const uint16_t* nbr, const int32_t* cnt, const 
                                  const BrickIndex& bi, int32_t kmax, int32_t* nbr_out, int32_t* cnt_out,
                                  hipStream_t st);
 hipError_t launch_bias(const BiasArgs& a, int blocks, hipStream_t st);
+hipError_t launch_torsions(const float4* pos, int64_t n, const int32_t* quads, int32_t count, const double* box,
+                           double* phi, hipStream_t st);
+hipError_t launch_torsion_forces(const float4* pos, int64_t n, const int32_t* quads, int32_t count, const double* box,
+                                 const double* dV, void* force, bool fp64, hipStream_t st);
+hipError_t launch_nearest(const float4* pos, int64_t n, int32_t centre, const int32_t* members, int32_t count,
+                          const double* box, double* s, int32_t* atom, const double* dV, void* force, bool fp64,
+                          hipStream_t st);
+hipError_t launch_fes_reweight(const double* s, const double* V, int64_t T, int32_t dims, const double* lo,
+                               const double* hi, const int32_t* nb, double kBT, double* F, hipStream_t st);
+hipError_t launch_fes_hills(const BiasArgs& b, const double* lo, const double* hi, const int32_t* nb, double scale,
+                            double* F, hipStream_t st);
+void allow_fes_lds();
 // Opt the staging kernels in to `bytes` of dynamic LDS.
 void allow_cv_lds(int bytes);
 void allow_build_lds(int bytes);

@@ -41,7 +41,10 @@ def _params(**kw):
 
 
 @pytest.mark.parametrize("kw,n", [
-    (dict(cv_kind=0), 10), (dict(cv_kind=4), 10), (dict(precision=2), 10), (dict(r_c=0.0), 10),
+    (dict(cv_kind=0), 10), (dict(cv_kind=5), 10), (dict(precision=2), 10), (dict(r_c=0.0), 10),
+    (dict(cv_kind=4, external_dims=3), 10), (dict(cv_kind=4, external_dims=0), 0),
+    (dict(cv_kind=4, external_dims=2, sigma=[1.0, 0.0]), 0), (dict(cv_kind=4, period=[-1.0, 0.0]), 0),
+    (dict(period=[float("inf"), 0.0]), 10), (dict(cv_kind=4, gamma=0.5), 0), (dict(cv_kind=4), -1),
     (dict(skin=-1.0), 10), (dict(taper=0.0), 10), (dict(taper=5.0), 10), (dict(bond_w=0.0), 10),
     (dict(count_w=-1.0), 10), (dict(cv_kind=1, cn_r0=0.0), 10), (dict(sigma=[0.0]), 10),
     (dict(cv_kind=3, sigma=[1.0, 0.0]), 10), (dict(gamma=0.5), 10), (dict(gamma=10.0, kBT=0.0), 10),
@@ -67,6 +70,47 @@ def test_null_context_calls():
                        ("gm_apply_bias_forces", [None, None, None, None]), ("gm_deposit_hill", [None, None]),
                        ("gm_status", [None, 0]), ("gm_set_stream", [None, None])]:
         assert getattr(lib, name)(*args) == -1, name
+
+
+def test_small_cv_calls_reject_bad_arguments_on_host():
+    """Argument checks of the context-free calls run before any device work."""
+    import ctypes as C
+
+    import paper_2510_06873_amd as P
+
+    lib = P.lib()
+    box = (C.c_double * 3)(10.0, 10.0, 10.0)
+    bad_box = (C.c_double * 3)(10.0, 0.0, 10.0)
+    fake = C.c_void_p(1 << 20)  # aligned, never dereferenced: every call below fails its checks first
+    assert lib.gm_torsions(fake, 10, fake, -1, box, fake, None) == -1
+    assert lib.gm_torsions(fake, 10, fake, (1 << 16) + 1, box, fake, None) == -1
+    assert lib.gm_torsions(None, 10, fake, 3, box, fake, None) == -1
+    assert lib.gm_torsions(fake, 10, fake, 3, bad_box, fake, None) == -1
+    assert lib.gm_torsions(None, 0, None, 0, None, None, None) == 0  # nothing to do
+    assert lib.gm_torsion_forces(fake, 10, fake, 3, box, fake, fake, 7, None) == -1  # precision
+    assert lib.gm_torsion_forces(fake, 10, fake, 3, box, fake, C.c_void_p((1 << 20) + 16), 1, None) == -1
+    assert lib.gm_nearest_distance(fake, 10, 10, fake, 5, box, fake, None, None) == -1  # centre out of range
+    assert lib.gm_nearest_distance(fake, 10, -1, fake, 5, box, fake, None, None) == -1
+    assert lib.gm_nearest_distance(fake, 10, 0, fake, 0, box, fake, None, None) == -1
+    assert lib.gm_nearest_distance_forces(fake, 10, 0, fake, 5, box, None, fake, 0, None) == -1
+    lo, hi, nb = (C.c_double * 2)(0.0, 0.0), (C.c_double * 2)(1.0, 1.0), (C.c_int32 * 2)(10, 10)
+    assert lib.gm_fes_reweight(fake, fake, 100, 3, lo, hi, nb, 1.0, fake, None) == -1
+    assert lib.gm_fes_reweight(fake, fake, 0, 2, lo, hi, nb, 1.0, fake, None) == -1
+    assert lib.gm_fes_reweight(fake, fake, 100, 2, lo, hi, nb, 0.0, fake, None) == -1
+    assert lib.gm_fes_reweight(fake, fake, 100, 2, hi, lo, nb, 1.0, fake, None) == -1
+    big = (C.c_int32 * 2)(1 << 13, 1 << 12)
+    assert lib.gm_fes_reweight(fake, fake, 100, 2, lo, hi, big, 1.0, fake, None) == -1
+    assert lib.gm_fes_hills(None, lo, hi, nb, fake) == -1
+
+
+def test_lattice_virial_on_host():
+    import paper_2510_06873_amd as P
+
+    assert P.binding.lattice_virial([3.0, 4.0, 5.0], [0.5, -2.0, 1.0]) == [-1.5, 8.0, -5.0]
+    assert P.binding.lattice_virial([3.0, 4.0, 5.0], [2.0]) == [-6.0]
+    import ctypes as C
+    out = (C.c_double * 3)()
+    assert P.lib().gm_lattice_virial((C.c_double * 3)(1, 1, 1), (C.c_double * 3)(1, 1, 1), 4, out) == -1
 
 
 def test_header_is_plain_c():

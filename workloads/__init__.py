@@ -316,3 +316,72 @@ def serving_requests(count=256, n_lo=1000, n_hi=200000, rate=2000.0, k_lo=100, k
         out.append(dict(rid=i, arrival=float(t[i]), pos=as_float4(pos, species), box=box, kind=kind, params=prm,
                         centres=centres, heights=heights, forces=forces, w0=w0, kBT=KBT_EV))
     return out
+
+
+# --------------------------------------------------------------------------
+# Stand-ins for the paper's small-CV studies (their molecules, NEP models and
+# trajectories are not available): geometry and random numbers only.
+# --------------------------------------------------------------------------
+def peptide_in_solvent(n_solvent=3000, box=(32.0, 32.0, 32.0), seed=41):
+    """An alanine-dipeptide-sized chain (22 atoms: a random backbone walk of
+    1.5 A bonds at ~111 degree angles, side atoms hung off it) in a box of
+    random solvent sites.  Returns positions (float32, wrapped), the box, the
+    22 chain atom ids and two backbone quadruples standing for Phi(C-N-CA-C)
+    and Psi(N-CA-C-N), plus 30 further random quadruples of chain atoms."""
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, np.float64)
+    chain = np.zeros((22, 3))
+    chain[0] = box / 2
+    d = rng.normal(size=3)
+    d /= np.linalg.norm(d)
+    turn = np.radians(180.0 - 111.0)  # direction change for a 111 degree bond angle
+    for i in range(1, 10):  # backbone
+        nd = rng.normal(size=3)
+        nd -= nd.dot(d) * d
+        nd /= np.linalg.norm(nd)
+        d = np.cos(turn) * d + np.sin(turn) * nd
+        chain[i] = chain[i - 1] + 1.5 * d
+    for i in range(10, 22):  # side atoms, 1.1 A off a backbone atom
+        v = rng.normal(size=3)
+        chain[i] = chain[rng.integers(0, 10)] + 1.1 * v / np.linalg.norm(v)
+    solvent = rng.random((n_solvent, 3)) * box
+    pos = np.concatenate([chain, solvent])
+    order = rng.permutation(len(pos))  # the chain scattered through the atom order
+    inv = np.empty_like(order)
+    inv[order] = np.arange(len(order))
+    pos = pos[order]
+    ids = inv[:22]
+    quads = [[ids[2], ids[3], ids[4], ids[5]], [ids[3], ids[4], ids[5], ids[6]]]
+    for _ in range(30):
+        quads.append(list(rng.choice(ids, 4, replace=False)))
+    return dict(pos=_wrap_f32(pos, box), box=box, chain=ids.astype(np.int32), quads=np.asarray(quads, np.int32))
+
+
+def surface_water(n_atoms=4000, n_h=800, box=(26.0, 26.0, 40.0), seed=43):
+    """A rutile-surface-with-water stand-in: random sites in the box, a chosen
+    centre (the surface oxygen) and a set of hydrogen sites.  Returns
+    positions (float32), box, centre id and the hydrogen ids."""
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, np.float64)
+    pos = rng.random((n_atoms, 3)) * box
+    h = np.sort(rng.choice(n_atoms, n_h, replace=False)).astype(np.int32)
+    others = np.setdiff1d(np.arange(n_atoms), h)
+    return dict(pos=_wrap_f32(pos, box), box=box, centre=int(rng.choice(others)), hydrogens=h)
+
+
+def biased_trace(T=200000, dims=2, seed=45, periodic=True):
+    """Samples (s_t, V_t) of a biased run stand-in: s from a mixture of
+    Gaussians (wrapped to [-pi, pi) when periodic), V from a sum of 64 random
+    Gaussian hills at those points (float64)."""
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(-2.5, 2.5, (4, dims))
+    comp = rng.integers(0, 4, T)
+    s = mu[comp] + rng.normal(0.0, 0.6, (T, dims))
+    if periodic:
+        s = (s + np.pi) % (2 * np.pi) - np.pi
+    c = rng.uniform(-np.pi, np.pi, (64, dims))
+    h = rng.uniform(0.5, 2.0, 64)
+    V = np.zeros(T)
+    for k in range(64):
+        V += h[k] * np.exp(-np.sum((s - c[k]) ** 2, axis=1) / (2 * 0.5 ** 2))
+    return s.reshape(T, dims) if dims > 1 else s[:, 0], V
