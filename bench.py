@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--serving", action="store_true",
                     help="also run the walker-serving workload (256 requests, continuous batching vs sequential)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving workload")
+    ap.add_argument("--autograd", action="store_true",
+                    help="only time the autograd wrappers (stored vs recompute) on the 262,144-atom 2-D CV")
     ap.add_argument("--autotune", action="store_true",
                     help="time candidate brick shapes / LDS budgets on this system first and use the fastest")
     ap.add_argument("--brick", default=None, help="force the brick shape, e.g. 3x3x4")
@@ -227,6 +229,68 @@ def cpu_baseline(wl_name="wz96k"):
                       f"FP64, single thread, {time.time() - t_all:.1f} s"}
 
 
+def autograd_bench(steps=20, warmup=3):
+    """The differentiation workload: 262,144 atoms, 2-D CV (coordination + q6
+    count) on a 2-D Gaussian bias of 5,000 hills placed around the CV value.
+    Times V(s(x)).backward() through the torch.autograd wrappers with the
+    per-atom state stored by the forward or recomputed in the backward, next
+    to the explicit calls (forward, bias, backward with the gradient out)."""
+    import torch
+
+    import workloads as W
+    from paper_2510_06873_amd import CV_COORD_Q6, FP32, Params, Pipeline
+    from paper_2510_06873_amd.autograd import bias_energy
+
+    wl = W.WORKLOADS["wz262k"]
+    d = W.structure(wl["structure"])
+    n = d["pos"].shape[0]
+    prm = Params(cv_kind=CV_COORD_Q6, precision=FP32, r_c=wl["r_c"], skin=wl["skin"], taper=wl["taper"],
+                 cn_r0=wl["cn_r0"], bond_d0=wl["bond_d0"], bond_w=wl["bond_w"], count_n0=wl["count_n0"],
+                 count_w=wl["count_w"], sigma=wl["sigma"], w0=wl["w0"], gamma=wl["gamma"], kBT=wl["kBT"],
+                 hill_capacity=wl["hills"]["k"] + 16, max_neighbors=64)
+    pipe = Pipeline(n, prm)
+    dev = torch.device("cuda", 0)
+    pos4 = torch.from_numpy(W.as_float4(d["pos"], d["species"])).to(dev)
+    pipe.build_neighbors_checked(pos4, d["box"])
+    s0 = pipe.cv_forward(pos4).cpu().numpy().copy()
+    sig = np.array(wl["sigma"])
+    cen = W.hill_centres(wl["hills"]["k"], s0 - 3 * sig, s0 + 3 * sig, seed=wl["hills"]["seed"])
+    st = torch.empty(2, dtype=torch.float64, device=dev)
+    for c in cen:
+        st.copy_(torch.as_tensor(c))
+        pipe.deposit_hill(st)
+    pipe.check()
+    x = pos4.clone().requires_grad_(True)
+    grad4 = torch.zeros((n, 4), dtype=torch.float32, device=dev)
+
+    def explicit():
+        pipe.cv_forward(pos4)
+        pipe.bias_eval()
+        pipe.cv_backward(pos4, pipe.dVds, grad4)
+
+    def through_autograd(mode):
+        x.grad = None
+        bias_energy(x, pipe, mode).backward()
+
+    out = {"workload": f"wz262k: {n} atoms, 2-D CV (coordination, q6 count), {len(cen)} hills, FP32",
+           "unit": "ms per forward + backward"}
+    for name, fn in (("explicit", explicit), ("stored", lambda: through_autograd("stored")),
+                     ("recompute", lambda: through_autograd("recompute"))):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        out[name + "_ms"] = round(e0.elapsed_time(e1) / steps, 4)
+        log(f"[bench] autograd {name}: {out[name + '_ms']} ms")
+    pipe.check()
+    return out
+
+
 def serving_requests(count=256, seed=7, n_hi=200000):
     """The serving workload as library requests."""
     import workloads as W
@@ -278,6 +342,9 @@ def main():
         return
     if args.serving_only:
         print(json.dumps({"serving": serving(args)}), flush=True)
+        return
+    if args.autograd:
+        print(json.dumps({"autograd": autograd_bench()}), flush=True)
         return
     S = setup(args.workload, args)
     n = S["n"]

@@ -429,3 +429,44 @@ def test_autograd_2d_bias_gradient(orc, mode, precision, tol):
     g = p4.grad.cpu().numpy().astype(np.float64)
     assert rel_force_err(g[:, :3], grad_ref) <= tol
     assert np.all(g[:, 3] == 0)
+
+
+def test_autograd_against_finite_differences_of_the_gpu_path():
+    """d V(s(x)) / dx from the autograd wrappers against central differences
+    of the GPU path itself (FP64 context, 2-D CV, 2,048 atoms): coordinates
+    moved by 2^-13 A (exact in FP32 at these magnitudes), Richardson
+    extrapolation over h and h/2, lists kept from the unperturbed build."""
+    from paper_2510_06873_amd.autograd import bias_energy
+
+    wl = dict(W.WORKLOADS["wz2048"], precision="fp64")
+    d = W.structure(wl["structure"])
+    pos, box = d["pos"], d["box"]
+    n = len(pos)
+    pipe = make_pipe(wl, n)
+    p4 = to_dev(W.as_float4(pos))
+    pipe.build_neighbors_checked(p4, box)
+    s0 = pipe.cv_forward(p4).cpu().numpy().copy()
+    sig = np.array(wl["sigma"])
+    cen = W.hill_centres(300, s0 - 2 * sig, s0 + 2 * sig, seed=17)
+    pipe.hills_set(cen, np.full(len(cen), wl["w0"]))
+    x = p4.clone().requires_grad_(True)
+    bias_energy(x, pipe, "recompute").backward()
+    grad = x.grad.cpu().numpy().astype(np.float64)
+
+    def V_at(delta, i, a):
+        q = pos.copy()
+        q[i, a] = np.float32(np.float64(q[i, a]) + delta)
+        assert np.float64(q[i, a]) - np.float64(pos[i, a]) == delta  # the move is exact
+        pipe.cv_forward(to_dev(W.as_float4(q)))
+        V, _ = pipe.bias_eval()
+        return V.item()
+
+    h = 2.0 ** -13
+    rng = np.random.default_rng(8)
+    big = np.argsort(-np.linalg.norm(grad[:, :3], axis=1))[:6]
+    for i in list(big) + list(rng.choice(n, 6, replace=False)):
+        for a in range(3):
+            d1 = (V_at(h, i, a) - V_at(-h, i, a)) / (2 * h)
+            d2 = (V_at(h / 2, i, a) - V_at(-h / 2, i, a)) / h
+            fd = (4 * d2 - d1) / 3
+            assert abs(fd - grad[i, a]) <= 1e-6 * np.abs(grad[:, :3]).max(), (i, a, fd, grad[i, a])
