@@ -57,6 +57,11 @@ def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_06873_amd.build` "
                           "(hipcc, gfx950); there is no CPU fallback")
+    # torch ships its own HIP runtime; load it first so that the library binds
+    # to the same one (two runtimes in one process do not share device memory
+    # or streams, and the library's allocations then fail)
+    import torch  # noqa: F401
+
     lib = C.CDLL(LIB_PATH)
     vp, dp, ip32, ip64 = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
     sig = {

@@ -7,6 +7,8 @@
 #include <new>
 #include <vector>
 
+#include <cmath>
+
 #include "gm_internal.h"
 
 using namespace gm;
@@ -294,6 +296,12 @@ void choose_bricks(gm_ctx* c, const int32_t nc[3]) {
   g.blocks = (g.nbricks + kXcd - 1) / kXcd * kXcd;
   g.tpa = best_tpa;
   g.kpart = ((c->kmax + best_tpa - 1) / best_tpa + 7) / 8 * 8;
+  // the build runs one thread per owned atom: 256 threads while a brick's
+  // atoms fit them with a margin for density fluctuations (small workgroups
+  // pack a CU best), else enough waves for the atoms (up to 1024 threads)
+  const double own = (double)best[0] * best[1] * best[2] * rho;
+  const int bt = (int)std::ceil(1.25 * own / 64.0) * 64;
+  g.build_threads = 1.1 * own <= kBlock ? kBlock : (bt > kBuildMaxThreads ? kBuildMaxThreads : bt);
 }
 
 // Upper bound of the total halo slots: each cell is counted once per brick
@@ -620,17 +628,15 @@ int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
   const float4* p4 = reinterpret_cast<const float4*>(pos4);
   c->built = c->fwd = c->bwd = false;
   // canonical cell list: counts, scan, scatter, per-cell sort by atom id
-  GM_TRY(hip_rc(launch_fill_i32(c->count, 0, ncells, st)));
-  GM_TRY(hip_rc(launch_fill_i32(c->stats, 0, 4, st)));
-  GM_TRY(hip_rc(launch_fill_i32(c->err + 1, 0, 1, st)));  // out-of-box flag (see the gather)
+  // cell counts, list statistics and the out-of-box flag (see the gather)
+  GM_TRY(hip_rc(launch_reset_build(c->count, ncells, c->stats, c->err, st)));
   GM_TRY(hip_rc(launch_cell_ids(p4, c->n, c->geom, c->cell, c->count, c->err, st)));
   GM_TRY(hip_rc(launch_scan(c->count, ncells, c->start, c->fill, c->scan_tmp, st)));
   GM_TRY(hip_rc(launch_scatter(c->cell, c->n, c->start, c->fill, c->perm, st)));
   GM_TRY(hip_rc(launch_sort_cells(c->start, ncells, c->perm, st)));
   // bricks: halo and owned sizes, their prefix sums, the slot tables
   GM_TRY(hip_rc(launch_brick_count(c->start, c->bg, c->brick_H, c->brick_O, st)));
-  GM_TRY(hip_rc(launch_scan(c->brick_H, c->bg.nbricks, c->brick_hb, nullptr, c->scan_tmp, st)));
-  GM_TRY(hip_rc(launch_scan(c->brick_O, c->bg.nbricks, c->brick_ob, nullptr, c->scan_tmp, st)));
+  GM_TRY(hip_rc(launch_scan2(c->brick_H, c->brick_hb, c->brick_O, c->brick_ob, c->bg.nbricks, c->scan_tmp, st)));
   const BrickIndex bi = brick_index(c);
   GM_TRY(hip_rc(launch_brick_fill(c->start, c->bg, bi, c->brick_hp, c->halo_rank, c->owned_slot, c->owned_rank,
                                   c->owned_hcell, c->err, st)));

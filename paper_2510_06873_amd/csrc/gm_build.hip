@@ -114,6 +114,48 @@ __global__ __launch_bounds__(kScanTile) void k_scan_tiles(const int32_t* __restr
   }
 }
 
+// Exclusive scan of up to two short arrays (n <= kScanSmall each) in one
+// workgroup: each thread sums a contiguous chunk, the chunk sums are scanned
+// in LDS, and each thread writes its chunk's prefixes; out[n] = total and
+// zero (if given) is cleared alongside.
+constexpr int kScanSmall = 16 * kScanTile;
+
+__device__ __forceinline__ void scan_small_one(const int32_t* __restrict__ in, int64_t n, int32_t* __restrict__ out,
+                                               int32_t* __restrict__ zero, int32_t* lds) {
+  const int64_t chunk = (n + kScanTile - 1) / kScanTile;
+  const int64_t lo = threadIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  int32_t sum = 0;
+  for (int64_t i = lo; i < hi; i++) sum += in[i];
+  const int32_t incl = block_scan_incl(sum, lds);
+  int32_t run = incl - sum;
+  for (int64_t i = lo; i < hi; i++) {
+    const int32_t v = in[i];
+    out[i] = run;
+    run += v;
+    if (zero) zero[i] = 0;
+  }
+  if (threadIdx.x == kScanTile - 1) out[n] = incl;
+}
+
+__global__ __launch_bounds__(kScanTile) void k_scan_small(const int32_t* __restrict__ in0, int64_t n0,
+                                                          int32_t* __restrict__ out0, int32_t* __restrict__ zero0,
+                                                          const int32_t* __restrict__ in1, int64_t n1,
+                                                          int32_t* __restrict__ out1) {
+  __shared__ int32_t lds[kScanTile];
+  scan_small_one(in0, n0, out0, zero0, lds);
+  if (in1) scan_small_one(in1, n1, out1, nullptr, lds);
+}
+
+// Clears what a rebuild accumulates into: the cell counts, the list
+// statistics and the out-of-box flag.
+__global__ __launch_bounds__(kBlock) void k_reset_build(int32_t* __restrict__ count, int64_t ncells,
+                                                        int32_t* __restrict__ stats, int32_t* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncells) count[i] = 0;
+  if (i < 4) stats[i] = 0;
+  if (i == 0) err[1] = 0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ cell, int64_t n,
                                                     const int32_t* __restrict__ start,
                                                     int32_t* __restrict__ fill, int32_t* __restrict__ perm) {
@@ -376,16 +418,16 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_build_nbr(const vec4_t<T>* __restrict__ pos_s, CellGeom cg, BrickGeom g,
+template <typename T, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_build_nbr(const vec4_t<T>* __restrict__ pos_s, CellGeom cg, BrickGeom g,
                                                       BrickIndex bi, double rl2, uint16_t* __restrict__ nbr,
                                                       int32_t kmax, int32_t* __restrict__ cnt, int32_t* err,
                                                       int32_t* stats) {
   extern __shared__ __align__(16) unsigned char smem[];
   float4* hpos = reinterpret_cast<float4*>(smem);
   __shared__ int32_t hp[kHaloCells + 1];
-  __shared__ double red[kBlock / 64];
-  __shared__ int32_t wmax[kBlock / 64];
+  __shared__ double red[MAXT / 64];
+  __shared__ int32_t wmax[MAXT / 64];
   const int64_t b = logical_brick(g);
   const bool live = b < g.nbricks;
   int32_t hb = 0, H = 0, ob = 0, O = 0, hx = 0, hxy = 0;
@@ -485,10 +527,31 @@ hipError_t launch_cell_ids(const float4* pos, int64_t n, const CellGeom& g, int3
 }
 
 hipError_t launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* zero, int32_t* tmp, hipStream_t st) {
+  if (n <= kScanSmall) {
+    k_scan_small<<<1, kScanTile, 0, st>>>(in, n, out, zero, nullptr, 0, nullptr);
+    return hipGetLastError();
+  }
   const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
   k_tile_sums<<<(unsigned)ntiles, kScanTile, 0, st>>>(in, n, tmp);
   k_scan_sums<<<1, kScanTile, 0, st>>>(tmp, ntiles, out, n);
   k_scan_tiles<<<(unsigned)ntiles, kScanTile, 0, st>>>(in, n, tmp, out, zero);
+  return hipGetLastError();
+}
+
+// Two exclusive scans (no zeroing); one launch when both are short.
+hipError_t launch_scan2(const int32_t* in0, int32_t* out0, const int32_t* in1, int32_t* out1, int64_t n,
+                        int32_t* tmp, hipStream_t st) {
+  if (n <= kScanSmall) {
+    k_scan_small<<<1, kScanTile, 0, st>>>(in0, n, out0, nullptr, in1, n, out1);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_scan(in0, n, out0, nullptr, tmp, st);
+  return e != hipSuccess ? e : launch_scan(in1, n, out1, nullptr, tmp, st);
+}
+
+hipError_t launch_reset_build(int32_t* count, int64_t ncells, int32_t* stats, int32_t* err, hipStream_t st) {
+  const int64_t n = ncells > 4 ? ncells : 4;
+  k_reset_build<<<grid_of(n, kBlock), kBlock, 0, st>>>(count, ncells, stats, err);
   return hipGetLastError();
 }
 
@@ -527,7 +590,10 @@ hipError_t launch_build_nbr(const vec4_t<T>* pos_s, const CellGeom& cg, const Br
                             double rl2, uint16_t* nbr, int32_t kmax, int32_t* cnt, int32_t* err, int32_t* stats,
                             hipStream_t st) {
   const size_t lds = (size_t)g.cap * sizeof(float4);
-  k_build_nbr<T><<<(unsigned)g.blocks, kBlock, lds, st>>>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, stats);
+  if (g.build_threads <= kBlock)
+    k_build_nbr<T, kBlock><<<(unsigned)g.blocks, kBlock, lds, st>>>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, stats);
+  else
+    k_build_nbr<T, kBuildMaxThreads><<<(unsigned)g.blocks, (unsigned)g.build_threads, lds, st>>>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, stats);
   return hipGetLastError();
 }
 
@@ -539,8 +605,10 @@ hipError_t launch_neighbor_ranks(const uint16_t* nbr, const int32_t* cnt, const 
 
 void allow_build_lds(int bytes) {
   const hipFuncAttribute A = hipFuncAttributeMaxDynamicSharedMemorySize;
-  (void)hipFuncSetAttribute((const void*)k_build_nbr<float>, A, bytes);
-  (void)hipFuncSetAttribute((const void*)k_build_nbr<double>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_build_nbr<float, kBlock>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_build_nbr<float, kBuildMaxThreads>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_build_nbr<double, kBlock>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_build_nbr<double, kBuildMaxThreads>, A, bytes);
   (void)hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 namespace gm {
 
 constexpr int kBlock = 256;  // threads per block of the per-atom kernels (4 waves)
+constexpr int kBuildMaxThreads = 1024;  // largest workgroup of the neighbour build
 constexpr int kXcd = 8;      // workgroups are dealt to the 8 XCDs round-robin
 constexpr int32_t kMaxTorsions = 1 << 16;   // torsion forces are summed by one thread in order
 constexpr int64_t kMaxFesBins = 1 << 24;
@@ -87,6 +88,7 @@ struct BrickGeom {
   int32_t blocks;  // workgroups launched per brick pass (nbricks rounded up to the XCD count)
   int32_t tpa;     // threads per owned atom (1, 2 or 4): lanes that split one atom's rows
   int32_t kpart;   // length of one part's sub-row (multiple of 8 entries, 16-byte aligned)
+  int32_t build_threads;  // workgroup size of the neighbour build (one thread per owned atom)
 };
 
 struct BrickIndex {
@@ -168,6 +170,9 @@ hipError_t launch_cell_ids(const float4* pos, int64_t n, const CellGeom& g, int3
                            int32_t* count, int32_t* err, hipStream_t st);
 // tmp: device int32[(n + 1023)/1024] scratch for the tile sums
 hipError_t launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* zero, int32_t* tmp, hipStream_t st);
+hipError_t launch_scan2(const int32_t* in0, int32_t* out0, const int32_t* in1, int32_t* out1, int64_t n,
+                        int32_t* tmp, hipStream_t st);
+hipError_t launch_reset_build(int32_t* count, int64_t ncells, int32_t* stats, int32_t* err, hipStream_t st);
 hipError_t launch_scatter(const int32_t* cell, int64_t n, const int32_t* start, int32_t* fill,
                           int32_t* perm, hipStream_t st);
 hipError_t launch_sort_cells(const int32_t* start, int64_t ncells, int32_t* perm, hipStream_t st);

@@ -93,13 +93,33 @@ def _finish(w: _Walker, t: float, admitted: float, keep_forces: bool) -> Result:
                   w.F.cpu().numpy().copy() if keep_forces else None)
 
 
+def _rebuild_concurrently(walkers, stream, aux):
+    """Neighbour rebuilds of several walkers, spread over the auxiliary streams
+    so that their chains of small kernels overlap on the device.  Each rebuild
+    starts after the work already on the main stream (which reads the old
+    lists) and the main stream waits for all of them."""
+    if not walkers:
+        return
+    used = aux[:len(walkers)]
+    for s in used:
+        s.wait_stream(stream)
+    for k, w in enumerate(walkers):
+        s = used[k % len(used)]
+        w.pipe.set_stream(s)
+        w.pipe.build_neighbors(w.pos, w.req.box)
+        w.pipe.set_stream(stream)
+    for s in used:
+        stream.wait_stream(s)
+
+
 def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64, keep_forces: bool = False,
-                  device=None):
+                  device=None, rebuild_streams: int = 3):
     """Run the requests with continuous batching; returns (results, stats)."""
     import torch
 
     dev = device or torch.device("cuda", 0)
     stream = torch.cuda.Stream(device=dev)
+    aux = [torch.cuda.Stream(device=dev) for _ in range(rebuild_streams)]
     pending = sorted(requests, key=lambda r: r.arrival)
     active: List[_Walker] = []
     admitted_at = {}
@@ -133,9 +153,8 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
                 batch = Batch([w.pipe for w in active], [w.pos for w in active], [w.F for w in active],
                               stream=stream)
                 members = ids
-            for w in active:  # rebuilds due at this walker's own step count
-                if w.done > 0 and w.done % w.req.pace == 0:
-                    w.pipe.build_neighbors(w.pos, w.req.box)
+            # rebuilds due at each walker's own step count
+            _rebuild_concurrently([w for w in active if w.done > 0 and w.done % w.req.pace == 0], stream, aux)
             batch.step()
             ticks += 1
             for w in active:
