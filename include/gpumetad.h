@@ -18,8 +18,14 @@
  * with gm_build_neighbors every few steps and gm_deposit_hill at the
  * deposition pace.  Every call validates its arguments on the host, ENQUEUES
  * its kernels on the context's HIP stream and returns; none synchronises except
- * the calls marked "synchronous".  Scalars (s, V, dV/ds) stay in device memory,
- * so a whole window of steps can be captured in a HIP graph.
+ * the calls marked "synchronous", which wait for the context's stream only.
+ * Scalars (s, V, dV/ds) stay in device memory, so a whole window of steps can
+ * be captured in a HIP graph.
+ *
+ * Memory: the library's device buffers come from a stream-ordered pool of its
+ * own (one per device, keeping up to 4 GiB cached between uses).  Allocation
+ * and release are operations on the stream the context or batch is bound to
+ * at that moment, so creating and destroying them never waits for the device.
  *
  * Pointer conventions
  *   "dev"  : device memory (e.g. from hipMalloc), owned by the caller,
@@ -110,14 +116,19 @@ typedef struct gm_params {
 typedef struct gm_ctx gm_ctx;
 
 /* Create a context for n_atoms atoms whose kernels run on hip_stream
- * (a HIP stream handle; NULL = the null stream).  Allocates every buffer the steps
- * need (synchronous).  *out is set to NULL on failure. */
+ * (a HIP stream handle; NULL = the null stream), on the current device.
+ * Allocates and zero-fills every buffer the steps need, in order on
+ * hip_stream (no wait).  *out is set to NULL on failure. */
 int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_stream);
 
-/* Free everything the context owns (synchronous; waits for its stream). */
+/* Free everything the context owns, in stream order on the context's stream
+ * (no wait): work already enqueued there may still use the buffers, and work
+ * on other streams that uses them must be ordered before this call. */
 int gm_destroy(gm_ctx* ctx);
 
-/* Re-bind the context to another stream (e.g. a capture stream). */
+/* Re-bind the context to another stream (e.g. a capture stream).  The caller
+ * orders the new stream after the context's work on the old one (an event),
+ * as for any data the two share. */
 int gm_set_stream(gm_ctx* ctx, void* hip_stream);
 
 /* Build the cell list (a stable counting sort of atoms by cell, cells of
@@ -171,12 +182,13 @@ int gm_apply_bias_forces(gm_ctx* ctx, const float* pos4, const double* dVds_dev,
  * and deposits nothing. */
 int gm_deposit_hill(gm_ctx* ctx, const double* s_dev);
 
-/* Checkpoint the hill history (synchronous).  centres: host double[cap*dims],
+/* Checkpoint the hill history (synchronous: waits for the context's stream).  centres: host double[cap*dims],
  * heights: host double[cap]; *k receives the hill count.  Either array may be
  * NULL to query the count only.  GM_ERR_INVALID_ARG if cap < count. */
 int gm_hills_get(gm_ctx* ctx, double* centres, double* heights, int64_t cap, int64_t* k);
 
-/* Restore a hill history (synchronous).  centres: host double[k*dims],
+/* Restore a hill history (synchronous: enqueued, then waits for the context's
+ * stream so that the host arrays may be reused on return).  centres: host double[k*dims],
  * heights: host double[k], 0 <= k <= hill_capacity.  Bias sums run in hill
  * index order, so a restored history reproduces V bit for bit. */
 int gm_hills_set(gm_ctx* ctx, const double* centres, const double* heights, int64_t k);
@@ -195,7 +207,7 @@ const char* gm_strerror(int code);
 int gm_neighbor_stats(gm_ctx* ctx, int32_t* max_count, int64_t* total, int64_t* cutoff_pairs);
 
 /* Set the neighbour-list row width (rounded up to a multiple of 4) and
- * reallocate; the lists must be rebuilt afterwards (synchronous). */
+ * reallocate in stream order (no wait); the lists must be rebuilt afterwards. */
 int gm_reserve_neighbors(gm_ctx* ctx, int32_t max_neighbors);
 
 /* Copy the cell list of the last build (enqueued device-to-device copies):
@@ -235,6 +247,9 @@ typedef struct gm_batch gm_batch;
  * precision) that stay valid while the batch exists. */
 int gm_batch_create(gm_batch** out, gm_ctx* const* walkers, int32_t count, const float* const* pos4,
                     void* const* force4, void* hip_stream);
+
+/* Free the batch's device tables in stream order on its stream (no wait); the
+ * walkers stay bound to that stream. */
 int gm_batch_destroy(gm_batch* batch);
 
 /* Rebuild every walker's cell and neighbour lists; boxes: host double[count][3]. */

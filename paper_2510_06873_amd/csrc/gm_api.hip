@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -55,12 +56,49 @@ struct gm_ctx {
 
 namespace {
 
+// Device memory comes from one stream-ordered pool per device: an allocation
+// or a free is an operation on the stream it names, so creating and destroying
+// contexts and batches while other streams run neither waits for the device
+// (as hipFree does) nor maps fresh memory each time; the pool keeps up to
+// kPoolKeepBytes cached across synchronisations.
+constexpr uint64_t kPoolKeepBytes = 4ull << 30;
+constexpr int kMaxDevices = 64;
+std::mutex g_pool_mu;
+hipMemPool_t g_pool[kMaxDevices] = {};
+
+hipMemPool_t device_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  if (!g_pool[dev]) {
+    hipMemPoolProps pp;
+    memset(&pp, 0, sizeof(pp));
+    pp.allocType = hipMemAllocationTypePinned;
+    pp.handleTypes = hipMemHandleTypeNone;
+    pp.location.type = hipMemLocationTypeDevice;
+    pp.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &pp) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    uint64_t keep = kPoolKeepBytes;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    g_pool[dev] = pool;
+  }
+  return g_pool[dev];
+}
+
+// Allocate in stream order on st: usable by work enqueued on st after this
+// call, and by other streams once ordered after that point.
 template <typename P>
-int dalloc(P** p, size_t bytes) {
+int dalloc(hipStream_t st, P** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
+  hipMemPool_t pool = device_pool();
+  if (!pool) return GM_ERR_HIP;
   void* q = nullptr;
-  if (hipMalloc(&q, bytes) != hipSuccess) {
+  if (hipMallocFromPoolAsync(&q, bytes, pool, st) != hipSuccess) {
     (void)hipGetLastError();
     return GM_ERR_OOM;
   }
@@ -68,9 +106,11 @@ int dalloc(P** p, size_t bytes) {
   return GM_OK;
 }
 
+// Free in stream order on st: the memory returns to the pool after the work
+// already enqueued on st, which must include every use of it.
 template <typename P>
-void dfree(P*& p) {
-  if (p) (void)hipFree(reinterpret_cast<void*>(p));
+void dfree(hipStream_t st, P*& p) {
+  if (p) (void)hipFreeAsync(reinterpret_cast<void*>(p), st);
   p = nullptr;
 }
 
@@ -296,12 +336,26 @@ void choose_bricks(gm_ctx* c, const int32_t nc[3]) {
   g.blocks = (g.nbricks + kXcd - 1) / kXcd * kXcd;
   g.tpa = best_tpa;
   g.kpart = ((c->kmax + best_tpa - 1) / best_tpa + 7) / 8 * 8;
-  // the build runs one thread per owned atom: 256 threads while a brick's
-  // atoms fit them with a margin for density fluctuations (small workgroups
-  // pack a CU best), else enough waves for the atoms (up to 1024 threads)
+  // The neighbour build stages the halo it expects with a margin (slots
+  // beyond are read from global memory), so that big-halo systems do not
+  // take a CU's LDS for little use; 512 threads when that staging is large
+  // (fewer workgroups share a CU), else 256.  A system with few bricks
+  // splits each brick's atoms over several workgroups (each stages the
+  // whole halo) so that the launch still fills the device, down to about one
+  // atom per lane group; the rows are the same for any split.
   const double own = (double)best[0] * best[1] * best[2] * rho;
-  const int bt = (int)std::ceil(1.25 * own / 64.0) * 64;
-  g.build_threads = 1.1 * own <= kBlock ? kBlock : (bt > kBuildMaxThreads ? kBuildMaxThreads : bt);
+  const double halo = (double)(best[0] + 2) * (best[1] + 2) * (best[2] + 2) * rho;
+  const int bcap = (int)std::ceil(1.25 * halo) + 64;
+  g.build_cap = bcap < cap ? bcap : cap;
+  g.build_threads = g.build_cap * (int)sizeof(float4) > 32768 ? kBuildMaxThreads : kBlock;
+  g.build_split = 1;
+  if (g.nbricks < kBuildFillBlocks) {
+    int split = (kBuildFillBlocks + g.nbricks - 1) / g.nbricks;
+    int most = (int)std::ceil(own / (g.build_threads / kBuildGroup));
+    most = most < 1 ? 1 : most;
+    split = split < most ? split : most;
+    g.build_split = split < kBuildMaxSplit ? split : kBuildMaxSplit;
+  }
 }
 
 // Upper bound of the total halo slots: each cell is counted once per brick
@@ -357,43 +411,43 @@ BiasArgs make_bias(gm_ctx* c, const double* s, int deposit) {
 }
 
 void free_all(gm_ctx* c) {
-  dfree(c->cell);
-  dfree(c->count);
-  dfree(c->start);
-  dfree(c->fill);
-  dfree(c->scan_tmp);
-  dfree(c->perm);
-  dfree(c->brick_H);
-  dfree(c->brick_O);
-  dfree(c->brick_hb);
-  dfree(c->brick_ob);
-  dfree(c->brick_hp);
-  dfree(c->halo_rank);
-  dfree(c->owned_slot);
-  dfree(c->owned_rank);
-  dfree(c->owned_hcell);
-  dfree(c->nbr);
-  dfree(c->cut);
-  dfree(c->cnt);
-  dfree(c->ccnt);
-  dfree(c->order);
-  dfree(c->err);
-  dfree(c->stats);
-  dfree(c->pos_s);
-  dfree(c->qrow);
-  dfree(c->grow);
-  dfree(c->frad);
-  dfree(c->nb);
-  dfree(c->cn_atom);
-  dfree(c->part_a);
-  dfree(c->part_b);
-  dfree(c->s_int);
-  dfree(c->V_int);
-  dfree(c->dV_int);
-  dfree(c->centres);
-  dfree(c->heights);
-  dfree(c->bias_part);
-  dfree(c->hill_count);
+  dfree(c->stream, c->cell);
+  dfree(c->stream, c->count);
+  dfree(c->stream, c->start);
+  dfree(c->stream, c->fill);
+  dfree(c->stream, c->scan_tmp);
+  dfree(c->stream, c->perm);
+  dfree(c->stream, c->brick_H);
+  dfree(c->stream, c->brick_O);
+  dfree(c->stream, c->brick_hb);
+  dfree(c->stream, c->brick_ob);
+  dfree(c->stream, c->brick_hp);
+  dfree(c->stream, c->halo_rank);
+  dfree(c->stream, c->owned_slot);
+  dfree(c->stream, c->owned_rank);
+  dfree(c->stream, c->owned_hcell);
+  dfree(c->stream, c->nbr);
+  dfree(c->stream, c->cut);
+  dfree(c->stream, c->cnt);
+  dfree(c->stream, c->ccnt);
+  dfree(c->stream, c->order);
+  dfree(c->stream, c->err);
+  dfree(c->stream, c->stats);
+  dfree(c->stream, c->pos_s);
+  dfree(c->stream, c->qrow);
+  dfree(c->stream, c->grow);
+  dfree(c->stream, c->frad);
+  dfree(c->stream, c->nb);
+  dfree(c->stream, c->cn_atom);
+  dfree(c->stream, c->part_a);
+  dfree(c->stream, c->part_b);
+  dfree(c->stream, c->s_int);
+  dfree(c->stream, c->V_int);
+  dfree(c->stream, c->dV_int);
+  dfree(c->stream, c->centres);
+  dfree(c->stream, c->heights);
+  dfree(c->stream, c->bias_part);
+  dfree(c->stream, c->hill_count);
 }
 
 int status_from_bits(int32_t bits) {
@@ -489,37 +543,38 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   const size_t n = c->external ? 1 : (size_t)n_atoms, T = c->fp64 ? 8 : 4;  // no atom buffers for external CVs
   const size_t cap = (size_t)(params->hill_capacity > 0 ? params->hill_capacity : 1);
   int rc = GM_OK;
-  if (rc == GM_OK) rc = dalloc(&c->cell, n * 4);
-  if (rc == GM_OK) rc = dalloc(&c->perm, n * 4);
-  if (rc == GM_OK) rc = dalloc(&c->owned_slot, n * 4);
-  if (rc == GM_OK) rc = dalloc(&c->owned_rank, n * 4);
-  if (rc == GM_OK) rc = dalloc(&c->owned_hcell, n * 4);
-  if (rc == GM_OK) rc = dalloc(&c->cnt, n * 4);
-  if (rc == GM_OK) rc = dalloc(&c->ccnt, n * 4 * 4);  // up to 4 parts per atom
-  if (rc == GM_OK) rc = dalloc(&c->order, n * 4);
-  if (rc == GM_OK) rc = dalloc(&c->nbr, n * (size_t)(c->kmax + 32) * 2);  // tpa sub-rows of kpart entries
-  if (rc == GM_OK) rc = dalloc(&c->cut, n * (size_t)(c->kmax + 32) * 2);
-  if (rc == GM_OK) rc = dalloc(&c->pos_s, n * 4 * T);
-  if (rc == GM_OK && c->has_q6) rc = dalloc(&c->qrow, n * 16 * T);
-  if (rc == GM_OK && c->has_q6) rc = dalloc(&c->grow, n * 16 * T);
-  if (rc == GM_OK && c->has_q6) rc = dalloc(&c->frad, n * 4 * T);
-  if (rc == GM_OK) rc = dalloc(&c->nb, n * T);
-  if (rc == GM_OK) rc = dalloc(&c->cn_atom, n * T);
-  if (rc == GM_OK) rc = dalloc(&c->s_int, 16);
-  if (rc == GM_OK) rc = dalloc(&c->V_int, 16);
-  if (rc == GM_OK) rc = dalloc(&c->dV_int, 16);
-  if (rc == GM_OK) rc = dalloc(&c->err, 16);
-  if (rc == GM_OK) rc = dalloc(&c->stats, 32);
-  if (rc == GM_OK) rc = dalloc(&c->centres, cap * c->dims * 8);
-  if (rc == GM_OK) rc = dalloc(&c->heights, cap * 8);
-  if (rc == GM_OK) rc = dalloc(&c->hill_count, 16);
-  if (rc == GM_OK) rc = dalloc(&c->bias_part, (size_t)c->bias_blocks * 3 * 8);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->cell, n * 4);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->perm, n * 4);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->owned_slot, n * 4);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->owned_rank, n * 4);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->owned_hcell, n * 4);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->cnt, n * 4);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->ccnt, n * 4 * 4);  // up to 4 parts per atom
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->order, n * 4);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->nbr, n * (size_t)(c->kmax + 32) * 2);  // tpa sub-rows of kpart entries
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->cut, n * (size_t)(c->kmax + 32) * 2);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->pos_s, n * 4 * T);
+  if (rc == GM_OK && c->has_q6) rc = dalloc(c->stream, &c->qrow, n * 16 * T);
+  if (rc == GM_OK && c->has_q6) rc = dalloc(c->stream, &c->grow, n * 16 * T);
+  if (rc == GM_OK && c->has_q6) rc = dalloc(c->stream, &c->frad, n * 4 * T);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->nb, n * T);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->cn_atom, n * T);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->s_int, 16);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->V_int, 16);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->dV_int, 16);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->err, 16);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->stats, 32);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->centres, cap * c->dims * 8);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->heights, cap * 8);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->hill_count, 16);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->bias_part, (size_t)c->bias_blocks * 3 * 8);
   if (rc == GM_OK) {
-    bool ok = hipMemset(c->err, 0, 16) == hipSuccess &&
-              hipMemset(c->hill_count, 0, 16) == hipSuccess && hipMemset(c->stats, 0, 32) == hipSuccess &&
-              hipMemset(c->s_int, 0, 16) == hipSuccess && hipMemset(c->V_int, 0, 16) == hipSuccess &&
-              hipMemset(c->dV_int, 0, 16) == hipSuccess && hipMemset(c->cn_atom, 0, n * T) == hipSuccess &&
-              hipMemset(c->nb, 0, n * T) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    hipStream_t st = c->stream;
+    bool ok = hipMemsetAsync(c->err, 0, 16, st) == hipSuccess &&
+              hipMemsetAsync(c->hill_count, 0, 16, st) == hipSuccess &&
+              hipMemsetAsync(c->stats, 0, 32, st) == hipSuccess && hipMemsetAsync(c->s_int, 0, 16, st) == hipSuccess &&
+              hipMemsetAsync(c->V_int, 0, 16, st) == hipSuccess && hipMemsetAsync(c->dV_int, 0, 16, st) == hipSuccess &&
+              hipMemsetAsync(c->cn_atom, 0, n * T, st) == hipSuccess && hipMemsetAsync(c->nb, 0, n * T, st) == hipSuccess;
     if (!ok) rc = GM_ERR_HIP;
   }
   if (rc != GM_OK) {
@@ -533,7 +588,6 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
 
 int gm_destroy(gm_ctx* c) {
   if (!c) return GM_ERR_INVALID_ARG;
-  (void)hipStreamSynchronize(c->stream);
   free_all(c);
   delete c;
   return GM_OK;
@@ -551,33 +605,32 @@ static int reserve_bricks(gm_ctx* c) {
   const int64_t nbk = c->bg.nbricks, blocks = c->bg.blocks, hbound = halo_bound(c);
   const bool grow_b = nbk > c->nbricks_cap, grow_h = hbound > c->halo_cap, grow_p = blocks > c->blocks_cap;
   if (!(grow_b || grow_h || grow_p)) return GM_OK;
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
   if (grow_b) {
-    dfree(c->brick_H);
-    dfree(c->brick_O);
-    dfree(c->brick_hb);
-    dfree(c->brick_ob);
-    dfree(c->brick_hp);
+    dfree(c->stream, c->brick_H);
+    dfree(c->stream, c->brick_O);
+    dfree(c->stream, c->brick_hb);
+    dfree(c->stream, c->brick_ob);
+    dfree(c->stream, c->brick_hp);
     c->nbricks_cap = 0;
-    GM_TRY(dalloc(&c->brick_H, (size_t)nbk * 4));
-    GM_TRY(dalloc(&c->brick_O, (size_t)nbk * 4));
-    GM_TRY(dalloc(&c->brick_hb, (size_t)(nbk + 1) * 4));
-    GM_TRY(dalloc(&c->brick_ob, (size_t)(nbk + 1) * 4));
-    GM_TRY(dalloc(&c->brick_hp, (size_t)nbk * (kHaloCells + 1) * 4));
+    GM_TRY(dalloc(c->stream, &c->brick_H, (size_t)nbk * 4));
+    GM_TRY(dalloc(c->stream, &c->brick_O, (size_t)nbk * 4));
+    GM_TRY(dalloc(c->stream, &c->brick_hb, (size_t)(nbk + 1) * 4));
+    GM_TRY(dalloc(c->stream, &c->brick_ob, (size_t)(nbk + 1) * 4));
+    GM_TRY(dalloc(c->stream, &c->brick_hp, (size_t)nbk * (kHaloCells + 1) * 4));
     c->nbricks_cap = nbk;
   }
   if (grow_h) {
-    dfree(c->halo_rank);
+    dfree(c->stream, c->halo_rank);
     c->halo_cap = 0;
-    GM_TRY(dalloc(&c->halo_rank, (size_t)hbound * 4));
+    GM_TRY(dalloc(c->stream, &c->halo_rank, (size_t)hbound * 4));
     c->halo_cap = hbound;
   }
   if (grow_p) {
-    dfree(c->part_a);
-    dfree(c->part_b);
+    dfree(c->stream, c->part_a);
+    dfree(c->stream, c->part_b);
     c->blocks_cap = 0;
-    GM_TRY(dalloc(&c->part_a, (size_t)blocks * 8));
-    GM_TRY(dalloc(&c->part_b, (size_t)blocks * 8));
+    GM_TRY(dalloc(c->stream, &c->part_a, (size_t)blocks * 8));
+    GM_TRY(dalloc(c->stream, &c->part_b, (size_t)blocks * 8));
     c->blocks_cap = blocks;
   }
   return GM_OK;
@@ -596,23 +649,21 @@ int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
   }
   const int64_t ncells = (int64_t)nc[0] * nc[1] * nc[2];
   if (ncells > c->ncells_cap) {
-    (void)hipStreamSynchronize(c->stream);
-    dfree(c->count);
-    dfree(c->start);
-    dfree(c->fill);
+    dfree(c->stream, c->count);
+    dfree(c->stream, c->start);
+    dfree(c->stream, c->fill);
     c->ncells_cap = 0;
-    GM_TRY(dalloc(&c->count, (size_t)ncells * 4));
-    GM_TRY(dalloc(&c->start, (size_t)(ncells + 1) * 4));
-    GM_TRY(dalloc(&c->fill, (size_t)ncells * 4));
+    GM_TRY(dalloc(c->stream, &c->count, (size_t)ncells * 4));
+    GM_TRY(dalloc(c->stream, &c->start, (size_t)(ncells + 1) * 4));
+    GM_TRY(dalloc(c->stream, &c->fill, (size_t)ncells * 4));
     c->ncells_cap = ncells;
   }
   c->ncells = ncells;
   const int64_t tiles = (ncells + 1023) / 1024 + 1;
   if (tiles > c->scan_tmp_cap) {
-    (void)hipStreamSynchronize(c->stream);
-    dfree(c->scan_tmp);
+    dfree(c->stream, c->scan_tmp);
     c->scan_tmp_cap = 0;
-    GM_TRY(dalloc(&c->scan_tmp, (size_t)tiles * 4));
+    GM_TRY(dalloc(c->stream, &c->scan_tmp, (size_t)tiles * 4));
     c->scan_tmp_cap = tiles;
   }
   for (int a = 0; a < 3; a++) {
@@ -632,8 +683,9 @@ int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
   GM_TRY(hip_rc(launch_reset_build(c->count, ncells, c->stats, c->err, st)));
   GM_TRY(hip_rc(launch_cell_ids(p4, c->n, c->geom, c->cell, c->count, c->err, st)));
   GM_TRY(hip_rc(launch_scan(c->count, ncells, c->start, c->fill, c->scan_tmp, st)));
-  GM_TRY(hip_rc(launch_scatter(c->cell, c->n, c->start, c->fill, c->perm, st)));
-  GM_TRY(hip_rc(launch_sort_cells(c->start, ncells, c->perm, st)));
+  // scatter into owned_rank (rewritten by the brick fill below), then rank
+  GM_TRY(hip_rc(launch_scatter(c->cell, c->n, c->start, c->fill, c->owned_rank, st)));
+  GM_TRY(hip_rc(launch_rank_cells(c->cell, c->start, c->owned_rank, c->n, c->perm, st)));
   // bricks: halo and owned sizes, their prefix sums, the slot tables
   GM_TRY(hip_rc(launch_brick_count(c->start, c->bg, c->brick_H, c->brick_O, st)));
   GM_TRY(hip_rc(launch_scan2(c->brick_H, c->brick_hb, c->brick_O, c->brick_ob, c->bg.nbricks, c->scan_tmp, st)));
@@ -708,16 +760,20 @@ int gm_apply_bias_forces(gm_ctx* c, const float* pos4, const double* dVds_dev, v
 
 int gm_hills_get(gm_ctx* c, double* centres, double* heights, int64_t cap, int64_t* k) {
   if (!c || !k) return GM_ERR_INVALID_ARG;
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
+  hipStream_t st = c->stream;
   int64_t K = 0;
-  if (hipMemcpy(&K, c->hill_count, 8, hipMemcpyDeviceToHost) != hipSuccess) return GM_ERR_HIP;
+  if (hipMemcpyAsync(&K, c->hill_count, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return GM_ERR_HIP;
   *k = K;
   if (centres || heights) {
     if (cap < K) return GM_ERR_INVALID_ARG;
-    if (centres && K && hipMemcpy(centres, c->centres, (size_t)K * c->dims * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    if (centres && K &&
+        hipMemcpyAsync(centres, c->centres, (size_t)K * c->dims * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
       return GM_ERR_HIP;
-    if (heights && K && hipMemcpy(heights, c->heights, (size_t)K * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    if (heights && K && hipMemcpyAsync(heights, c->heights, (size_t)K * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
       return GM_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return GM_ERR_HIP;
   }
   return GM_OK;
 }
@@ -725,24 +781,24 @@ int gm_hills_get(gm_ctx* c, double* centres, double* heights, int64_t cap, int64
 int gm_hills_set(gm_ctx* c, const double* centres, const double* heights, int64_t k) {
   if (!c || k < 0 || k > c->p.hill_capacity) return GM_ERR_INVALID_ARG;
   if (k > 0 && (!centres || !heights)) return GM_ERR_INVALID_ARG;
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
-  if (k && hipMemcpy(c->centres, centres, (size_t)k * c->dims * 8, hipMemcpyHostToDevice) != hipSuccess)
+  // in stream order; the wait at the end is for the host buffers to be read
+  hipStream_t st = c->stream;
+  if (k && hipMemcpyAsync(c->centres, centres, (size_t)k * c->dims * 8, hipMemcpyHostToDevice, st) != hipSuccess)
     return GM_ERR_HIP;
-  if (k && hipMemcpy(c->heights, heights, (size_t)k * 8, hipMemcpyHostToDevice) != hipSuccess) return GM_ERR_HIP;
-  if (hipMemcpy(c->hill_count, &k, 8, hipMemcpyHostToDevice) != hipSuccess) return GM_ERR_HIP;
-  return GM_OK;
+  if (k && hipMemcpyAsync(c->heights, heights, (size_t)k * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+    return GM_ERR_HIP;
+  if (hipMemcpyAsync(c->hill_count, &k, 8, hipMemcpyHostToDevice, st) != hipSuccess) return GM_ERR_HIP;
+  return hipStreamSynchronize(st) == hipSuccess ? GM_OK : GM_ERR_HIP;
 }
 
 int gm_status(gm_ctx* c, int sync) {
   if (!c) return GM_ERR_INVALID_ARG;
   if (!sync) return c->last_status;
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
   int32_t bits = 0;
-  if (hipMemcpy(&bits, c->err, 4, hipMemcpyDeviceToHost) != hipSuccess) return GM_ERR_HIP;
-  if (bits) {
-    const int32_t zero = 0;
-    if (hipMemcpy(c->err, &zero, 4, hipMemcpyHostToDevice) != hipSuccess) return GM_ERR_HIP;
-  }
+  if (hipMemcpyAsync(&bits, c->err, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return GM_ERR_HIP;
+  if (bits && launch_fill_i32(c->err, 0, 1, c->stream) != hipSuccess) return GM_ERR_HIP;
   c->last_status = status_from_bits(bits);
   return c->last_status;
 }
@@ -756,9 +812,10 @@ int gm_neighbor_stats(gm_ctx* c, int32_t* max_count, int64_t* total, int64_t* cu
       GM_TRY(hip_rc(launch_sum_i32(c->ccnt, c->n * c->bg.tpa, reinterpret_cast<unsigned long long*>(c->stats + 4),
                                    c->stream)));
   }
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
   int32_t s[8];
-  if (hipMemcpy(s, c->stats, 32, hipMemcpyDeviceToHost) != hipSuccess) return GM_ERR_HIP;
+  if (hipMemcpyAsync(s, c->stats, 32, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return GM_ERR_HIP;
   if (max_count) *max_count = s[0];
   unsigned long long t;
   if (total) {
@@ -775,14 +832,13 @@ int gm_neighbor_stats(gm_ctx* c, int32_t* max_count, int64_t* total, int64_t* cu
 int gm_reserve_neighbors(gm_ctx* c, int32_t max_neighbors) {
   if (c && c->external) return GM_ERR_STATE;
   if (!c || max_neighbors < 1 || max_neighbors > 4096) return GM_ERR_INVALID_ARG;
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return GM_ERR_HIP;
-  dfree(c->nbr);
-  dfree(c->cut);
+  dfree(c->stream, c->nbr);
+  dfree(c->stream, c->cut);
   c->kmax = (max_neighbors + 3) / 4 * 4;
   c->built = c->fwd = c->bwd = false;
   c->version++;
-  GM_TRY(dalloc(&c->nbr, (size_t)c->n * (c->kmax + 32) * 2));
-  return dalloc(&c->cut, (size_t)c->n * (c->kmax + 32) * 2);
+  GM_TRY(dalloc(c->stream, &c->nbr, (size_t)c->n * (c->kmax + 32) * 2));
+  return dalloc(c->stream, &c->cut, (size_t)c->n * (c->kmax + 32) * 2);
 }
 
 int gm_copy_cell_list(gm_ctx* c, int32_t* perm_dev, int32_t* cell_start_dev, int32_t* ncell) {
@@ -850,11 +906,11 @@ void append(std::vector<unsigned char>& v, const T& x) {
   v.insert(v.end(), p, p + sizeof(T));
 }
 
+// Replace a device table with a host image, in stream order on st (no wait).
 int upload(std::vector<unsigned char>& host, void** dev, hipStream_t st) {
-  dfree(*dev);
-  GM_TRY(dalloc(dev, host.size()));
-  if (hipMemcpyAsync(*dev, host.data(), host.size(), hipMemcpyHostToDevice, st) != hipSuccess) return GM_ERR_HIP;
-  return hipStreamSynchronize(st) == hipSuccess ? GM_OK : GM_ERR_HIP;
+  dfree(st, *dev);
+  GM_TRY(dalloc(st, dev, (host.size() + 3) / 4 * 4));
+  return hip_rc(launch_upload(*dev, host.data(), host.size(), st));
 }
 
 int upload_i32(const std::vector<int32_t>& v, int32_t** dev, hipStream_t st) {
@@ -948,13 +1004,13 @@ int batch_step_t(gm_batch* B) {
 
 void free_batch(gm_batch* B) {
   for (auto& g : B->groups) {
-    dfree(g.d_cv);
-    dfree(g.d_gather);
-    dfree(g.d_bias);
-    dfree(g.d_dep);
-    dfree(g.d_blk_cv);
-    dfree(g.d_blk_gather);
-    dfree(g.d_blk_bias);
+    dfree(B->stream, g.d_cv);
+    dfree(B->stream, g.d_gather);
+    dfree(B->stream, g.d_bias);
+    dfree(B->stream, g.d_dep);
+    dfree(B->stream, g.d_blk_cv);
+    dfree(B->stream, g.d_blk_gather);
+    dfree(B->stream, g.d_blk_bias);
   }
 }
 
@@ -1098,7 +1154,6 @@ int gm_batch_create(gm_batch** out, gm_ctx* const* walkers, int32_t count, const
 
 int gm_batch_destroy(gm_batch* B) {
   if (!B) return GM_ERR_INVALID_ARG;
-  (void)hipStreamSynchronize(B->stream);
   free_batch(B);
   delete B;
   return GM_OK;

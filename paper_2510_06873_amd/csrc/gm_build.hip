@@ -6,6 +6,8 @@
 // that one workgroup each handles; a brick's atoms and its one-cell halo are
 // addressed by "slots" in halo-cell order, which is also how the neighbour
 // rows refer to neighbours (16-bit entries).
+#include <string.h>
+
 #include "gm_device.h"
 
 namespace gm {
@@ -166,22 +168,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ 
   perm[start[c] + slot] = (int32_t)i;
 }
 
-// The atomic scatter leaves each cell's atoms in arbitrary order; sorting each
-// (short) segment by atom id makes the permutation the unique stable order.
-__global__ __launch_bounds__(kBlock) void k_sort_cells(const int32_t* __restrict__ start, int64_t ncells,
+// The atomic scatter leaves each cell's atoms in arbitrary order; placing each
+// atom at its rank by id within its cell's segment makes the permutation the
+// unique stable order.  One thread per atom counts the smaller ids of its
+// segment (the segment's reads are shared by its atoms and cached), so dense
+// cells cost linear time per atom instead of a quadratic sort per cell.
+__global__ __launch_bounds__(kBlock) void k_rank_cells(const int32_t* __restrict__ cell,
+                                                       const int32_t* __restrict__ start,
+                                                       const int32_t* __restrict__ scattered, int64_t n,
                                                        int32_t* __restrict__ perm) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncells) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int32_t v = scattered[t];
+  const int32_t c = cell[v];
   const int32_t b = start[c], e = start[c + 1];
-  for (int32_t i = b + 1; i < e; i++) {
-    int32_t v = perm[i];
-    int32_t k = i - 1;
-    while (k >= b && perm[k] > v) {
-      perm[k + 1] = perm[k];
-      k--;
-    }
-    perm[k + 1] = v;
-  }
+  int32_t r = 0;
+  for (int32_t k = b; k < e; k++) r += scattered[k] < v ? 1 : 0;
+  perm[b + r] = v;
 }
 
 template <typename T>
@@ -319,17 +322,25 @@ __global__ __launch_bounds__(kBlock) void k_brick_fill(const int32_t* __restrict
 // r_list^2 the FP32 answer is the FP64 one, and only pairs inside the band
 // are tested in FP64.  The bound needs coordinates inside [0, L) (then the
 // minimum image rounds once, at the pair's magnitude); if the gather flagged
-// any outside, every pair takes the FP64 test.  Candidates are the atoms of the 27 cells around the
-// atom's own cell: nine runs of three x-adjacent halo cells, whose slots are
-// contiguous, visited in a fixed order.
+// any outside, every pair takes the FP64 test.  Candidates are the atoms of
+// the 27 cells around the atom's own cell: nine runs of three x-adjacent halo
+// cells, whose slots are contiguous, visited in a fixed order.
+//
+// A group of kBuildGroup lanes builds one atom's row: it tests kBuildGroup
+// consecutive candidates of a run at once, and a ballot gives each lane that
+// passes the number of passing lanes before it, i.e. its entry index.  The
+// row therefore holds the candidates in run order and slot order within a
+// run, the order of a sequential scan.  Entry e lives in sub-row e % tpa at
+// index e / tpa; the rest of each sub-row's last 16-byte piece is zeroed,
+// since the CV passes read rows in whole pieces.
 // MODE 0: FP32 plain differences (halo off the faces), 1: FP32 minimum image,
 // 2: FP64 only (coordinates outside the box).
 template <int MODE, typename T>
 __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, const CellGeom& cg,
                                            const BrickGeom& g, const BrickIndex& bi, double rl2, uint16_t* nbr,
                                            int32_t kmax, int32_t* cnt, int32_t* err, const float4* hpos,
-                                           const int32_t* hp, int32_t hb, int32_t ob, int32_t O, int32_t hx,
-                                           int32_t hxy, int32_t& mymax, double& mysum) {
+                                           const int32_t* hp, int32_t hb, int32_t ob, int32_t k0, int32_t k1,
+                                           int32_t hx, int32_t hxy, int32_t& mymax, double& mysum) {
 #pragma clang fp contract(off)
   float Lf[3], iLf[3], Llo[3];
 #pragma unroll
@@ -339,82 +350,82 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
     Llo[d] = (float)(cg.L[d] - (double)Lf[d]);
   }
   const float lo2 = (float)(rl2 * (1.0 - 4e-6)), hi2 = (float)(rl2 * (1.0 + 4e-6));
-  for (int32_t k = threadIdx.x; k < O; k += blockDim.x) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int lig = lane & (kBuildGroup - 1);
+  const uint64_t gmask = ((1ull << kBuildGroup) - 1) << (lane - lig);
+  const uint64_t below = gmask & ((1ull << lane) - 1);
+  const int32_t groups = (int32_t)(blockDim.x / kBuildGroup);
+  const int32_t tsh = g.tpa == 4 ? 2 : (g.tpa == 2 ? 1 : 0);
+  const int32_t cap = g.build_cap;
+  for (int32_t k = k0 + (int32_t)(threadIdx.x / kBuildGroup); k < k1; k += groups) {
     const int32_t si = bi.owned_slot[ob + k];
     const int32_t hc = bi.owned_hcell[ob + k];
     float4 pi;
-    if (si < g.cap) {
+    if (si < cap) {
       pi = hpos[si];
     } else {
       const vec4_t<T> p = pos_s[bi.halo_rank[hb + si]];
       pi = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
     }
-    int32_t count = 0;
-    // entry e of the row goes to sub-row e % tpa; each sub-row is written in
-    // 16-byte pieces
-    SlotWriter w0, w1, w2, w3;
-    w0.init(nbr + subrow(g, ob, k, 0));
-    w1.init(nbr + subrow(g, ob, k, g.tpa > 1 ? 1 : 0));
-    w2.init(nbr + subrow(g, ob, k, g.tpa > 2 ? 2 : 0));
-    w3.init(nbr + subrow(g, ob, k, g.tpa > 3 ? 3 : 0));
+    int32_t count = 0;  // the same in every lane of the group
     for (int cz = -1; cz <= 1; cz++)
       for (int cy = -1; cy <= 1; cy++) {
         const int h = hc + cz * hxy + cy * hx;  // middle cell of the x-run
         const int32_t se = hp[h + 2];
-        for (int32_t sl = hp[h - 1]; sl < se; sl++) {
-          if (sl == si) continue;
-          float4 pj;
-          if (sl < g.cap) {
-            pj = hpos[sl];
-          } else {
-            const vec4_t<T> p = pos_s[bi.halo_rank[hb + sl]];
-            pj = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
-          }
-          float ex, ey, ez;
-          if constexpr (MODE == 1) {
-            ex = mic(pj.x, pi.x, Lf[0], iLf[0], Llo[0]);
-            ey = mic(pj.y, pi.y, Lf[1], iLf[1], Llo[1]);
-            ez = mic(pj.z, pi.z, Lf[2], iLf[2], Llo[2]);
-          } else {
-            ex = pj.x - pi.x;
-            ey = pj.y - pi.y;
-            ez = pj.z - pi.z;
-          }
-          const float r2f = (ex * ex + ey * ey) + ez * ez;
-          bool in = MODE != 2 && r2f < lo2;
-          if (MODE == 2 || (!in && r2f <= hi2)) {
-            double d0 = (double)pj.x - (double)pi.x;
-            double d1 = (double)pj.y - (double)pi.y;
-            double d2 = (double)pj.z - (double)pi.z;
-            d0 = d0 - cg.L[0] * rint(d0 * cg.invL[0]);
-            d1 = d1 - cg.L[1] * rint(d1 * cg.invL[1]);
-            d2 = d2 - cg.L[2] * rint(d2 * cg.invL[2]);
-            in = d0 * d0 + d1 * d1 + d2 * d2 < rl2;
-          }
-          if (in) {
-            if (count < kmax) {
-              const int prt = count & (g.tpa - 1);
-              if (prt == 0)
-                w0.push(sl);
-              else if (prt == 1)
-                w1.push(sl);
-              else if (prt == 2)
-                w2.push(sl);
-              else
-                w3.push(sl);
+        for (int32_t base = hp[h - 1]; base < se; base += kBuildGroup) {
+          const int32_t sl = base + lig;
+          bool in = false;
+          if (sl < se && sl != si) {
+            float4 pj;
+            if (sl < cap) {
+              pj = hpos[sl];
+            } else {
+              const vec4_t<T> p = pos_s[bi.halo_rank[hb + sl]];
+              pj = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
             }
-            count++;
+            float ex, ey, ez;
+            if constexpr (MODE == 1) {
+              ex = mic(pj.x, pi.x, Lf[0], iLf[0], Llo[0]);
+              ey = mic(pj.y, pi.y, Lf[1], iLf[1], Llo[1]);
+              ez = mic(pj.z, pi.z, Lf[2], iLf[2], Llo[2]);
+            } else {
+              ex = pj.x - pi.x;
+              ey = pj.y - pi.y;
+              ez = pj.z - pi.z;
+            }
+            const float r2f = (ex * ex + ey * ey) + ez * ez;
+            in = MODE != 2 && r2f < lo2;
+            if (MODE == 2 || (!in && r2f <= hi2)) {
+              double d0 = (double)pj.x - (double)pi.x;
+              double d1 = (double)pj.y - (double)pi.y;
+              double d2 = (double)pj.z - (double)pi.z;
+              d0 = d0 - cg.L[0] * rint(d0 * cg.invL[0]);
+              d1 = d1 - cg.L[1] * rint(d1 * cg.invL[1]);
+              d2 = d2 - cg.L[2] * rint(d2 * cg.invL[2]);
+              in = d0 * d0 + d1 * d1 + d2 * d2 < rl2;
+            }
           }
+          const uint64_t m = __ballot(in);
+          if (in) {
+            const int32_t e = count + __popcll(m & below);
+            if (e < kmax) nbr[subrow(g, ob, k, e & (g.tpa - 1)) + (e >> tsh)] = (uint16_t)sl;
+          }
+          count += __popcll(m & gmask);
         }
       }
-    w0.flush();
-    if (g.tpa > 1) w1.flush();
-    if (g.tpa > 2) w2.flush();
-    if (g.tpa > 3) w3.flush();
-    cnt[ob + k] = count;
-    if (count > kmax) atomicOr(err, kErrOverflow);
-    mymax = count > mymax ? count : mymax;
-    mysum += (double)count;
+    const int32_t stored = count < kmax ? count : kmax;
+    for (int32_t i = lig; i < 8 * g.tpa; i += kBuildGroup) {
+      const int32_t part = i >> 3;
+      const int32_t np = stored > part ? ((stored - 1 - part) >> tsh) + 1 : 0;
+      const int32_t at = np + (i & 7);
+      if (at < ((np + 7) & ~7)) nbr[subrow(g, ob, k, part) + at] = 0;
+    }
+    if (lig == 0) {
+      cnt[ob + k] = count;
+      if (count > kmax) atomicOr(err, kErrOverflow);
+      mymax = count > mymax ? count : mymax;
+      mysum += (double)count;
+    }
   }
 }
 
@@ -428,9 +439,14 @@ __global__ __launch_bounds__(MAXT) void k_build_nbr(const vec4_t<T>* __restrict_
   __shared__ int32_t hp[kHaloCells + 1];
   __shared__ double red[MAXT / 64];
   __shared__ int32_t wmax[MAXT / 64];
-  const int64_t b = logical_brick(g);
+  // build_split workgroups share a brick (consecutive logical indices, so on
+  // one XCD): each stages the brick's halo and builds the rows of a
+  // contiguous share of its owned atoms.
+  const int64_t lb = logical_brick(g);
+  const int64_t b = lb / g.build_split;
+  const int32_t part = (int32_t)(lb - b * g.build_split);
   const bool live = b < g.nbricks;
-  int32_t hb = 0, H = 0, ob = 0, O = 0, hx = 0, hxy = 0;
+  int32_t hb = 0, H = 0, ob = 0, k0 = 0, k1 = 0, hx = 0, hxy = 0;
   int mode = 2;
   if (live) {
     const BrickShape s = brick_shape(b, g);
@@ -439,11 +455,14 @@ __global__ __launch_bounds__(MAXT) void k_build_nbr(const vec4_t<T>* __restrict_
     hb = bi.hb[b];
     H = bi.hb[b + 1] - hb;
     ob = bi.ob[b];
-    O = bi.ob[b + 1] - ob;
+    const int32_t O = bi.ob[b + 1] - ob;
+    const int32_t share = (O + g.build_split - 1) / g.build_split;
+    k0 = part * share < O ? part * share : O;
+    k1 = k0 + share < O ? k0 + share : O;
     mode = err[1] != 0 ? 2 : (halo_touches_face(s, g) ? 1 : 0);
     const int nh = s.h[0] * s.h[1] * s.h[2];
     for (int h = threadIdx.x; h <= nh; h += blockDim.x) hp[h] = bi.hp[b * (kHaloCells + 1) + h];
-    const int32_t ns = H < g.cap ? H : g.cap;
+    const int32_t ns = H < g.build_cap ? H : g.build_cap;
     for (int32_t sl = threadIdx.x; sl < ns; sl += blockDim.x) {
       const vec4_t<T> p = pos_s[bi.halo_rank[hb + sl]];
       hpos[sl] = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
@@ -453,11 +472,14 @@ __global__ __launch_bounds__(MAXT) void k_build_nbr(const vec4_t<T>* __restrict_
   int32_t mymax = 0;
   double mysum = 0.0;
   if (mode == 0)
-    build_rows<0, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, hx, hxy, mymax, mysum);
+    build_rows<0, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, k0, k1, hx, hxy, mymax,
+                     mysum);
   else if (mode == 1)
-    build_rows<1, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, hx, hxy, mymax, mysum);
+    build_rows<1, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, k0, k1, hx, hxy, mymax,
+                     mysum);
   else
-    build_rows<2, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, hx, hxy, mymax, mysum);
+    build_rows<2, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, k0, k1, hx, hxy, mymax,
+                     mysum);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const int32_t v = __shfl_down(mymax, o, 64);
@@ -520,6 +542,35 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+// A small host image copied into device memory inside the kernel arguments,
+// which the runtime copies when the launch is enqueued: the host buffer may
+// go away as soon as this returns, and nothing waits for the stream (a copy
+// from pageable memory may).  Pieces of kUploadWords words per launch keep the
+// arguments under the 4 KiB limit.
+constexpr int kUploadWords = 896;
+struct UploadPiece {
+  uint32_t w[kUploadWords];
+};
+
+__global__ void k_upload(uint32_t* dst, UploadPiece src, int32_t n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src.w[i];
+}
+
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  const unsigned char* s = static_cast<const unsigned char*>(src);
+  uint32_t* d = static_cast<uint32_t*>(dst);
+  for (size_t off = 0; off < bytes; off += sizeof(UploadPiece)) {
+    UploadPiece piece;
+    const size_t nb = bytes - off < sizeof(UploadPiece) ? bytes - off : sizeof(UploadPiece);
+    memset(&piece, 0, sizeof(piece));
+    memcpy(piece.w, s + off, nb);
+    k_upload<<<1, kBlock, 0, st>>>(d + off / 4, piece, (int32_t)((nb + 3) / 4));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_cell_ids(const float4* pos, int64_t n, const CellGeom& g, int32_t* cell, int32_t* count,
                            int32_t* err, hipStream_t st) {
   k_cell_ids<<<grid_of(n, kBlock), kBlock, 0, st>>>(pos, n, g, cell, count, err);
@@ -561,8 +612,9 @@ hipError_t launch_scatter(const int32_t* cell, int64_t n, const int32_t* start, 
   return hipGetLastError();
 }
 
-hipError_t launch_sort_cells(const int32_t* start, int64_t ncells, int32_t* perm, hipStream_t st) {
-  k_sort_cells<<<grid_of(ncells, kBlock), kBlock, 0, st>>>(start, ncells, perm);
+hipError_t launch_rank_cells(const int32_t* cell, const int32_t* start, const int32_t* scattered, int64_t n,
+                             int32_t* perm, hipStream_t st) {
+  k_rank_cells<<<grid_of(n, kBlock), kBlock, 0, st>>>(cell, start, scattered, n, perm);
   return hipGetLastError();
 }
 
@@ -589,11 +641,14 @@ template <typename T>
 hipError_t launch_build_nbr(const vec4_t<T>* pos_s, const CellGeom& cg, const BrickGeom& g, const BrickIndex& bi,
                             double rl2, uint16_t* nbr, int32_t kmax, int32_t* cnt, int32_t* err, int32_t* stats,
                             hipStream_t st) {
-  const size_t lds = (size_t)g.cap * sizeof(float4);
+  const size_t lds = (size_t)g.build_cap * sizeof(float4);
+  const unsigned grid = (unsigned)((int64_t)g.blocks * g.build_split);
   if (g.build_threads <= kBlock)
-    k_build_nbr<T, kBlock><<<(unsigned)g.blocks, kBlock, lds, st>>>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, stats);
+    k_build_nbr<T, kBlock><<<grid, (unsigned)g.build_threads, lds, st>>>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err,
+                                                                         stats);
   else
-    k_build_nbr<T, kBuildMaxThreads><<<(unsigned)g.blocks, (unsigned)g.build_threads, lds, st>>>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, stats);
+    k_build_nbr<T, kBuildMaxThreads><<<grid, (unsigned)g.build_threads, lds, st>>>(pos_s, cg, g, bi, rl2, nbr, kmax,
+                                                                                   cnt, err, stats);
   return hipGetLastError();
 }
 

@@ -10,7 +10,10 @@
 namespace gm {
 
 constexpr int kBlock = 256;  // threads per block of the per-atom kernels (4 waves)
-constexpr int kBuildMaxThreads = 1024;  // largest workgroup of the neighbour build
+constexpr int kBuildMaxThreads = 512;   // largest workgroup of the neighbour build
+constexpr int kBuildGroup = 8;          // lanes that build one atom's row together
+constexpr int kBuildFillBlocks = 1024;  // workgroups a neighbour build aims for (4 per CU)
+constexpr int kBuildMaxSplit = 32;      // most workgroups sharing one brick in the build
 constexpr int kXcd = 8;      // workgroups are dealt to the 8 XCDs round-robin
 constexpr int32_t kMaxTorsions = 1 << 16;   // torsion forces are summed by one thread in order
 constexpr int64_t kMaxFesBins = 1 << 24;
@@ -88,7 +91,9 @@ struct BrickGeom {
   int32_t blocks;  // workgroups launched per brick pass (nbricks rounded up to the XCD count)
   int32_t tpa;     // threads per owned atom (1, 2 or 4): lanes that split one atom's rows
   int32_t kpart;   // length of one part's sub-row (multiple of 8 entries, 16-byte aligned)
-  int32_t build_threads;  // workgroup size of the neighbour build (one thread per owned atom)
+  int32_t build_threads;  // workgroup size of the neighbour build (kBuildGroup lanes per atom)
+  int32_t build_split;    // workgroups per brick in the neighbour build (each takes a share of its atoms)
+  int32_t build_cap;      // halo slots the neighbour build stages in LDS (slots beyond: global memory)
 };
 
 struct BrickIndex {
@@ -166,6 +171,9 @@ struct GatherArgs {
 
 // ---- launchers -------------------------------------------------------------
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+// Copy bytes of host memory to dst (device, at least bytes rounded up to a
+// multiple of 4) through kernel arguments; src may be freed on return.
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t st);
 hipError_t launch_cell_ids(const float4* pos, int64_t n, const CellGeom& g, int32_t* cell,
                            int32_t* count, int32_t* err, hipStream_t st);
 // tmp: device int32[(n + 1023)/1024] scratch for the tile sums
@@ -175,7 +183,9 @@ hipError_t launch_scan2(const int32_t* in0, int32_t* out0, const int32_t* in1, i
 hipError_t launch_reset_build(int32_t* count, int64_t ncells, int32_t* stats, int32_t* err, hipStream_t st);
 hipError_t launch_scatter(const int32_t* cell, int64_t n, const int32_t* start, int32_t* fill,
                           int32_t* perm, hipStream_t st);
-hipError_t launch_sort_cells(const int32_t* start, int64_t ncells, int32_t* perm, hipStream_t st);
+// perm[start[c] + rank] = atom: each cell's atoms of `scattered` in id order.
+hipError_t launch_rank_cells(const int32_t* cell, const int32_t* start, const int32_t* scattered, int64_t n,
+                             int32_t* perm, hipStream_t st);
 hipError_t launch_brick_count(const int32_t* start, const BrickGeom& g, int32_t* H, int32_t* O,
                               hipStream_t st);
 hipError_t launch_brick_fill(const int32_t* start, const BrickGeom& g, const BrickIndex& bi,

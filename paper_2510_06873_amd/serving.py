@@ -8,6 +8,14 @@ tick boundaries while a slot and HBM budget are free, and advances every
 active walker by one step per tick with one launch per pass for all of them
 (``Batch``).  Finished walkers free their slot and memory for the queue.
 
+The batch stream never waits for the host: admissions (context creation, the
+hill and position uploads, the first build and its overflow check) run on an
+admission stream whose synchronous calls wait for admission work only, and a
+finished walker's CV, bias and forces are copied to pinned host memory behind
+an event that the loop polls; its status check and release follow once the
+event has completed.  The library's buffers come from a stream-ordered pool,
+so creating and releasing walkers does not stall the device either.
+
 ``serve_sequential`` runs the same requests one after another with the
 per-walker calls, the baseline the batched loop is measured against.
 """
@@ -93,6 +101,18 @@ def _finish(w: _Walker, t: float, admitted: float, keep_forces: bool) -> Result:
                   w.F.cpu().numpy().copy() if keep_forces else None)
 
 
+@dataclass
+class _Retiring:
+    """Walkers that finished at one tick: host copies of their results land
+    behind ``event`` on the batch stream."""
+    event: object
+    walkers: list
+    s: object                   # pinned (W, 2) CVs of the whole batch at that tick
+    V: object                   # pinned (W,) biases
+    rows: list                  # row of each walker in s / V
+    forces: list                # pinned force copies (keep_forces) or None
+
+
 def _rebuild_concurrently(walkers, stream, aux):
     """Neighbour rebuilds of several walkers, spread over the auxiliary streams
     so that their chains of small kernels overlap on the device.  Each rebuild
@@ -119,9 +139,11 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
 
     dev = device or torch.device("cuda", 0)
     stream = torch.cuda.Stream(device=dev)
+    adm = torch.cuda.Stream(device=dev)
     aux = [torch.cuda.Stream(device=dev) for _ in range(rebuild_streams)]
     pending = sorted(requests, key=lambda r: r.arrival)
     active: List[_Walker] = []
+    retiring: List[_Retiring] = []
     admitted_at = {}
     results: List[Result] = []
     used = 0
@@ -130,20 +152,47 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
     batch = None
     members = None
     t0 = time.perf_counter()
+
+    def retire(entry: _Retiring):
+        nonlocal used
+        entry.event.synchronize()
+        t = time.perf_counter() - t0
+        for w, k, F in zip(entry.walkers, entry.rows, entry.forces):
+            # the event covers every use of the walker on the batch stream, so
+            # its status read and its release go to the admission stream
+            w.pipe.set_stream(adm)
+            w.pipe.check()
+            results.append(Result(w.req.rid, w.req.n, w.req.arrival, admitted_at[w.req.rid], t,
+                                  entry.s[k, :w.pipe.dims].numpy().copy(), float(entry.V[k]),
+                                  F.numpy().copy() if F is not None else None))
+            used -= w.bytes
+            w.close()
+
     with torch.cuda.stream(stream):
-        while pending or active:
+        while pending or active or retiring:
+            while retiring and retiring[0].event.query():
+                retire(retiring.pop(0))
             now = time.perf_counter() - t0
+            joined = False
             while (pending and pending[0].arrival <= now and len(active) < max_slots
                    and used + device_bytes(pending[0]) <= hbm_budget):
                 req = pending.pop(0)
-                w = _Walker(req, dev, torch, stream)
-                w.pipe.build_neighbors_checked(w.pos, req.box)
+                with torch.cuda.stream(adm):
+                    w = _Walker(req, dev, torch, adm)
+                    w.pipe.build_neighbors_checked(w.pos, req.box)  # waits for admission work only
+                w.pos.record_stream(stream)
+                w.F.record_stream(stream)
                 active.append(w)
+                joined = True
                 used += w.bytes
                 peak_used = max(peak_used, used)
                 admitted_at[req.rid] = time.perf_counter() - t0
+            if joined:
+                stream.wait_stream(adm)
             if not active:
-                if pending:
+                if retiring:
+                    retire(retiring.pop(0))
+                elif pending:
                     time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
                 continue
             ids = tuple(w.req.rid for w in active)
@@ -164,22 +213,26 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
             finished = [w for w in active if w.done >= w.req.steps]
             if finished:
                 s, V = batch.values()
-                for w in active:
-                    k = members.index(w.req.rid)
-                    w.pipe.s = s[k, :w.pipe.dims].clone()
-                    w.pipe.V = V[k:k + 1].clone()
-                stream.synchronize()
-                t = time.perf_counter() - t0
+                s_h = torch.empty(s.shape, dtype=s.dtype, pin_memory=True)
+                V_h = torch.empty(V.shape, dtype=V.dtype, pin_memory=True)
+                s_h.copy_(s, non_blocking=True)
+                V_h.copy_(V, non_blocking=True)
+                forces = []
                 for w in finished:
-                    w.pipe.check()
-                    results.append(_finish(w, t, admitted_at[w.req.rid], keep_forces))
-                    used -= w.bytes
+                    if keep_forces:
+                        F_h = torch.empty(w.F.shape, dtype=w.F.dtype, pin_memory=True)
+                        F_h.copy_(w.F, non_blocking=True)
+                        forces.append(F_h)
+                    else:
+                        forces.append(None)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+                retiring.append(_Retiring(ev, finished, s_h, V_h, [members.index(w.req.rid) for w in finished],
+                                          forces))
                 active = [w for w in active if w.done < w.req.steps]
                 batch.close()
                 batch = None
                 members = None
-                for w in finished:
-                    w.close()
         stream.synchronize()
     wall = time.perf_counter() - t0
     return results, _stats(results, wall, ticks=ticks, peak_bytes=peak_used)

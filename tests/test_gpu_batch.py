@@ -77,3 +77,52 @@ def test_batch_bitwise_equals_solo():
         assert np.array_equal(forces[k].cpu().numpy(), F_solo), k
         c, h = p.hills_get()
         assert np.array_equal(c, c_solo) and np.array_equal(h, h_solo), k
+
+
+def _run_solo(wl, d, dev, k, steps):
+    pipe, p4, F = setup(wl, d, dev, k)
+    for step in range(steps):
+        if step == 1:
+            pipe.deposit_hill()
+        pipe.step(p4, F)
+    return pipe, F
+
+
+def test_context_churn_on_another_stream():
+    """Contexts created, stepped and destroyed on one stream while another
+    context steps on a second stream: every result is bitwise that of a quiet
+    run on the default stream (buffers are allocated, zero-filled and released
+    in stream order, with no device-wide wait to keep them apart)."""
+    dev = torch.device("cuda", 0)
+    ws = walkers()
+    long_k, long_steps = 3, 12
+    ref = {}
+    for k, (wl, d) in enumerate(ws):
+        pipe, F = _run_solo(wl, d, dev, k, long_steps if k == long_k else 3)
+        torch.cuda.synchronize()
+        ref[k] = (pipe.s.cpu().numpy().copy(), pipe.V.item(), F.cpu().numpy().copy(), pipe.hills_get())
+        pipe.close()
+    sA, sB = torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(sA):
+        wl, d = ws[long_k]
+        pA, FA = _run_solo(wl, d, dev, long_k, long_steps)  # enqueued on sA, not waited for
+    for rnd in range(2):
+        for k in (0, 1, 2, 4):
+            with torch.cuda.stream(sB):
+                pipe, F = _run_solo(ws[k][0], ws[k][1], dev, k, 3)
+                got = (pipe.s.cpu().numpy().copy(), pipe.V.item(), F.cpu().numpy().copy(), pipe.hills_get())
+                assert pipe.status(True) == 0
+                pipe.close()
+            s, V, Fr, (c, h) = ref[k]
+            assert np.array_equal(got[0], s) and got[1] == V, (rnd, k)
+            assert np.array_equal(got[2], Fr), (rnd, k)
+            assert np.array_equal(got[3][0], c) and np.array_equal(got[3][1], h), (rnd, k)
+    sA.synchronize()
+    with torch.cuda.stream(sA):
+        assert pA.status(True) == 0
+        s, V, Fr, (c, h) = ref[long_k]
+        assert np.array_equal(pA.s.cpu().numpy(), s) and pA.V.item() == V
+        assert np.array_equal(FA.cpu().numpy(), Fr)
+        cA, hA = pA.hills_get()
+        assert np.array_equal(cA, c) and np.array_equal(hA, h)
+        pA.close()
