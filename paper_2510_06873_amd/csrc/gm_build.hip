@@ -43,6 +43,35 @@ __device__ __forceinline__ bool cell_coords(float4 p, const CellGeom& g, int32_t
   return ok;
 }
 
+// atomicAdd(&base[key], 1) for every active lane of the wave, with one
+// atomic per distinct key: atoms arrive in spatially coherent order, so a
+// wave's lanes mostly share a few cells and would otherwise queue on the same
+// addresses.  The lanes first find, without touching memory, the lowest lane
+// holding their key (the group's leader) and their rank in the group; then
+// every leader adds its group's size in one atomic instruction.  Returns the
+// value the lane's own increment would have seen (equal keys take
+// consecutive values in lane order).
+__device__ __forceinline__ int32_t wave_count_add(int32_t* base, int32_t key) {
+  const int lane = (int)(threadIdx.x & 63);
+  uint64_t todo = __ballot(1);
+  int leader = lane;
+  int32_t rank = 0, size = 1;
+  while (todo != 0) {
+    const int first = __ffsll((unsigned long long)todo) - 1;
+    const int32_t fk = __shfl(key, first, 64);
+    const uint64_t same = __ballot(key == fk) & todo;
+    if ((same >> lane) & 1ull) {
+      leader = first;
+      rank = (int32_t)__popcll(same & ((1ull << lane) - 1ull));
+      size = (int32_t)__popcll(same);
+    }
+    todo &= ~same;
+  }
+  int32_t old = 0;
+  if (lane == leader) old = atomicAdd(&base[key], size);
+  return __shfl(old, leader, 64) + rank;
+}
+
 __global__ __launch_bounds__(kBlock) void k_cell_ids(const float4* __restrict__ pos, int64_t n,
                                                      CellGeom g, int32_t* __restrict__ cell,
                                                      int32_t* __restrict__ count, int32_t* err) {
@@ -52,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids(const float4* __restrict__ 
   if (!cell_coords(pos[i], g, c)) atomicOr(err, kErrNonFinite);
   int32_t id = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
   cell[i] = id;
-  atomicAdd(&count[id], 1);
+  (void)wave_count_add(count, id);
 }
 
 // Exclusive prefix sum of n int32 values, out[n] = total, in three launches:
@@ -163,8 +192,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ 
                                                     int32_t* __restrict__ fill, int32_t* __restrict__ perm) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int32_t c = cell[i];
-  int32_t slot = atomicAdd(&fill[c], 1);
+  const int32_t c = cell[i];
+  const int32_t slot = wave_count_add(fill, c);
   perm[start[c] + slot] = (int32_t)i;
 }
 

@@ -196,13 +196,17 @@ __device__ __forceinline__ void grad_s(const YCoef<T>& c, T ux, T uy, T uz, cons
                                        T& Sx, T& Sy, T& Sz) {
   T E[7];
   eval_E(c, uz, E);
-  S = w[0] * E[0];
-  Sz = w[0] * c.rat[0] * E[1];
-  Sx = T(0);
-  Sy = T(0);
-  T Rp = T(1), Ip = T(0), R = ux, I = uy;
+  // m = 1 on its own: zeta^0 = 1, so U = w_1 and V = w_2 (no products with
+  // the zero imaginary part, which IEEE rules keep the compiler from folding)
+  const T T1 = w[1] * ux + w[2] * uy;
+  S = w[0] * E[0] + E[1] * T1;
+  Sx = E[1] * w[1];
+  Sy = E[1] * w[2];
+  Sz = w[0] * c.rat[0] * E[1] + c.rat[1] * E[2] * T1;
+  T Rp = ux, Ip = uy;
+  T R = ux * ux - uy * uy, I = ux * uy + uy * ux;
 #pragma unroll
-  for (int m = 1; m <= 6; m++) {
+  for (int m = 2; m <= 6; m++) {
     const T wa = w[2 * m - 1], wb = w[2 * m];
     const T Tm = wa * R + wb * I;
     const T U = wa * Rp + wb * Ip;
