@@ -16,6 +16,11 @@ an event that the loop polls; its status check and release follow once the
 event has completed.  The library's buffers come from a stream-ordered pool,
 so creating and releasing walkers does not stall the device either.
 
+Walkers are prepared ahead: while a tick's step runs on the device, the loop
+admits queued requests (within the HBM budget, which counts them) into a
+staging list, so that when a group of walkers finishes together the next ones
+join at once instead of being created one by one while the device idles.
+
 ``serve_sequential`` runs the same requests one after another with the
 per-walker calls, the baseline the batched loop is measured against.
 """
@@ -133,8 +138,11 @@ def _rebuild_concurrently(walkers, stream, aux):
 
 
 def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64, keep_forces: bool = False,
-                  device=None, rebuild_streams: int = 3):
-    """Run the requests with continuous batching; returns (results, stats)."""
+                  device=None, rebuild_streams: int = 3, stage_ahead: Optional[int] = None):
+    """Run the requests with continuous batching; returns (results, stats).
+
+    stage_ahead: most walkers prepared ahead of a free slot (default max_slots;
+    0 admits only into free slots)."""
     import torch
 
     dev = device or torch.device("cuda", 0)
@@ -143,6 +151,8 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
     aux = [torch.cuda.Stream(device=dev) for _ in range(rebuild_streams)]
     pending = sorted(requests, key=lambda r: r.arrival)
     active: List[_Walker] = []
+    staged: List[_Walker] = []
+    stage_cap = max_slots if stage_ahead is None else int(stage_ahead)
     retiring: List[_Retiring] = []
     admitted_at = {}
     results: List[Result] = []
@@ -168,25 +178,33 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
             used -= w.bytes
             w.close()
 
+    def can_prepare():
+        return (pending and pending[0].arrival <= time.perf_counter() - t0
+                and used + device_bytes(pending[0]) <= hbm_budget)
+
+    def prepare():
+        nonlocal used, peak_used
+        req = pending.pop(0)
+        with torch.cuda.stream(adm):
+            w = _Walker(req, dev, torch, adm)
+            w.pipe.build_neighbors_checked(w.pos, req.box)  # waits for admission work only
+        w.pos.record_stream(stream)
+        w.F.record_stream(stream)
+        used += w.bytes
+        peak_used = max(peak_used, used)
+        return w
+
     with torch.cuda.stream(stream):
-        while pending or active or retiring:
+        while pending or active or retiring or staged:
             while retiring and retiring[0].event.query():
                 retire(retiring.pop(0))
-            now = time.perf_counter() - t0
+            # free slots take the staged walkers first, then fresh admissions
             joined = False
-            while (pending and pending[0].arrival <= now and len(active) < max_slots
-                   and used + device_bytes(pending[0]) <= hbm_budget):
-                req = pending.pop(0)
-                with torch.cuda.stream(adm):
-                    w = _Walker(req, dev, torch, adm)
-                    w.pipe.build_neighbors_checked(w.pos, req.box)  # waits for admission work only
-                w.pos.record_stream(stream)
-                w.F.record_stream(stream)
+            while len(active) < max_slots and (staged or can_prepare()):
+                w = staged.pop(0) if staged else prepare()
                 active.append(w)
                 joined = True
-                used += w.bytes
-                peak_used = max(peak_used, used)
-                admitted_at[req.rid] = time.perf_counter() - t0
+                admitted_at[w.req.rid] = time.perf_counter() - t0
             if joined:
                 stream.wait_stream(adm)
             if not active:
@@ -210,6 +228,13 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
                 w.done += 1
                 if w.done % w.req.pace == 0:
                     w.pipe.deposit_hill()
+            # prepare walkers for the next free slots while the step runs
+            step_done = torch.cuda.Event()
+            step_done.record(stream)
+            made = 0
+            while len(staged) < stage_cap and can_prepare() and (made == 0 or not step_done.query()):
+                staged.append(prepare())
+                made += 1
             finished = [w for w in active if w.done >= w.req.steps]
             if finished:
                 s, V = batch.values()
