@@ -158,6 +158,36 @@ def test_q6_cv_and_forces(orc, spec, precision, tol_s, tol_f):
     assert np.max(np.abs(pipe.atom_values(ATOM_C).cpu().numpy() - o["c"])) <= 50 * tol_a
 
 
+@pytest.mark.parametrize("precision,tol_s,tol_f", [("fp32", 1e-5, 1e-4), ("fp64", 1e-10, 1e-10)])
+def test_dense_cluster_in_gas(orc, precision, tol_s, tol_f):
+    """Bricks sized for the mean density (3.9 atoms per cell): next to the
+    cluster (about 33 atoms per cell) a brick's halo holds some 1,300 slots,
+    more than the neighbour build and the CV passes stage in LDS (998), so
+    both read the rest from global memory, and such a brick owns more atoms
+    than its workgroup has threads.  The rows start 96 wide and overflow
+    (131 neighbours in the cluster), so the checked build grows them.  Bond
+    and count thresholds are lowered (0.4 and 2 bonds, width 0.5) so that the
+    disordered atoms sit on the slopes of both logistics (s ~ 1,700 of 3,900)."""
+    d = W.cluster_in_gas()
+    pos, box = d["pos"], d["box"]
+    n = len(pos)
+    wl = dict(Q6CV, precision=precision, bond_d0=0.4, count_n0=2.0, count_w=0.5)
+    pipe = make_pipe(wl, n, max_neighbors=96)
+    p4 = to_dev(W.as_float4(pos))
+    pipe.build_neighbors_checked(p4, box)
+    off, nb = orc.neighbors(pos, box, 4.0)
+    assert np.diff(off).max() > 96
+    rows = gpu_neighbor_sets(pipe)
+    for i in range(n):
+        assert np.array_equal(rows[i], nb[off[i]:off[i + 1]]), i
+    F_in = W.external_forces(n, seed=12)
+    dv = [0.53]
+    s, F = run_step(pipe, pos, None, box, F_in, dv)
+    s_ref, g_ref, _ = oracle_cvs(orc, pos, box, wl, nl=(off, nb))
+    assert abs(s[0] - s_ref[0]) <= tol_s * abs(s_ref[0])
+    assert rel_force_err(F[:, :3] - F_in[:, :3].astype(np.float64), -dv[0] * g_ref[0]) <= tol_f
+
+
 def test_q6_forces_wrapped_pairs_long_box(orc):
     """Pairs across the periodic faces of a 204 A box: the minimum-image
     difference must not round at the magnitude of the box length (FP32 ulp at

@@ -385,3 +385,34 @@ def biased_trace(T=200000, dims=2, seed=45, periodic=True):
     for k in range(64):
         V += h[k] * np.exp(-np.sum((s - c[k]) ** 2, axis=1) / (2 * 0.5 ** 2))
     return s.reshape(T, dims) if dims > 1 else s[:, 0], V
+
+
+def cluster_in_gas(n_cluster=900, n_gas=3000, box=(40.0, 40.0, 40.0), edge=12.0, corner=(13.3, 9.7, 21.1),
+                   dmin=1.1, seed=47):
+    """A dense cluster in a gas: n_cluster atoms in a cube of the given edge
+    (about 0.5 atoms/A^3) and n_gas atoms over the whole box, no two closer
+    than dmin through the periodic faces (random sequential addition).  Bricks
+    sized for the mean density then see halos far larger than expected near
+    the cluster.  Returns positions (float32) and the box."""
+    spec = dict(n_cluster=n_cluster, n_gas=n_gas, box=list(box), edge=edge, corner=list(corner), dmin=dmin,
+                seed=seed)
+
+    def make():
+        rng = np.random.default_rng(seed)
+        L = np.asarray(box, np.float64)
+        placed = np.zeros((n_cluster + n_gas, 3))
+        count = 0
+        for n, lo, span in ((n_cluster, np.asarray(corner, np.float64), np.full(3, edge)),
+                            (n_gas, np.zeros(3), L)):
+            got = 0
+            while got < n:
+                x = lo + rng.random(3) * span
+                d = placed[:count] - x
+                d -= L * np.rint(d / L)
+                if count == 0 or np.min(np.einsum("ij,ij->i", d, d)) >= dmin * dmin:
+                    placed[count] = x
+                    count += 1
+                    got += 1
+        return dict(pos=_wrap_f32(placed, L), box=L)
+
+    return _cached("cluster_in_gas", spec, make)
