@@ -40,7 +40,8 @@ struct gm_ctx {
   int32_t *halo_rank = nullptr, *owned_slot = nullptr, *owned_rank = nullptr, *owned_hcell = nullptr;
   // neighbour rows and the per-step in-cutoff rows (16-bit halo slots)
   uint16_t *nbr = nullptr, *cut = nullptr;
-  int32_t *cnt = nullptr, *ccnt = nullptr, *order = nullptr, *err = nullptr, *stats = nullptr;
+  int32_t *cnt = nullptr, *ccnt = nullptr, *err = nullptr, *stats = nullptr;
+  int4* order = nullptr;  // per brick, by rank: (atom, halo slot, sorted position, 0)
   void *pos_s = nullptr, *qrow = nullptr, *grow = nullptr, *frad = nullptr, *nb = nullptr, *cn_atom = nullptr;
   double *part_a = nullptr, *part_b = nullptr, *s_int = nullptr, *V_int = nullptr, *dV_int = nullptr;
   double *centres = nullptr, *heights = nullptr, *bias_part = nullptr;
@@ -550,7 +551,7 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   if (rc == GM_OK) rc = dalloc(c->stream, &c->owned_hcell, n * 4);
   if (rc == GM_OK) rc = dalloc(c->stream, &c->cnt, n * 4);
   if (rc == GM_OK) rc = dalloc(c->stream, &c->ccnt, n * 4 * 4);  // up to 4 parts per atom
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->order, n * 4);
+  if (rc == GM_OK) rc = dalloc(c->stream, &c->order, n * 16);
   if (rc == GM_OK) rc = dalloc(c->stream, &c->nbr, n * (size_t)(c->kmax + 32) * 2);  // tpa sub-rows of kpart entries
   if (rc == GM_OK) rc = dalloc(c->stream, &c->cut, n * (size_t)(c->kmax + 32) * 2);
   if (rc == GM_OK) rc = dalloc(c->stream, &c->pos_s, n * 4 * T);

@@ -102,11 +102,11 @@ __device__ __forceinline__ void fetch_rec(const CvArgs<T>& a, const Brick& k, co
   }
 }
 
+// The force (or gradient) row of atom id, whose current value v was read
+// earlier by the same thread.
 template <typename T>
-__device__ __forceinline__ void write_out(const CvArgs<T>& a, int32_t rank, T gx, T gy, T gz) {
-  const int32_t id = a.perm[rank];
+__device__ __forceinline__ void write_out_at(const CvArgs<T>& a, int32_t id, vec4_t<T> v, T gx, T gy, T gz) {
   vec4_t<T>* out = reinterpret_cast<vec4_t<T>*>(a.out4) + id;
-  vec4_t<T> v = *out;
   if (a.mode == 0) {
     v.x -= gx;
     v.y -= gy;
@@ -118,6 +118,12 @@ __device__ __forceinline__ void write_out(const CvArgs<T>& a, int32_t rank, T gx
   }
   *out = v;
   if (!(isfinite(v.x) && isfinite(v.y) && isfinite(v.z))) atomicOr(a.err, kErrNonFinite);
+}
+
+template <typename T>
+__device__ __forceinline__ void write_out(const CvArgs<T>& a, int32_t rank, T gx, T gy, T gz) {
+  const int32_t id = a.perm[rank];
+  write_out_at(a, id, reinterpret_cast<const vec4_t<T>*>(a.out4)[id], gx, gy, gz);
 }
 
 // Fixed-order sum of the per-workgroup partials, in one workgroup (its own
@@ -174,10 +180,10 @@ __device__ __forceinline__ T group_sum(T v, int TPA) {
 // come from a register stream over the part's sub-row.
 template <bool ALL, typename T, class Body>
 __device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr, const T* rows,
-                                             const uint16_t* crow, int32_t n, Body body) {
+                                             const uint16_t* crow, int32_t n, uint4 first, Body body) {
   if (n <= 0) return;
   SlotStream st;
-  st.init(crow, n);
+  st.init_first(crow, n, first);
   vec4_t<T> pa, pb;
   T va[16], vb[16];
   fetch_rec<ALL>(a, k, lr, rows, st.pop(), pa, va);
@@ -201,11 +207,59 @@ __device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k,
   const int32_t part = threadIdx.x & (TPA - 1);                    \
   for (int32_t o = threadIdx.x / TPA; o < (k).O; o += blockDim.x / TPA)
 
-#define GM_FOR_RANKED(a, k)                                                 \
-  const int TPA = (a).bg.tpa;                                               \
-  const int32_t part = threadIdx.x & (TPA - 1);                             \
-  for (int32_t r_ = threadIdx.x / TPA; r_ < (k).O; r_ += blockDim.x / TPA) \
-    if (const int32_t o = (a).order[(k).ob + r_]; true)
+// The head of an owned atom in the ranked passes: its record from pass 1
+// (atom, halo slot, sorted position), its in-cutoff count and the first 16
+// bytes of its cut sub-row.  A thread's first head is loaded around the halo
+// staging (record before, the rest after) so that these dependent loads wait
+// alongside the staging instead of after it; later heads (bricks with more
+// atoms than threads) are loaded in place.
+struct AtomHead {
+  int32_t o, si, ri, nc;
+  uint4 c0;
+};
+
+template <typename T>
+__device__ __forceinline__ void head_record(const CvArgs<T>& a, const Brick& k, int32_t r, AtomHead& h) {
+  const int4 rec = a.order[k.ob + r];
+  h.o = rec.x;
+  h.si = rec.y;
+  h.ri = rec.z;
+}
+
+template <typename T>
+__device__ __forceinline__ void head_rows(const CvArgs<T>& a, const Brick& k, int32_t part, AtomHead& h) {
+  h.nc = a.ccnt[(int64_t)(k.ob + h.o) * a.bg.tpa + part];
+  h.c0 = *reinterpret_cast<const uint4*>(a.cut + subrow(a.bg, k.ob, h.o, part));  // allocated even when nc = 0
+}
+
+// Threads past the brick's atoms load the last atom's head (valid memory,
+// never used), so that the loads need no branch.
+template <typename T>
+__device__ __forceinline__ AtomHead head_begin(const CvArgs<T>& a, const Brick& k) {
+  AtomHead h;
+  h.o = 0;
+  h.si = h.ri = h.nc = 0;
+  h.c0 = make_uint4(0, 0, 0, 0);
+  if (k.O > 0) {
+    const int32_t r = (int32_t)(threadIdx.x / a.bg.tpa);
+    head_record(a, k, r < k.O ? r : k.O - 1, h);
+  }
+  return h;
+}
+
+template <typename T>
+__device__ __forceinline__ void head_end(const CvArgs<T>& a, const Brick& k, AtomHead& h) {
+  if (k.O > 0) head_rows(a, k, (int32_t)(threadIdx.x & (a.bg.tpa - 1)), h);
+}
+
+// h starts as the thread's first head; later atoms overwrite it in place.
+#define GM_FOR_RANKED(a, k, h0)                                                                \
+  const int TPA = (a).bg.tpa;                                                                  \
+  const int32_t part = threadIdx.x & (TPA - 1);                                                \
+  AtomHead h = (h0);                                                                           \
+  for (int32_t r_ = threadIdx.x / TPA; r_ < (k).O; r_ += blockDim.x / TPA)                    \
+    if ((r_ == (int32_t)(threadIdx.x / TPA) ? (void)0 : (head_record(a, k, r_, h), head_rows(a, k, part, h))), true) \
+      if (const int32_t o = h.o, si = h.si, ri = h.ri, nc = h.nc; true)
 
 // Stable counting sort of the owned atoms by key, descending (equal keys keep
 // cell order), written as order[rank] = atom.  Thread t ranks atom t: per-wave
@@ -217,11 +271,13 @@ __device__ __forceinline__ void rank_owned(const CvArgs<T>& a, const Brick& k, i
   constexpr int B = BrickBlock<T>::value, NW = B / 64;
   int32_t* hist = keys + B;               // [NW][kRankBins]: counts, then offsets
   int32_t* start = hist + NW * kRankBins;  // [kRankBins]
+  const int32_t* sr = start + kRankBins;   // [B][2]: halo slot, sorted position
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   for (int i = t; i < NW * kRankBins; i += B) hist[i] = 0;
   __syncthreads();
   if (k.O > B) {
-    for (int32_t o = t; o < k.O; o += B) a.order[k.ob + o] = o;
+    for (int32_t o = t; o < k.O; o += B)
+      a.order[k.ob + o] = make_int4(o, a.bi.owned_slot[k.ob + o], a.bi.owned_rank[k.ob + o], 0);
     return;
   }
   const bool act = t < k.O;
@@ -254,7 +310,8 @@ __device__ __forceinline__ void rank_owned(const CvArgs<T>& a, const Brick& k, i
     same &= bit ? m : ~m;
   }
   const int below = __popcll(same & ((1ull << lane) - 1ull));
-  if (act) a.order[k.ob + start[key] + hist[w * kRankBins + key] + below] = t;
+  if (act)
+    a.order[k.ob + start[key] + hist[w * kRankBins + key] + below] = make_int4(t, sr[2 * t], sr[2 * t + 1], 0);
 }
 
 // --------------------------------------------------------------------------
@@ -289,7 +346,12 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
     int32_t longest = nc;
     if (TPA >= 2) longest = max(longest, __shfl_xor(longest, 1, 64));
     if (TPA >= 4) longest = max(longest, __shfl_xor(longest, 2, 64));
-    if (part == 0 && o < BrickBlock<T>::value) keys[o] = longest;
+    if (part == 0 && o < BrickBlock<T>::value) {
+      keys[o] = longest;
+      int32_t* sr = keys + BrickBlock<T>::value * (1 + kRankBins / 64) + kRankBins;
+      sr[2 * o] = si;
+      sr[2 * o + 1] = ri;
+    }
     // Phase 2: the weighted harmonics over the in-cutoff slots only (the
     // thread reads back its own sub-row).
     T Q[13];
@@ -369,17 +431,15 @@ __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, in
 // Pass 2
 // --------------------------------------------------------------------------
 template <typename T, bool ALL, bool WRAP>
-__device__ __forceinline__ double pass2_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr) {
+__device__ __forceinline__ double pass2_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr,
+                                              const AtomHead& h0) {
   double c_part = 0.0;
-  GM_FOR_RANKED(a, k) {
-    const int32_t si = a.bi.owned_slot[k.ob + o];
-    const int32_t ri = a.bi.owned_rank[k.ob + o];
+  GM_FOR_RANKED(a, k, h0) {
     vec4_t<T> pi;
     T qi[16];
     fetch_rec<ALL>(a, k, lr, a.qrow, si, pi, qi);
-    const int32_t nc = a.ccnt[(int64_t)(k.ob + o) * TPA + part];
     T nbond = T(0);
-    walk_records<ALL>(a, k, lr, a.qrow, a.cut + subrow(a.bg, k.ob, o, part), nc, [&](const vec4_t<T>& pj, const T* qj) {
+    walk_records<ALL>(a, k, lr, a.qrow, a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0, [&](const vec4_t<T>& pj, const T* qj) {
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T r = g_sqrt(r2);
@@ -408,10 +468,12 @@ __device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, in
   vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
   __shared__ double red[BrickBlock<T>::value / 64];
   const Brick k = brick_begin(a, brick);
+  AtomHead h0 = head_begin(a, k);
   stage_rows(a, k, a.qrow, lr);
+  head_end(a, k, h0);
   __syncthreads();
   const double c_part = brick_variant(a, k, [&](auto all, auto wrap) {
-    return pass2_atoms<T, decltype(all)::value, decltype(wrap)::value>(a, k, lr);
+    return pass2_atoms<T, decltype(all)::value, decltype(wrap)::value>(a, k, lr, h0);
   });
   const double b = block_sum(c_part, red);
   if (threadIdx.x == 0) a.part_a[blk] = b;
@@ -421,20 +483,18 @@ __device__ __forceinline__ void pass2_body(const CvArgs<T>& a, int64_t brick, in
 // Pass 3
 // --------------------------------------------------------------------------
 template <typename T, bool ALL, bool WRAP>
-__device__ __forceinline__ void pass3_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr) {
-  GM_FOR_RANKED(a, k) {
-    const int32_t si = a.bi.owned_slot[k.ob + o];
-    const int32_t ri = a.bi.owned_rank[k.ob + o];
+__device__ __forceinline__ void pass3_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr,
+                                            const AtomHead& h0) {
+  GM_FOR_RANKED(a, k, h0) {
     vec4_t<T> pi;
     T qi[16];
     fetch_rec<ALL>(a, k, lr, a.qrow, si, pi, qi);
     const T dci = qi[14];
-    const int32_t nc = a.ccnt[(int64_t)(k.ob + o) * TPA + part];
-    T h[13];
+    T hs[13];
 #pragma unroll
-    for (int m = 0; m < 13; m++) h[m] = T(0);
+    for (int m = 0; m < 13; m++) hs[m] = T(0);
     T rx = T(0), ry = T(0), rz = T(0);
-    walk_records<ALL>(a, k, lr, a.qrow, a.cut + subrow(a.bg, k.ob, o, part), nc, [&](const vec4_t<T>& pj, const T* qj) {
+    walk_records<ALL>(a, k, lr, a.qrow, a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0, [&](const vec4_t<T>& pj, const T* qj) {
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
@@ -448,7 +508,7 @@ __device__ __forceinline__ void pass3_atoms(const CvArgs<T>& a, const Brick& k, 
       const T cs = dci + qj[14];
       const T coef = f * b * (T(1) - b) * a.inv_bond_w * cs;
 #pragma unroll
-      for (int m = 0; m < 13; m++) h[m] += coef * qj[m];
+      for (int m = 0; m < 13; m++) hs[m] += coef * qj[m];
       if (df != T(0)) {
         const T rad = cs * b * df * rinv;
         rx += rad * dx;
@@ -457,18 +517,18 @@ __device__ __forceinline__ void pass3_atoms(const CvArgs<T>& a, const Brick& k, 
       }
     });
 #pragma unroll
-    for (int m = 0; m < 13; m++) h[m] = group_sum(h[m], TPA);
+    for (int m = 0; m < 13; m++) hs[m] = group_sum(hs[m], TPA);
     rx = group_sum(rx, TPA);
     ry = group_sum(ry, TPA);
     rz = group_sum(rz, TPA);
     if (part == 0) {
       T proj = T(0);
 #pragma unroll
-      for (int m = 0; m < 13; m++) proj += qi[m] * h[m];
+      for (int m = 0; m < 13; m++) proj += qi[m] * hs[m];
       const T inv = qi[13] >= T(1e-12) ? T(1) / qi[13] : T(0);
       T g[16];
 #pragma unroll
-      for (int m = 0; m < 13; m++) g[m] = (h[m] - proj * qi[m]) * inv;
+      for (int m = 0; m < 13; m++) g[m] = (hs[m] - proj * qi[m]) * inv;
       g[13] = dci;
       g[14] = T(0);
       g[15] = T(0);
@@ -488,10 +548,12 @@ __device__ __forceinline__ void pass3_body(const CvArgs<T>& a, int64_t brick, in
   extern __shared__ __align__(16) unsigned char smem[];
   vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
   const Brick k = brick_begin(a, brick);
+  AtomHead h0 = head_begin(a, k);
   stage_rows(a, k, a.qrow, lr);
+  head_end(a, k, h0);
   __syncthreads();
   brick_variant(a, k, [&](auto all, auto wrap) {
-    pass3_atoms<T, decltype(all)::value, decltype(wrap)::value>(a, k, lr);
+    pass3_atoms<T, decltype(all)::value, decltype(wrap)::value>(a, k, lr, h0);
   });
 }
 
@@ -500,19 +562,17 @@ __device__ __forceinline__ void pass3_body(const CvArgs<T>& a, int64_t brick, in
 // both ends of a pair reuse one Jacobian with g_i + g_j).
 // --------------------------------------------------------------------------
 template <typename T, bool CN, bool ALL, bool WRAP>
-__device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr) {
+__device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr,
+                                            const AtomHead& h0) {
   const T seed_q = a.seed ? (T)a.seed[a.dims - 1] : T(1);
   const T seed_cn = (CN && a.seed) ? (T)(a.seed[0] * 2.0 * a.inv_n) : T(0);
-  GM_FOR_RANKED(a, k) {
-    const int32_t si = a.bi.owned_slot[k.ob + o];
-    const int32_t ri = a.bi.owned_rank[k.ob + o];
+  GM_FOR_RANKED(a, k, h0) {
     vec4_t<T> pi;
     T gi[16];
     fetch_rec<ALL>(a, k, lr, a.grow, si, pi, gi);
-    const int32_t nc = a.ccnt[(int64_t)(k.ob + o) * TPA + part];
     T ax = T(0), ay = T(0), az = T(0);
     T cx = T(0), cy = T(0), cz = T(0);
-    walk_records<ALL>(a, k, lr, a.grow, a.cut + subrow(a.bg, k.ob, o, part), nc, [&](const vec4_t<T>& pj, const T* gj) {
+    walk_records<ALL>(a, k, lr, a.grow, a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0, [&](const vec4_t<T>& pj, const T* gj) {
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
@@ -572,10 +632,12 @@ __device__ __forceinline__ void pass4_body(const CvArgs<T>& a, int64_t brick, in
   extern __shared__ __align__(16) unsigned char smem[];
   vec4_t<T>* lr = reinterpret_cast<vec4_t<T>*>(smem);
   const Brick k = brick_begin(a, brick);
+  AtomHead h0 = head_begin(a, k);
   stage_rows(a, k, a.grow, lr);
+  head_end(a, k, h0);
   __syncthreads();
   brick_variant(a, k, [&](auto all, auto wrap) {
-    pass4_atoms<T, CN, decltype(all)::value, decltype(wrap)::value>(a, k, lr);
+    pass4_atoms<T, CN, decltype(all)::value, decltype(wrap)::value>(a, k, lr, h0);
   });
 }
 
@@ -583,15 +645,13 @@ __device__ __forceinline__ void pass4_body(const CvArgs<T>& a, int64_t brick, in
 // Coordination number alone: forces over the in-cutoff slots of pass 1.
 // --------------------------------------------------------------------------
 template <typename T, bool ALL, bool WRAP>
-__device__ __forceinline__ void cn_force_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lp) {
+__device__ __forceinline__ void cn_force_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lp,
+                                               const AtomHead& h0) {
   const T seed = (T)((a.seed ? a.seed[0] : 1.0) * 2.0 * a.inv_n);
-  GM_FOR_RANKED(a, k) {
-    const int32_t si = a.bi.owned_slot[k.ob + o];
-    const int32_t ri = a.bi.owned_rank[k.ob + o];
+  GM_FOR_RANKED(a, k, h0) {
     const vec4_t<T> pi = fetch_pos<ALL>(a, k, lp, si);
-    const int32_t nc = a.ccnt[(int64_t)(k.ob + o) * TPA + part];
     SlotStream st;
-    st.init(a.cut + subrow(a.bg, k.ob, o, part), nc);
+    st.init_first(a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0);
     T cx = T(0), cy = T(0), cz = T(0);
     for (int32_t j = 0; j < nc; j++) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, st.pop());
@@ -619,10 +679,12 @@ __device__ __forceinline__ void cn_force_body(const CvArgs<T>& a, int64_t brick,
   extern __shared__ __align__(16) unsigned char smem[];
   vec4_t<T>* lp = reinterpret_cast<vec4_t<T>*>(smem);
   const Brick k = brick_begin(a, brick);
+  AtomHead h0 = head_begin(a, k);
   stage_pos(a, k, lp);
+  head_end(a, k, h0);
   __syncthreads();
   brick_variant(a, k, [&](auto all, auto wrap) {
-    cn_force_atoms<T, decltype(all)::value, decltype(wrap)::value>(a, k, lp);
+    cn_force_atoms<T, decltype(all)::value, decltype(wrap)::value>(a, k, lp, h0);
   });
 }
 
@@ -649,12 +711,16 @@ __device__ __forceinline__ int64_t xcd_remap() {
   return (b % kXcd) * per + b / kXcd;
 }
 
+// Two brick workgroups share a CU (their staged halos fill its LDS): keep the
+// register use of the FP32 passes within what 4 waves per SIMD allow.
+#define GM_PASS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+
 #define GM_PASS_KERNELS(NAME, BODY, TMPL, TARGS)                                                      \
-  TMPL __global__ __launch_bounds__(BrickBlock<T>::value) void NAME(CvArgs<T> a) {                    \
+  TMPL __global__ __launch_bounds__(BrickBlock<T>::value) GM_PASS_OCCUPANCY void NAME(CvArgs<T> a) { \
     const int64_t g = logical_brick(a.bg);                                                            \
     BODY TARGS(a, g, (int32_t)g, (int32_t)gridDim.x);                                                 \
   }                                                                                                   \
-  TMPL __global__ __launch_bounds__(BrickBlock<T>::value) void NAME##_batch(                           \
+  TMPL __global__ __launch_bounds__(BrickBlock<T>::value) GM_PASS_OCCUPANCY void NAME##_batch(         \
       const CvArgs<T>* __restrict__ tab,                                                              \
                                                               const int32_t* __restrict__ blk_start,  \
                                                               int32_t W) {                            \

@@ -332,6 +332,15 @@ struct SlotStream {
     if (n > 0) cur = src[0];
   }
 
+  // The same, with the row's first 16 bytes already loaded.
+  __device__ __forceinline__ void init_first(const uint16_t* row, int32_t count, uint4 first) {
+    src = reinterpret_cast<const uint4*>(row);
+    n = count;
+    j = 0;
+    cur = first;
+    nxt = first;
+  }
+
   __device__ __forceinline__ int32_t pop() {
     const int32_t s = (int32_t)(cur.x & 0xffffu);
     cur.x = __builtin_amdgcn_alignbit(cur.y, cur.x, 16);

@@ -47,11 +47,12 @@ struct BrickBlock {
 
 // Pass 1 ranks the owned atoms of a brick by their longest in-cutoff part
 // (keys clamped to kRankBins buckets); its LDS scratch after the staged
-// positions: one key per thread, a histogram per wave, the bucket starts.
+// positions: one key per thread, a histogram per wave, the bucket starts,
+// then each atom's halo slot and sorted position (for the ranked records).
 constexpr int kRankBins = 128;
 template <typename T>
 constexpr int rank_lds_bytes() {
-  return (BrickBlock<T>::value * (1 + kRankBins / 64) + kRankBins) * 4;
+  return (BrickBlock<T>::value * (3 + kRankBins / 64) + kRankBins) * 4;
 }
 
 // Coefficients of E_m(z) = A_m d^m P_6/dz^m (z), the z part of the real l = 6
@@ -114,7 +115,8 @@ struct CvArgs {
   const int32_t* cnt;      // [N] row lengths, brick order
   uint16_t* cut;           // in-cutoff slots of the current step, same layout as nbr
   int32_t* ccnt;           // [N][tpa] in-cutoff counts per part, brick order
-  int32_t* order;          // [N] per brick: owned atoms ranked by longest in-cutoff part (pass 1)
+  int4* order;             // [N] per brick, by rank: (atom, halo slot, sorted position, 0) of the owned atoms
+                           // ranked by longest in-cutoff part (pass 1)
   const int32_t* perm;     // sorted position -> caller's atom id
   BrickGeom bg;
   BrickIndex bi;
