@@ -123,7 +123,8 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
 
 /* Free everything the context owns, in stream order on the context's stream
  * (no wait): work already enqueued there may still use the buffers, and work
- * on other streams that uses them must be ordered before this call. */
+ * on other streams that uses them must be ordered before this call.  The
+ * stream must still exist. */
 int gm_destroy(gm_ctx* ctx);
 
 /* Re-bind the context to another stream (e.g. a capture stream).  The caller
@@ -182,15 +183,17 @@ int gm_apply_bias_forces(gm_ctx* ctx, const float* pos4, const double* dVds_dev,
  * and deposits nothing. */
 int gm_deposit_hill(gm_ctx* ctx, const double* s_dev);
 
-/* Checkpoint the hill history (synchronous: waits for the context's stream).  centres: host double[cap*dims],
- * heights: host double[cap]; *k receives the hill count.  Either array may be
- * NULL to query the count only.  GM_ERR_INVALID_ARG if cap < count. */
+/* Checkpoint the hill history (synchronous: waits for the context's stream).
+ * centres: host double[cap*dims], heights: host double[cap]; *k receives the
+ * hill count.  Either array may be NULL to query the count only.
+ * GM_ERR_INVALID_ARG if cap < count. */
 int gm_hills_get(gm_ctx* ctx, double* centres, double* heights, int64_t cap, int64_t* k);
 
 /* Restore a hill history (synchronous: enqueued, then waits for the context's
- * stream so that the host arrays may be reused on return).  centres: host double[k*dims],
- * heights: host double[k], 0 <= k <= hill_capacity.  Bias sums run in hill
- * index order, so a restored history reproduces V bit for bit. */
+ * stream so that the host arrays may be reused on return).
+ * centres: host double[k*dims], heights: host double[k],
+ * 0 <= k <= hill_capacity.  Bias sums run in hill index order, so a restored
+ * history reproduces V bit for bit. */
 int gm_hills_set(gm_ctx* ctx, const double* centres, const double* heights, int64_t k);
 
 /* Read and clear the sticky device error word.  sync != 0 waits for the
