@@ -86,3 +86,70 @@ def test_window_graph_replays_match_eager(precision):
         for name, x, y in zip(("s", "V", "F", "centres", "heights"), a, b):
             assert np.array_equal(x, y), (k, name)
     assert len(got[-1][4]) == 40 + replays + 1
+
+
+def test_batch_graph_replays_match_eager():
+    """A batch of uneven walkers (all three CV kinds): one step for all of them
+    and a deposit, captured once and replayed; every walker's CV, bias,
+    forces and hills after each replay equal the eager batch's bitwise."""
+    from paper_2510_06873_amd import Batch, Pipeline
+
+    dev = torch.device("cuda", 0)
+    kinds = [dict(Q6_2D, cv="q6", sigma=[20.0]), dict(Q6_2D, cv="coord", sigma=[0.2]), dict(Q6_2D)]
+    structs = [W.wurtzite_slab(nx=4, ny=3, nz=6, seed=21), W.wurtzite_slab(nx=8, ny=4, nz=8, seed=5),
+               W.wurtzite_slab(nx=6, ny=4, nz=4, seed=9)]
+
+    def make(stream):
+        pipes, pos, forces, boxes = [], [], [], []
+        with torch.cuda.stream(stream):
+            for k, (wl, d) in enumerate(zip(kinds, structs)):
+                n = len(d["pos"])
+                pipe = Pipeline(n, params_for(wl, max_neighbors=96), stream=stream)
+                p4 = torch.from_numpy(W.as_float4(d["pos"], d["species"])).to(dev)
+                pipe.build_neighbors_checked(p4, d["box"])
+                s0 = pipe.cv_forward(p4).cpu().numpy()
+                sig = np.array(wl["sigma"])
+                pipe.hills_set(W.hill_centres(20, s0 - 2 * sig, s0 + 2 * sig, seed=30 + k), np.full(20, wl["w0"]))
+                pipes.append(pipe)
+                pos.append(p4)
+                forces.append(torch.from_numpy(W.external_forces(n, seed=40 + k)).to(dev))
+                boxes.append(d["box"])
+            batch = Batch(pipes, pos, forces, stream=stream)
+            batch.build(boxes)
+        return batch, pipes, forces
+
+    def iteration(batch):
+        batch.step()
+        batch.deposit()
+
+    def snapshot(batch, pipes, forces):
+        s, V = batch.values()
+        batch.stream.synchronize()
+        return [(s[k].cpu().numpy().copy(), V[k].item(), forces[k].cpu().numpy().copy(), *p.hills_get())
+                for k, p in enumerate(pipes)]
+
+    replays = 3
+    se = torch.cuda.Stream(device=dev)
+    be, pe, fe = make(se)
+    eager = []
+    with torch.cuda.stream(se):
+        for _ in range(replays + 1):
+            iteration(be)
+            eager.append(snapshot(be, pe, fe))
+    sg = torch.cuda.Stream(device=dev)
+    bg, pg, fg = make(sg)
+    with torch.cuda.stream(sg):
+        iteration(bg)
+        got = [snapshot(bg, pg, fg)]
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=sg):
+            iteration(bg)
+        for _ in range(replays):
+            graph.replay()
+            got.append(snapshot(bg, pg, fg))
+    for p in pe + pg:
+        assert p.status(True) == 0
+    for r, (a, b) in enumerate(zip(eager, got)):
+        for k in range(len(kinds)):
+            for name, x, y in zip(("s", "V", "F", "centres", "heights"), a[k], b[k]):
+                assert np.array_equal(x, y), (r, k, name)
