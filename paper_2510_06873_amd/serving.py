@@ -142,7 +142,12 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
     """Run the requests with continuous batching; returns (results, stats).
 
     stage_ahead: most walkers prepared ahead of a free slot (default max_slots;
-    0 admits only into free slots)."""
+    0 admits only into free slots).  A request that would not fit the budget
+    even alone is rejected before anything runs (it could never be admitted)."""
+    for r in requests:
+        if device_bytes(r) > hbm_budget:
+            raise ValueError(f"request {r.rid} needs {device_bytes(r)} bytes of device memory, "
+                             f"more than the whole budget of {hbm_budget}")
     import torch
 
     dev = device or torch.device("cuda", 0)

@@ -37,3 +37,4 @@ def test_seeded_and_float32():
 def test_hill_centres_range():
     c = W.hill_centres(1000, [0.0], [14.0], seed=11)
     assert c.shape == (1000, 1) and c.min() >= 0 and c.max() < 14
+
