@@ -6,10 +6,9 @@ import pytest
 def test_serving_rejects_a_request_larger_than_the_budget():
     """A walker that alone exceeds the HBM budget could never be admitted: the
     server refuses the request set up front instead of waiting for it."""
-    from paper_2510_06873_amd.serving import Request, device_bytes, serve_batched
-
     try:
         from paper_2510_06873_amd import Params
+        from paper_2510_06873_amd.serving import Request, device_bytes, serve_batched
     except ImportError:
         pytest.skip("library not built")
     pos = np.zeros((1000, 4), np.float32)
