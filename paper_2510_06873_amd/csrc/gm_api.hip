@@ -67,6 +67,9 @@ constexpr int kMaxDevices = 64;
 std::mutex g_pool_mu;
 hipMemPool_t g_pool[kMaxDevices] = {};
 
+std::mutex g_lds_mu;
+int g_lds_max = 0;  // largest LDS staging budget of any context so far (bytes)
+
 hipMemPool_t device_pool() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
@@ -537,8 +540,14 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
     int want = params->lds_kb > 0 ? params->lds_kb * 1024 : 80 * 1024;
     if (want > lim) want = lim;
     c->lds_budget = want - 2048;
-    allow_cv_lds(c->lds_budget);
-    allow_build_lds(c->lds_budget);
+    // The kernels' LDS limit is an attribute of the function, shared by every
+    // context: keep it at the largest budget any context asked for, so that a
+    // context created later with a smaller one does not fail the launches of
+    // an earlier one.
+    std::lock_guard<std::mutex> lock(g_lds_mu);
+    if (c->lds_budget > g_lds_max) g_lds_max = c->lds_budget;
+    allow_cv_lds(g_lds_max);
+    allow_build_lds(g_lds_max);
   }
 
   const size_t n = c->external ? 1 : (size_t)n_atoms, T = c->fp64 ? 8 : 4;  // no atom buffers for external CVs

@@ -126,3 +126,30 @@ def test_context_churn_on_another_stream():
         cA, hA = pA.hills_get()
         assert np.array_equal(cA, c) and np.array_equal(hA, h)
         pA.close()
+
+
+def test_context_with_a_smaller_lds_budget_created_later():
+    """The kernels' LDS limit is shared by all contexts: a context created
+    later with a smaller staging budget (as the autotuner makes) must leave an
+    earlier context's launches working and its results unchanged."""
+    from paper_2510_06873_amd import Pipeline
+
+    dev = torch.device("cuda", 0)
+    wl, d = walkers()[3]
+    ref, F_ref = _run_solo(wl, d, dev, 3, 2)
+    torch.cuda.synchronize()
+    s_ref, F_ref = ref.s.cpu().numpy().copy(), F_ref.cpu().numpy().copy()
+    ref.close()
+    pipe, p4, F = setup(wl, d, dev, 3)  # default budget (78 KiB)
+    prm = params_for(wl, max_neighbors=96)
+    prm.lds_kb = 40
+    later = Pipeline(len(d["pos"]), prm)
+    for step in range(2):
+        if step == 1:
+            pipe.deposit_hill()
+        pipe.step(p4, F)
+    torch.cuda.synchronize()
+    assert pipe.status(True) == 0
+    assert np.array_equal(pipe.s.cpu().numpy(), s_ref)
+    assert np.array_equal(F.cpu().numpy(), F_ref)
+    later.close()
