@@ -153,17 +153,26 @@ constexpr int kScanSmall = 16 * kScanTile;
 
 __device__ __forceinline__ void scan_small_one(const int32_t* __restrict__ in, int64_t n, int32_t* __restrict__ out,
                                                int32_t* __restrict__ zero, int32_t* lds) {
-  const int64_t chunk = (n + kScanTile - 1) / kScanTile;
+  const int64_t chunk = (n + kScanTile - 1) / kScanTile;  // <= kScanSmall / kScanTile
   const int64_t lo = threadIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  // the chunk goes to registers in one batch of independent loads (a loop
+  // of loads and sums waits for each load in turn)
+  constexpr int kMaxChunk = kScanSmall / kScanTile;
+  int32_t v[kMaxChunk];
+#pragma unroll
+  for (int j = 0; j < kMaxChunk; j++) v[j] = lo + j < hi ? in[lo + j] : 0;
   int32_t sum = 0;
-  for (int64_t i = lo; i < hi; i++) sum += in[i];
+#pragma unroll
+  for (int j = 0; j < kMaxChunk; j++) sum += v[j];
   const int32_t incl = block_scan_incl(sum, lds);
   int32_t run = incl - sum;
-  for (int64_t i = lo; i < hi; i++) {
-    const int32_t v = in[i];
-    out[i] = run;
-    run += v;
-    if (zero) zero[i] = 0;
+#pragma unroll
+  for (int j = 0; j < kMaxChunk; j++) {
+    if (lo + j < hi) {
+      out[lo + j] = run;
+      if (zero) zero[lo + j] = 0;
+    }
+    run += v[j];
   }
   if (threadIdx.x == kScanTile - 1) out[n] = incl;
 }
