@@ -330,16 +330,14 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
     // Phase 1: distance filter over the neighbour sub-row, writing this
     // step's in-cutoff slots (cheap, so divergence costs little).
     uint16_t* crow = a.cut + subrow(a.bg, k.ob, o, part);
-    SlotStream st;
-    st.init(a.nbr + subrow(a.bg, k.ob, o, part), cp);
+    const uint16_t* nrow = a.nbr + subrow(a.bg, k.ob, o, part);
     SlotWriter wr;
     wr.init(crow);
-    for (int32_t j = 0; j < cp; j++) {
-      const int32_t s = st.pop();
+    for_slots(nrow, cp, first_chunk(nrow, cp), [&](int32_t s) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
       if (pair_vec<WRAP>(pi, pj, a, dx, dy, dz) < a.rc2) wr.push(s);
-    }
+    }, [&] { wr.commit(); });
     wr.flush();
     const int32_t nc = wr.n;
     a.ccnt[(int64_t)(k.ob + o) * TPA + part] = nc;
@@ -358,10 +356,8 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
 #pragma unroll
     for (int m = 0; m < 13; m++) Q[m] = T(0);
     T fsum = T(0), cnsum = T(0);
-    SlotStream sc;
-    sc.init(crow, nc);
-    for (int32_t j = 0; j < nc; j++) {
-      const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, sc.pop());
+    for_slots(crow, nc, first_chunk(crow, nc), [&](int32_t s) {
+      const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
@@ -377,7 +373,7 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
         const T x2 = x * x;
         cnsum += g_rcp(T(1) + x2 * x2 * x2);
       }
-    }
+    });
     if (Q6) {
 #pragma unroll
       for (int m = 0; m < 13; m++) Q[m] = group_sum(Q[m], TPA);
@@ -650,11 +646,9 @@ __device__ __forceinline__ void cn_force_atoms(const CvArgs<T>& a, const Brick& 
   const T seed = (T)((a.seed ? a.seed[0] : 1.0) * 2.0 * a.inv_n);
   GM_FOR_RANKED(a, k, h0) {
     const vec4_t<T> pi = fetch_pos<ALL>(a, k, lp, si);
-    SlotStream st;
-    st.init_first(a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0);
     T cx = T(0), cy = T(0), cz = T(0);
-    for (int32_t j = 0; j < nc; j++) {
-      const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, st.pop());
+    for_slots(a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0, [&](int32_t s) {
+      const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
@@ -666,7 +660,7 @@ __device__ __forceinline__ void cn_force_atoms(const CvArgs<T>& a, const Brick& 
       cx += swp * dx;
       cy += swp * dy;
       cz += swp * dz;
-    }
+    });
     cx = group_sum(cx, TPA);
     cy = group_sum(cy, TPA);
     cz = group_sum(cz, TPA);

@@ -354,16 +354,58 @@ struct SlotStream {
   }
 };
 
-// Appends 16-bit slots to one sub-row, 8 per 16-byte store.
+// Visits the first n slots of a sub-row in order, 8 to a block: the load of
+// the next block's 16 bytes is issued before the current block is visited,
+// so its wait falls after 8 bodies.  The prefetch index is clamped to the
+// row's last used chunk, so the load is unconditional and in bounds.  `first`
+// holds the row's first 16 bytes when the caller loaded them already.
+// `after` runs once after each block: a body that writes memory keeps its
+// stores there, since a store in the inner loop (with no load beside it)
+// makes the compiler wait for the prefetch before the loop instead.
+template <class Body, class After>
+__device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, uint4 first, Body body, After after) {
+  const uint4* src = reinterpret_cast<const uint4*>(row);
+  const int32_t last = (n - 1) >> 3;
+  uint4 cur = first;
+  for (int32_t b = 0; b < n; b += 8) {
+    const uint4 nxt = src[min((b >> 3) + 1, last)];
+    const int32_t m = min(8, n - b);
+    for (int32_t e = 0; e < m; e++) {
+      body((int32_t)(cur.x & 0xffffu));
+      cur.x = __builtin_amdgcn_alignbit(cur.y, cur.x, 16);
+      cur.y = __builtin_amdgcn_alignbit(cur.z, cur.y, 16);
+      cur.z = __builtin_amdgcn_alignbit(cur.w, cur.z, 16);
+      cur.w = cur.w >> 16;
+    }
+    after();
+    cur = nxt;
+  }
+}
+
+template <class Body>
+__device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, uint4 first, Body body) {
+  for_slots(row, n, first, body, [] {});
+}
+
+__device__ __forceinline__ uint4 first_chunk(const uint16_t* row, int32_t n) {
+  return n > 0 ? *reinterpret_cast<const uint4*>(row) : make_uint4(0, 0, 0, 0);
+}
+
+// Appends 16-bit slots to one sub-row, 8 per 16-byte store.  A filled 16
+// bytes is held until commit(), which the caller runs after every 8 pushes or
+// fewer (so at most one is pending); flush() writes the partial tail.
 struct SlotWriter {
   uint4* dst;
-  uint4 buf;
+  uint4 buf, full;
   int32_t n;
+  bool ready;
 
   __device__ __forceinline__ void init(uint16_t* row) {
     dst = reinterpret_cast<uint4*>(row);
     buf = make_uint4(0, 0, 0, 0);
+    full = buf;
     n = 0;
+    ready = false;
   }
 
   __device__ __forceinline__ void push(int32_t s) {
@@ -375,12 +417,20 @@ struct SlotWriter {
     buf.w |= w == 3 ? v : 0u;
     n++;
     if ((n & 7) == 0) {
-      dst[(n >> 3) - 1] = buf;
+      full = buf;
+      ready = true;
       buf = make_uint4(0, 0, 0, 0);
     }
   }
 
+  // The pending 16 bytes are those that ended at the last multiple of 8.
+  __device__ __forceinline__ void commit() {
+    if (ready) dst[(n >> 3) - 1] = full;
+    ready = false;
+  }
+
   __device__ __forceinline__ void flush() {
+    commit();
     if (n & 7) dst[n >> 3] = buf;
   }
 };
