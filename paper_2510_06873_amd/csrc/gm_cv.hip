@@ -167,11 +167,37 @@ __global__ __launch_bounds__(kBlock) void k_finish_batch(const CvArgs<T>* __rest
 // Threads per atom: TPA adjacent lanes share one owned atom; lane part p
 // walks the atom's rows at entries p, p + TPA, ...  (the per-step cutoff rows
 // are stored as TPA interleaved sub-lists, one per part), and the parts'
-// partial sums are combined with xor shuffles (same result in every part).
+// partial sums are combined with xor exchanges inside each quad of lanes
+// (same result in every part).  The exchanges are DPP quad permutations, a
+// register move, rather than a shuffle through the LDS crossbar; the lanes of
+// one atom are active together, so every source lane holds its partial.
+template <int CTRL>
+__device__ __forceinline__ int32_t quad_xor(int32_t v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float quad_xor(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double quad_xor(double v) {
+  const int64_t b = __double_as_longlong(v);
+  const int32_t lo = (int32_t)b, hi = (int32_t)(b >> 32);
+  const int32_t l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  const int32_t h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)h2 << 32) | (uint32_t)l2));
+}
+
+// quad_perm selectors: lane q of a quad reads lane q ^ 1, respectively q ^ 2
+constexpr int kQuadXor1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);
+constexpr int kQuadXor2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
+
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int TPA) {
-  if (TPA >= 2) v += __shfl_xor(v, 1, 64);
-  if (TPA >= 4) v += __shfl_xor(v, 2, 64);
+  if (TPA >= 2) v += quad_xor<kQuadXor1>(v);
+  if (TPA >= 4) v += quad_xor<kQuadXor2>(v);
   return v;
 }
 
@@ -342,8 +368,8 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
     const int32_t nc = wr.n;
     a.ccnt[(int64_t)(k.ob + o) * TPA + part] = nc;
     int32_t longest = nc;
-    if (TPA >= 2) longest = max(longest, __shfl_xor(longest, 1, 64));
-    if (TPA >= 4) longest = max(longest, __shfl_xor(longest, 2, 64));
+    if (TPA >= 2) longest = max(longest, quad_xor<kQuadXor1>(longest));
+    if (TPA >= 4) longest = max(longest, quad_xor<kQuadXor2>(longest));
     if (part == 0 && o < BrickBlock<T>::value) {
       keys[o] = longest;
       int32_t* sr = keys + BrickBlock<T>::value * (1 + kRankBins / 64) + kRankBins;
