@@ -406,6 +406,9 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
       pi = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
     }
     int32_t count = 0;  // the same in every lane of the group
+    // entry e goes to sub-row e % TPA at e / TPA: 32-bit offsets from the
+    // atom's first sub-row
+    uint16_t* const row0 = nbr + subrow(g, ob, k, 0);
     for (int cz = -1; cz <= 1; cz++)
       for (int cy = -1; cy <= 1; cy++) {
         const int h = hc + cz * hxy + cy * hx;  // middle cell of the x-run
@@ -414,10 +417,9 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
           const int32_t sl = base + lig;
           bool in = false;
           if (sl < se && sl != si) {
-            float4 pj;
-            if (sl < cap) {
-              pj = hpos[sl];
-            } else {
+            // staged slots (nearly all) read LDS; the rest global memory
+            float4 pj = hpos[min(sl, cap - 1)];
+            if (sl >= cap) {
               const vec4_t<T> p = pos_s[bi.halo_rank[hb + sl]];
               pj = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
             }
@@ -446,7 +448,7 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
           const uint64_t m = __ballot(in);
           if (in) {
             const int32_t e = count + __popcll(m & below);
-            if (e < kmax) nbr[subrow(g, ob, k, e & (g.tpa - 1)) + (e >> tsh)] = (uint16_t)sl;
+            if (e < kmax) row0[(e & (g.tpa - 1)) * g.kpart + (e >> tsh)] = (uint16_t)sl;
           }
           count += __popcll(m & gmask);
         }
