@@ -242,10 +242,12 @@ __device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k,
 // order (pass 1) or in the order pass 1 ranked them by their longest
 // in-cutoff part (passes 2-4), so that the lanes of a wave walk rows of
 // similar length (a wave loops as long as its longest lane).
-#define GM_FOR_OWNED(a, k)                                         \
-  const int TPA = (a).bg.tpa;                                      \
-  const int32_t part = threadIdx.x & (TPA - 1);                    \
-  for (int32_t o = threadIdx.x / TPA; o < (k).O; o += blockDim.x / TPA)
+// TPA is a power of two: atom and part come from shifts and masks.
+#define GM_FOR_OWNED(a, k)                                             \
+  const int TPA = (a).bg.tpa;                                          \
+  const int TSH = __builtin_ctz((unsigned)TPA);                        \
+  const int32_t part = threadIdx.x & (TPA - 1);                        \
+  for (int32_t o = (int32_t)(threadIdx.x >> TSH); o < (k).O; o += (int32_t)(blockDim.x >> TSH))
 
 // The head of an owned atom in the ranked passes: its record from pass 1
 // (atom, halo slot, sorted position), its in-cutoff count and the first 16
@@ -281,7 +283,7 @@ __device__ __forceinline__ AtomHead head_begin(const CvArgs<T>& a, const Brick& 
   h.si = h.ri = h.nc = 0;
   h.c0 = make_uint4(0, 0, 0, 0);
   if (k.O > 0) {
-    const int32_t r = (int32_t)(threadIdx.x / a.bg.tpa);
+    const int32_t r = (int32_t)(threadIdx.x >> __builtin_ctz((unsigned)a.bg.tpa));
     head_record(a, k, r < k.O ? r : k.O - 1, h);
   }
   return h;
@@ -295,10 +297,11 @@ __device__ __forceinline__ void head_end(const CvArgs<T>& a, const Brick& k, Ato
 // h starts as the thread's first head; later atoms overwrite it in place.
 #define GM_FOR_RANKED(a, k, h0)                                                                \
   const int TPA = (a).bg.tpa;                                                                  \
+  const int TSH = __builtin_ctz((unsigned)TPA);                                                \
   const int32_t part = threadIdx.x & (TPA - 1);                                                \
   AtomHead h = (h0);                                                                           \
-  for (int32_t r_ = threadIdx.x / TPA; r_ < (k).O; r_ += blockDim.x / TPA)                    \
-    if ((r_ == (int32_t)(threadIdx.x / TPA) ? (void)0 : (head_record(a, k, r_, h), head_rows(a, k, part, h))), true) \
+  for (int32_t r_ = (int32_t)(threadIdx.x >> TSH); r_ < (k).O; r_ += (int32_t)(blockDim.x >> TSH)) \
+    if ((r_ == (int32_t)(threadIdx.x >> TSH) ? (void)0 : (head_record(a, k, r_, h), head_rows(a, k, part, h))), true) \
       if (const int32_t o = h.o, si = h.si, ri = h.ri, nc = h.nc; true)
 
 // Stable counting sort of the owned atoms by key, descending (equal keys keep
@@ -366,18 +369,18 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
     const int32_t ri = a.bi.owned_rank[k.ob + o];
     const vec4_t<T> pi = fetch_pos<ALL>(a, k, lp, si);
     const int32_t c = min(a.cnt[k.ob + o], a.kmax);
-    const int32_t cp = c > part ? (c - part + TPA - 1) / TPA : 0;
+    const int32_t cp = c > part ? ((c - part - 1) >> TSH) + 1 : 0;
     // Phase 1: distance filter over the neighbour sub-row, writing this
     // step's in-cutoff slots (cheap, so divergence costs little).
     uint16_t* crow = a.cut + subrow(a.bg, k.ob, o, part);
     const uint16_t* nrow = a.nbr + subrow(a.bg, k.ob, o, part);
     SlotWriter wr;
     wr.init(crow);
-    for_slots(nrow, cp, first_chunk(nrow, cp), [&](int32_t s) {
+    for_slots<true>(nrow, cp, first_chunk(nrow, cp), [&](int32_t s) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
       if (pair_vec<WRAP>(pi, pj, a, dx, dy, dz) < a.rc2) wr.push(s);
-    }, [&] { wr.commit(); });
+    }, [] {});
     wr.flush();
     const int32_t nc = wr.n;
     a.ccnt[(int64_t)(k.ob + o) * TPA + part] = nc;

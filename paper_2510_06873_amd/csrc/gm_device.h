@@ -173,12 +173,12 @@ __device__ __forceinline__ void accumulate_y(const YCoef<T>& c, T ux, T uy, T uz
   T E[7];
   eval_E_roots(c, uz, E);
   Q[0] += f * E[0];
-  T R = ux, I = uy;
+  // (R, I) = f (ux + i uy)^m: the weight rides along the recurrence
+  T R = f * ux, I = f * uy;
 #pragma unroll
   for (int m = 1; m <= 6; m++) {
-    const T fE = f * E[m];
-    Q[2 * m - 1] += fE * R;
-    Q[2 * m] += fE * I;
+    Q[2 * m - 1] += E[m] * R;
+    Q[2 * m] += E[m] * I;
     if (m < 6) {
       const T R2 = R * ux - I * uy;
       const T I2 = R * uy + I * ux;
@@ -362,20 +362,34 @@ struct SlotStream {
 // `after` runs once after each block: a body that writes memory keeps its
 // stores there, since a store in the inner loop (with no load beside it)
 // makes the compiler wait for the prefetch before the loop instead.
-template <class Body, class After>
+// UNROLL = true writes the 8 bodies of a block out (each guarded by the
+// row's length), for small bodies whose state would otherwise be copied
+// around the inner loop.
+template <bool UNROLL = false, class Body, class After>
 __device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, uint4 first, Body body, After after) {
   const uint4* src = reinterpret_cast<const uint4*>(row);
   const int32_t last = (n - 1) >> 3;
   uint4 cur = first;
   for (int32_t b = 0; b < n; b += 8) {
     const uint4 nxt = src[min((b >> 3) + 1, last)];
+    // Settle the wait for this block's 16 bytes here (in the first block
+    // they are still in flight), so that no wait inside the block can also
+    // drain the prefetch behind a store the body issued.
+    asm volatile("" ::"v"(cur.x), "v"(cur.y), "v"(cur.z), "v"(cur.w));
     const int32_t m = min(8, n - b);
-    for (int32_t e = 0; e < m; e++) {
-      body((int32_t)(cur.x & 0xffffu));
-      cur.x = __builtin_amdgcn_alignbit(cur.y, cur.x, 16);
-      cur.y = __builtin_amdgcn_alignbit(cur.z, cur.y, 16);
-      cur.z = __builtin_amdgcn_alignbit(cur.w, cur.z, 16);
-      cur.w = cur.w >> 16;
+    if constexpr (UNROLL) {
+      const uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
+#pragma unroll
+      for (int e = 0; e < 8; e++)
+        if (e < m) body((int32_t)((w[e >> 1] >> ((e & 1) * 16)) & 0xffffu));
+    } else {
+      for (int32_t e = 0; e < m; e++) {
+        body((int32_t)(cur.x & 0xffffu));
+        cur.x = __builtin_amdgcn_alignbit(cur.y, cur.x, 16);
+        cur.y = __builtin_amdgcn_alignbit(cur.z, cur.y, 16);
+        cur.z = __builtin_amdgcn_alignbit(cur.w, cur.z, 16);
+        cur.w = cur.w >> 16;
+      }
     }
     after();
     cur = nxt;
@@ -384,54 +398,52 @@ __device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, uint4 
 
 template <class Body>
 __device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, uint4 first, Body body) {
-  for_slots(row, n, first, body, [] {});
+  for_slots<false>(row, n, first, body, [] {});
 }
 
 __device__ __forceinline__ uint4 first_chunk(const uint16_t* row, int32_t n) {
   return n > 0 ? *reinterpret_cast<const uint4*>(row) : make_uint4(0, 0, 0, 0);
 }
 
-// Appends 16-bit slots to one sub-row, 8 per 16-byte store.  A filled 16
-// bytes is held until commit(), which the caller runs after every 8 pushes or
-// fewer (so at most one is pending); flush() writes the partial tail.
+// Appends 16-bit slots to one sub-row, 8 per 16-byte store.  The 16 bytes
+// in registers are a shift register of the last 8 slots (the newest enters
+// at the top, so after 8 pushes they lie in row order and are stored);
+// flush() writes the partial tail, shifted down to the front with zeros
+// behind it.
 struct SlotWriter {
   uint4* dst;
-  uint4 buf, full;
+  uint4 buf;
   int32_t n;
-  bool ready;
 
   __device__ __forceinline__ void init(uint16_t* row) {
     dst = reinterpret_cast<uint4*>(row);
     buf = make_uint4(0, 0, 0, 0);
-    full = buf;
     n = 0;
-    ready = false;
   }
 
   __device__ __forceinline__ void push(int32_t s) {
-    const uint32_t v = ((uint32_t)s & 0xffffu) << ((n & 1) * 16);
-    const int w = (n >> 1) & 3;
-    buf.x |= w == 0 ? v : 0u;
-    buf.y |= w == 1 ? v : 0u;
-    buf.z |= w == 2 ? v : 0u;
-    buf.w |= w == 3 ? v : 0u;
+    buf.x = __builtin_amdgcn_alignbit(buf.y, buf.x, 16);
+    buf.y = __builtin_amdgcn_alignbit(buf.z, buf.y, 16);
+    buf.z = __builtin_amdgcn_alignbit(buf.w, buf.z, 16);
+    buf.w = (buf.w >> 16) | ((uint32_t)s << 16);
     n++;
-    if ((n & 7) == 0) {
-      full = buf;
-      ready = true;
-      buf = make_uint4(0, 0, 0, 0);
-    }
-  }
-
-  // The pending 16 bytes are those that ended at the last multiple of 8.
-  __device__ __forceinline__ void commit() {
-    if (ready) dst[(n >> 3) - 1] = full;
-    ready = false;
+    if ((n & 7) == 0) dst[(n >> 3) - 1] = buf;
   }
 
   __device__ __forceinline__ void flush() {
-    commit();
-    if (n & 7) dst[n >> 3] = buf;
+    const int r = n & 7;
+    if (r) {
+      // the r newest slots sit in the top r entries: shift them down by
+      // 8 - r entries, bringing zeros in above
+      uint4 b = buf;
+      for (int k = r; k < 8; k++) {
+        b.x = __builtin_amdgcn_alignbit(b.y, b.x, 16);
+        b.y = __builtin_amdgcn_alignbit(b.z, b.y, 16);
+        b.z = __builtin_amdgcn_alignbit(b.w, b.z, 16);
+        b.w = b.w >> 16;
+      }
+      dst[n >> 3] = b;
+    }
   }
 };
 
