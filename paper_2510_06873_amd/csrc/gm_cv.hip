@@ -216,8 +216,13 @@ __device__ __forceinline__ T group_sum(T v, int TPA) {
 }
 
 // Walk the n cutoff slots of one part, two records in flight: the next
-// record is fetched from LDS before the current one is used; slot numbers
-// come from a register stream over the part's sub-row.
+// record is fetched before the current one is used; slot numbers come from a
+// register stream over the part's sub-row.  When every slot is staged (ALL)
+// the pops and LDS fetches are unconditional (only the bodies are guarded),
+// so that the compiler can count the LDS reads in flight and wait for the
+// current record only; past the row's end the stream yields slots of the same
+// row (its zero padding or an earlier 16 bytes again), which are valid
+// records.  Otherwise a fetch may go to global memory and stays guarded.
 template <bool ALL, typename T, class Body>
 __device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr, const T* rows,
                                              const uint16_t* crow, int32_t n, uint4 first, Body body) {
@@ -227,13 +232,22 @@ __device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k,
   vec4_t<T> pa, pb;
   T va[16], vb[16];
   fetch_rec<ALL>(a, k, lr, rows, st.pop(), pa, va);
-  for (int32_t j = 0; j < n; j += 2) {
-    const bool b_ok = j + 1 < n;
-    if (b_ok) fetch_rec<ALL>(a, k, lr, rows, st.pop(), pb, vb);
-    body(pa, va);
-    if (b_ok) {
-      if (j + 2 < n) fetch_rec<ALL>(a, k, lr, rows, st.pop(), pa, va);
-      body(pb, vb);
+  if constexpr (ALL) {
+    for (int32_t j = 0; j < n; j += 2) {
+      fetch_rec<ALL>(a, k, lr, rows, st.pop(), pb, vb);
+      body(pa, va);
+      fetch_rec<ALL>(a, k, lr, rows, st.pop(), pa, va);
+      if (j + 1 < n) body(pb, vb);
+    }
+  } else {
+    for (int32_t j = 0; j < n; j += 2) {
+      const bool b_ok = j + 1 < n;
+      if (b_ok) fetch_rec<ALL>(a, k, lr, rows, st.pop(), pb, vb);
+      body(pa, va);
+      if (b_ok) {
+        if (j + 2 < n) fetch_rec<ALL>(a, k, lr, rows, st.pop(), pa, va);
+        body(pb, vb);
+      }
     }
   }
 }
