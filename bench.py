@@ -37,14 +37,15 @@ FLOPS_PER_PAIR_P4 = 210
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_pass4_wz1m_hbm_traffic.txt")
 KERNEL_SOURCES = ("gm_cv.hip", "gm_device.h", "gm_internal.h")
 # k_pass4 per owned atom: slot/rank tables 8, cutoff count 4, position 16, adjoint
-# row 64, taper term 16, permutation 4, force read + write 32
-P4_BYTES_PER_ATOM = 144
+# row 64 (its last three lanes hold the taper term), permutation 4, force read +
+# write 32
+P4_BYTES_PER_ATOM = 128
 # one MD step per atom: gather (perm 4, positions 16 read + 16 write), pass 1
 # (positions 16, q-hat row write 64), pass 2 (q-hat row 64, c' 4, count 4),
-# pass 3 (q-hat row 64, adjoint row write 64, taper term 16), pass 4 (as above
-# less what is counted), plus the per-step cutoff rows (2 B per pair, written
-# once and read three times, counted as 8 B per pair) and the rebuild / 10
-STEP_BYTES_PER_ATOM = 36 + 80 + 72 + 144 + 144
+# pass 3 (q-hat row 64, adjoint row write 64), pass 4 (as above), plus the
+# per-step cutoff rows (2 B per pair, written once and read three times,
+# counted as 8 B per pair) and the rebuild / 10
+STEP_BYTES_PER_ATOM = 36 + 80 + 72 + 128 + 128
 
 
 def kernel_digest():

@@ -42,7 +42,7 @@ struct gm_ctx {
   uint16_t *nbr = nullptr, *cut = nullptr;
   int32_t *cnt = nullptr, *ccnt = nullptr, *err = nullptr, *stats = nullptr;
   int4* order = nullptr;  // per brick, by rank: (atom, halo slot, sorted position, 0)
-  void *pos_s = nullptr, *qrow = nullptr, *grow = nullptr, *frad = nullptr, *nb = nullptr, *cn_atom = nullptr;
+  void *pos_s = nullptr, *qrow = nullptr, *grow = nullptr, *nb = nullptr, *cn_atom = nullptr;
   double *part_a = nullptr, *part_b = nullptr, *s_int = nullptr, *V_int = nullptr, *dV_int = nullptr;
   double *centres = nullptr, *heights = nullptr, *bias_part = nullptr;
   int64_t* hill_count = nullptr;
@@ -281,7 +281,6 @@ CvArgs<T> make_args(gm_ctx* c) {
     a.yc = c->ycd;
   a.qrow = reinterpret_cast<T*>(c->qrow);
   a.grow = reinterpret_cast<T*>(c->grow);
-  a.frad = reinterpret_cast<vec4_t<T>*>(c->frad);
   a.nb = reinterpret_cast<T*>(c->nb);
   a.cn_atom = reinterpret_cast<T*>(c->cn_atom);
   a.part_a = c->part_a;
@@ -440,7 +439,6 @@ void free_all(gm_ctx* c) {
   dfree(c->stream, c->pos_s);
   dfree(c->stream, c->qrow);
   dfree(c->stream, c->grow);
-  dfree(c->stream, c->frad);
   dfree(c->stream, c->nb);
   dfree(c->stream, c->cn_atom);
   dfree(c->stream, c->part_a);
@@ -566,7 +564,6 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   if (rc == GM_OK) rc = dalloc(c->stream, &c->pos_s, n * 4 * T);
   if (rc == GM_OK && c->has_q6) rc = dalloc(c->stream, &c->qrow, n * 16 * T);
   if (rc == GM_OK && c->has_q6) rc = dalloc(c->stream, &c->grow, n * 16 * T);
-  if (rc == GM_OK && c->has_q6) rc = dalloc(c->stream, &c->frad, n * 4 * T);
   if (rc == GM_OK) rc = dalloc(c->stream, &c->nb, n * T);
   if (rc == GM_OK) rc = dalloc(c->stream, &c->cn_atom, n * T);
   if (rc == GM_OK) rc = dalloc(c->stream, &c->s_int, 16);

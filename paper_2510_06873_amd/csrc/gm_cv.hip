@@ -582,16 +582,12 @@ __device__ __forceinline__ void pass3_atoms(const CvArgs<T>& a, const Brick& k, 
       T g[16];
 #pragma unroll
       for (int m = 0; m < 13; m++) g[m] = (hs[m] - proj * qi[m]) * inv;
-      g[13] = dci;
-      g[14] = T(0);
-      g[15] = T(0);
+      // the taper radial sum rides in the row's last three lanes, which pass 4
+      // reads with the atom's own staged record
+      g[13] = rx;
+      g[14] = ry;
+      g[15] = rz;
       store_row16(a.grow + (int64_t)ri * 16, g);
-      vec4_t<T> fr;
-      fr.x = rx;
-      fr.y = ry;
-      fr.z = rz;
-      fr.w = T(0);
-      a.frad[ri] = fr;
     }
   }
 }
@@ -671,10 +667,9 @@ __device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, 
       cz = group_sum(cz, TPA);
     }
     if (part == 0) {
-      const vec4_t<T> fr = a.frad[ri];
-      ax += fr.x;
-      ay += fr.y;
-      az += fr.z;
+      ax += gi[13];
+      ay += gi[14];
+      az += gi[15];
       write_out(a, ri, -(seed_q * ax + seed_cn * cx), -(seed_q * ay + seed_cn * cy), -(seed_q * az + seed_cn * cz));
     }
   }

@@ -130,8 +130,7 @@ struct CvArgs {
   double inv_n;
   YCoef<T> yc;
   T* qrow;          // [N][16] by sorted position: qhat(13), |Q|, c', sum f
-  T* grow;          // [N][16]: g(13), c'
-  vec4_t<T>* frad;  // [N]: sum over taper pairs of (c'_i + c'_j) b_ij f'(r) r_hat
+  T* grow;          // [N][16]: g(13), then the sum over taper pairs of (c'_i + c'_j) b_ij f'(r) r_hat (3)
   T* nb;            // [N] bond counts
   T* cn_atom;       // [N] per-atom coordination sums
   double* part_a;   // per-workgroup FP64 partial sums (count / coordination)

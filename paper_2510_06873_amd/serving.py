@@ -80,7 +80,7 @@ def device_bytes(req: Request) -> int:
     per_atom += 4 * 7 + 2 * 2 * kmax            # cell, perm, owned tables, counts, neighbour + cutoff rows
     per_atom += 4 * t + 2 * t                   # sorted positions, bond count, coordination
     if p.cv_kind != 1:
-        per_atom += 16 * t * 2 + 4 * t          # q-hat and adjoint rows, taper term
+        per_atom += 16 * t * 2                  # q-hat and adjoint rows
     per_atom += 4 * 8                           # halo slot table (bounded by 8 halo copies per atom)
     hills = p.hill_capacity * (p.dims + 1) * 8
     return int(n * per_atom + hills + (1 << 20))
