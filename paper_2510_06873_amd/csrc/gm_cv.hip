@@ -495,7 +495,7 @@ __device__ __forceinline__ double pass2_atoms(const CvArgs<T>& a, const Brick& k
     walk_records<ALL>(a, k, lr, a.qrow, a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0, [&](const vec4_t<T>& pj, const T* qj) {
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
-      const T r = g_sqrt(r2);
+      const T r = r2 * g_rsqrt(r2);  // the same r as passes 3 and 4
       T df;
       const T f = taper_w(r, a, df);
       T d = T(0);
