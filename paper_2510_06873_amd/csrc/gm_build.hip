@@ -261,6 +261,25 @@ __global__ __launch_bounds__(kBlock) void k_gather_batch(const GatherArgs* __res
   gather_body<T>(tab[lo], (g - blk_start[lo]) * blockDim.x + threadIdx.x);
 }
 
+// Inclusive prefix sum of v over the workgroup's threads in thread order
+// (blockDim.x a multiple of 64, at most kBlock): shuffle scans within each
+// wave, then each wave adds the totals of the waves before it.  All threads
+// call; wsum holds kBlock / 64 ints of LDS.
+__device__ __forceinline__ int32_t block_scan_incl_wave(int32_t v, int32_t* wsum) {
+  const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  if (lane == 63) wsum[w] = v;
+  __syncthreads();
+  int32_t add = 0;
+  for (int i = 0; i < w; i++) add += wsum[i];
+  __syncthreads();
+  return v + add;
+}
+
 // --------------------------------------------------------------------------
 // Bricks: halo sizes, halo slot tables, owned atoms (every rebuild)
 // --------------------------------------------------------------------------
@@ -299,28 +318,36 @@ __global__ __launch_bounds__(kBlock) void k_brick_fill(const int32_t* __restrict
                                                        int32_t* __restrict__ hp_out, int32_t* __restrict__ halo_rank,
                                                        int32_t* __restrict__ owned_slot, int32_t* __restrict__ owned_rank,
                                                        int32_t* __restrict__ owned_hcell, int32_t* err) {
+  static_assert(kHaloCells <= kBlock && kOwnCells <= kBlock, "one thread per halo cell");
   __shared__ int32_t hcell[kHaloCells], hpre[kHaloCells + 1];
   __shared__ int32_t oh[kOwnCells], opre[kOwnCells + 1];
+  __shared__ int32_t wsum[kBlock / 64];
   const int64_t b = blockIdx.x;
   const BrickShape s = brick_shape(b, g);
   const int nh = s.h[0] * s.h[1] * s.h[2];
   const int no = s.e[0] * s.e[1] * s.e[2];
-  for (int h = threadIdx.x; h < nh; h += blockDim.x) {
-    const int hx = h % s.h[0], hy = (h / s.h[0]) % s.h[1], hz = h / (s.h[0] * s.h[1]);
+  const int t = (int)threadIdx.x;
+  // thread t: halo cell t (its atom count) and owned cell t
+  int32_t ch = 0;
+  if (t < nh) {
+    const int hx = t % s.h[0], hy = (t / s.h[0]) % s.h[1], hz = t / (s.h[0] * s.h[1]);
     const int32_t c = halo_cell_id(s, g, hx, hy, hz);
-    hcell[h] = c;
-    hpre[h + 1] = start[c + 1] - start[c];
+    hcell[t] = c;
+    ch = start[c + 1] - start[c];
   }
-  for (int k = threadIdx.x; k < no; k += blockDim.x) {
-    const int ox = k % s.e[0], oy = (k / s.e[0]) % s.e[1], oz = k / (s.e[0] * s.e[1]);
-    oh[k] = ((oz + 1) * s.h[1] + (oy + 1)) * s.h[0] + (ox + 1);
+  if (t < no) {
+    const int ox = t % s.e[0], oy = (t / s.e[0]) % s.e[1], oz = t / (s.e[0] * s.e[1]);
+    oh[t] = ((oz + 1) * s.h[1] + (oy + 1)) * s.h[0] + (ox + 1);
   }
+  const int32_t hin = block_scan_incl_wave(ch, wsum);
+  if (t < nh) hpre[t + 1] = hin;
+  if (t == 0) hpre[0] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    hpre[0] = 0;
-    for (int h = 0; h < nh; h++) hpre[h + 1] += hpre[h];
+  const int32_t co = t < no ? hpre[oh[t] + 1] - hpre[oh[t]] : 0;
+  const int32_t oin = block_scan_incl_wave(co, wsum);
+  if (t < no) opre[t + 1] = oin;
+  if (t == 0) {
     opre[0] = 0;
-    for (int k = 0; k < no; k++) opre[k + 1] = opre[k] + (hpre[oh[k] + 1] - hpre[oh[k]]);
     if (hpre[nh] > 65535) atomicOr(err, kErrOverflow);  // slots must fit 16 bits
   }
   __syncthreads();
