@@ -667,9 +667,14 @@ __device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, 
       cz = group_sum(cz, TPA);
     }
     if (part == 0) {
-      ax += gi[13];
-      ay += gi[14];
-      az += gi[15];
+      // the taper radial sum: the last lanes of the atom's own record, read
+      // again here rather than held through the walk
+      vec4_t<T> po;
+      T go[16];
+      fetch_rec<ALL>(a, k, lr, a.grow, si, po, go);
+      ax += go[13];
+      ay += go[14];
+      az += go[15];
       write_out(a, ri, -(seed_q * ax + seed_cn * cx), -(seed_q * ay + seed_cn * cy), -(seed_q * az + seed_cn * cz));
     }
   }
