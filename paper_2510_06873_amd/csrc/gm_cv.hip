@@ -413,7 +413,7 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
 #pragma unroll
     for (int m = 0; m < 13; m++) Q[m] = T(0);
     T fsum = T(0), cnsum = T(0);
-    for_slots(crow, nc, first_chunk(crow, nc), [&](int32_t s) {
+    for_slots<true>(crow, nc, first_chunk(crow, nc), [&](int32_t s) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);

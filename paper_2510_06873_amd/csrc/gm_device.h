@@ -396,9 +396,9 @@ __device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, uint4 
   }
 }
 
-template <class Body>
+template <bool UNROLL = false, class Body>
 __device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, uint4 first, Body body) {
-  for_slots<false>(row, n, first, body, [] {});
+  for_slots<UNROLL>(row, n, first, body, [] {});
 }
 
 __device__ __forceinline__ uint4 first_chunk(const uint16_t* row, int32_t n) {
