@@ -394,7 +394,7 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
       if (pair_vec<WRAP>(pi, pj, a, dx, dy, dz) < a.rc2) wr.push(s);
-    }, [] {});
+    });
     wr.flush();
     const int32_t nc = wr.n;
     a.ccnt[(int64_t)(k.ob + o) * TPA + part] = nc;

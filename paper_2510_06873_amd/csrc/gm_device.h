@@ -359,14 +359,12 @@ struct SlotStream {
 // so its wait falls after 8 bodies.  The prefetch index is clamped to the
 // row's last used chunk, so the load is unconditional and in bounds.  `first`
 // holds the row's first 16 bytes when the caller loaded them already.
-// `after` runs once after each block: a body that writes memory keeps its
-// stores there, since a store in the inner loop (with no load beside it)
-// makes the compiler wait for the prefetch before the loop instead.
 // UNROLL = true writes the 8 bodies of a block out (each guarded by the
-// row's length), for small bodies whose state would otherwise be copied
-// around the inner loop.
-template <bool UNROLL = false, class Body, class After>
-__device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, uint4 first, Body body, After after) {
+// row's length, slots taken by constant index); a body may then also store
+// to memory, whereas a store inside the rolled inner loop (with no load
+// beside it) makes the compiler wait for the prefetch before that loop.
+template <bool UNROLL = false, class Body>
+__device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, uint4 first, Body body) {
   const uint4* src = reinterpret_cast<const uint4*>(row);
   const int32_t last = (n - 1) >> 3;
   uint4 cur = first;
@@ -391,14 +389,8 @@ __device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, uint4 
         cur.w = cur.w >> 16;
       }
     }
-    after();
     cur = nxt;
   }
-}
-
-template <bool UNROLL = false, class Body>
-__device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, uint4 first, Body body) {
-  for_slots<UNROLL>(row, n, first, body, [] {});
 }
 
 __device__ __forceinline__ uint4 first_chunk(const uint16_t* row, int32_t n) {
