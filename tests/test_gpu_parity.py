@@ -188,6 +188,52 @@ def test_dense_cluster_in_gas(orc, precision, tol_s, tol_f):
     assert rel_force_err(F[:, :3] - F_in[:, :3].astype(np.float64), -dv[0] * g_ref[0]) <= tol_f
 
 
+@pytest.mark.parametrize("precision,brick,tol_s,tol_f", [("fp32", (1, 1, 1), 1e-5, 1e-4), ("fp32", (2, 2, 2), 1e-5, 1e-4),
+                                                          ("fp32", (3, 3, 3), 1e-5, 1e-4),
+                                                          ("fp64", (1, 1, 1), 1e-10, 1e-10)])
+def test_rows_ending_on_16_byte_boundaries(orc, precision, brick, tol_s, tol_f):
+    """A simple cubic lattice (a = 1.6 A, 14^3 atoms, 0.02 A jitter) with r_c
+    3.45 and skin 0.3: every atom has exactly 32 neighbours inside r_c (shells
+    1.6, 2.26, 2.77 and 3.2 A) and 56 in its list (plus 3.58 A), so with 4, 2
+    or 1 threads per atom (bricks of 1, 8 and 27 cells) every in-cutoff
+    sub-row holds 8, 16 or 32 slots: each row walk ends exactly on a 16-byte
+    chunk, and every row write ends with a full chunk and no partial tail.
+    The 3x3x3 bricks stage less than their halo (the whole system), so their
+    walks also take the path that reads records from global memory.  Bond and
+    count thresholds (0.96 / 0.02 and 27 / 0.5) put the atoms on the slopes
+    of both logistics (s ~ 1,360 of 2,744)."""
+    a, L = 1.6, 14
+    g = np.arange(L) * a
+    box = np.full(3, L * a)
+    rng = np.random.default_rng(7)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pos = np.mod(pos + rng.uniform(-0.02, 0.02, pos.shape), box).astype(np.float32)
+    pos[pos >= box.astype(np.float32)] = 0.0  # the oracle sees the FP32 coordinates the GPU gets
+    pos = pos.astype(np.float64)
+    n = len(pos)
+    wl = dict(Q6CV, precision=precision, r_c=3.45, skin=0.3, bond_d0=0.96, bond_w=0.02, count_n0=27.0,
+              count_w=0.5)
+    prm = params_for(wl)
+    prm.brick = brick
+    from paper_2510_06873_amd import Pipeline
+
+    pipe = Pipeline(n, prm)
+    off, nb = orc.neighbors(pos, box, 3.75)
+    assert np.diff(off).min() == np.diff(off).max() == 56
+    F_in = W.external_forces(n, seed=13)
+    dv = [0.41]
+    s, F = run_step(pipe, pos, None, box, F_in, dv)
+    rows = gpu_neighbor_sets(pipe)
+    for i in range(n):
+        assert np.array_equal(rows[i], nb[off[i]:off[i + 1]]), i
+    _, _, cut = pipe.neighbor_stats(cutoff_pairs=True)
+    assert cut == 32 * n
+    s_ref, g_ref, _ = oracle_cvs(orc, pos, box, wl, nl=(off, nb))
+    assert 0.3 * n < s_ref[0] < 0.7 * n
+    assert abs(s[0] - s_ref[0]) <= tol_s * abs(s_ref[0])
+    assert rel_force_err(F[:, :3] - F_in[:, :3].astype(np.float64), -dv[0] * g_ref[0]) <= tol_f
+
+
 def test_q6_forces_wrapped_pairs_long_box(orc):
     """Pairs across the periodic faces of a 204 A box: the minimum-image
     difference must not round at the magnitude of the box length (FP32 ulp at
