@@ -227,19 +227,33 @@ template <bool ALL, typename T, class Body>
 __device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr, const T* rows,
                                              const uint16_t* crow, int32_t n, uint4 first, Body body) {
   if (n <= 0) return;
-  SlotStream st;
-  st.init_first(crow, n, first);
   vec4_t<T> pa, pb;
   T va[16], vb[16];
-  fetch_rec<ALL>(a, k, lr, rows, st.pop(), pa, va);
   if constexpr (ALL) {
-    for (int32_t j = 0; j < n; j += 2) {
-      fetch_rec<ALL>(a, k, lr, rows, st.pop(), pb, vb);
-      body(pa, va);
-      fetch_rec<ALL>(a, k, lr, rows, st.pop(), pa, va);
-      if (j + 1 < n) body(pb, vb);
+    // blocks of 8 slots, written out: slot e of a block by constant index,
+    // the next block's 16 bytes loaded at the block start (its first slot is
+    // the lookahead of the block's last pair)
+    const uint4* src = reinterpret_cast<const uint4*>(crow);
+    const int32_t last = (n - 1) >> 3;
+    uint4 cur = first;
+    fetch_rec<ALL>(a, k, lr, rows, (int32_t)(cur.x & 0xffffu), pa, va);
+    for (int32_t b = 0; b < n; b += 8) {
+      const uint4 nxt = src[min((b >> 3) + 1, last)];
+      const uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        fetch_rec<ALL>(a, k, lr, rows, (int32_t)(w[e >> 1] >> 16), pb, vb);
+        if (b + e < n) body(pa, va);
+        const int32_t s2 = e + 2 < 8 ? (int32_t)(w[(e + 2) >> 1] & 0xffffu) : (int32_t)(nxt.x & 0xffffu);
+        fetch_rec<ALL>(a, k, lr, rows, s2, pa, va);
+        if (b + e + 1 < n) body(pb, vb);
+      }
+      cur = nxt;
     }
   } else {
+    SlotStream st;
+    st.init_first(crow, n, first);
+    fetch_rec<ALL>(a, k, lr, rows, st.pop(), pa, va);
     for (int32_t j = 0; j < n; j += 2) {
       const bool b_ok = j + 1 < n;
       if (b_ok) fetch_rec<ALL>(a, k, lr, rows, st.pop(), pb, vb);
