@@ -718,7 +718,7 @@ __device__ __forceinline__ void cn_force_atoms(const CvArgs<T>& a, const Brick& 
   GM_FOR_RANKED(a, k, h0) {
     const vec4_t<T> pi = fetch_pos<ALL>(a, k, lp, si);
     T cx = T(0), cy = T(0), cz = T(0);
-    for_slots(a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0, [&](int32_t s) {
+    for_slots<true>(a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0, [&](int32_t s) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
