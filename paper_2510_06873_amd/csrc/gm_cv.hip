@@ -576,12 +576,11 @@ __device__ __forceinline__ void pass3_atoms(const CvArgs<T>& a, const Brick& k, 
       const T coef = f * b * (T(1) - b) * a.inv_bond_w * cs;
 #pragma unroll
       for (int m = 0; m < 13; m++) hs[m] += coef * qj[m];
-      if (df != T(0)) {
-        const T rad = cs * b * df * rinv;
-        rx += rad * dx;
-        ry += rad * dy;
-        rz += rad * dz;
-      }
+      // df = 0 below the taper shell: the radial term adds zero there
+      const T rad = cs * b * df * rinv;
+      rx += rad * dx;
+      ry += rad * dy;
+      rz += rad * dz;
     });
 #pragma unroll
     for (int m = 0; m < 13; m++) hs[m] = group_sum(hs[m], TPA);
@@ -653,11 +652,10 @@ __device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, 
       T px = fr * (Sx - ud * ux);
       T py = fr * (Sy - ud * uy);
       T pz = fr * (Sz - ud * uz);
-      if (df != T(0)) {
-        px += df * S * ux;
-        py += df * S * uy;
-        pz += df * S * uz;
-      }
+      const T dS = df * S;  // zero below the taper shell
+      px += dS * ux;
+      py += dS * uy;
+      pz += dS * uz;
       ax += px;
       ay += py;
       az += pz;
