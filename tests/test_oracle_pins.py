@@ -452,3 +452,102 @@ def test_deposit_sequence_matches_stepwise(orc):
     for k in (0, 1, 57, 199):
         V = orc.bias(cen[:k], h[:k], sig, cen[k])[0]
         assert h[k] == orc.wt_height(1.2, 10.0, W.KBT_KJMOL, V)
+
+
+# --------------------------------------------------------------------------
+# The crystalline-count stage (bond dots -> b_ij -> n_i -> c_i -> s), pinned
+# by geometry: the bond dots come from the Legendre addition theorem over the
+# two atoms' shells (never from the oracle's harmonics), the taper weights from
+# the pair distances, and the logistics are the workload's definition.
+# --------------------------------------------------------------------------
+def _logistic(x, centre, width):
+    return 1.0 / (1.0 + np.exp(-(x - centre) / width))
+
+
+def _shell_dots(pos, box, rc, D, pairs):
+    """d_ij = Q_i.Q_j / (|Q_i||Q_j|) by the addition theorem, for each (i, j)."""
+    cache = {}
+
+    def shell(i):
+        if i not in cache:
+            u, r = _shell(pos, box, i, rc)
+            cache[i] = (u, _taper(r, rc, D))
+        return cache[i]
+
+    out = []
+    for i, j in pairs:
+        ui, fi = shell(i)
+        uj, fj = shell(j)
+        qii = fi @ eval_legendre(6, ui @ ui.T) @ fi
+        qjj = fj @ eval_legendre(6, uj @ uj.T) @ fj
+        qij = fi @ eval_legendre(6, ui @ uj.T) @ fj
+        out.append(qij / np.sqrt(qii * qjj))
+    return np.array(out)
+
+
+def test_count_stage_perfect_wurtzite_closed_form(orc):
+    """Perfect wurtzite: every atom has 9 bond dots of exactly 1 (its own site
+    type) and 8 of one value d2 (the other type, from the addition theorem),
+    all weights 1, so n_i = 9 b(1) + 8 b(d2) and s = N c(n) for every atom."""
+    pos, sp, box = W.wurtzite_ideal(6, 3, 4)
+    nl = orc.neighbors(pos, box, 4.0)
+    out = orc.q6_forward(pos, box, nl, orc.q6_params(**Q6CV))
+    n = len(pos)
+    # an atom of the other site type among atom 0's neighbours (dot != 1)
+    u0, r0 = _shell(pos, box, 0, 3.6)
+    assert len(r0) == 17 and np.all(r0 < 3.6 - 0.2)  # all weights are 1
+    d = pos - pos[0]
+    d -= box * np.rint(d / box)
+    cand = [j for j in range(1, n) if np.linalg.norm(d[j]) < 3.6]
+    dots = _shell_dots(pos, box, 3.6, 0.2, [(0, j) for j in cand])
+    same = np.abs(dots - 1.0) < 1e-9
+    assert same.sum() == 9 and (~same).sum() == 8
+    d2 = dots[~same]
+    assert np.ptp(d2) < 1e-12 and abs(d2[0] - 0.6610857) < 1e-7
+    n_ref = 9 * _logistic(1.0, 0.7, 0.02) + 8 * _logistic(d2[0], 0.7, 0.02)
+    c_ref = _logistic(n_ref, 5.5, 0.25)
+    assert abs(n_ref - 10.0001686) < 1e-7
+    assert np.max(np.abs(out["nb"] - n_ref)) < 1e-12
+    assert np.max(np.abs(out["c"] - c_ref)) < 1e-15
+    assert abs(out["s"] - n * c_ref) < 1e-12 * n
+    assert abs(out["s"] / n - (1 - 1.5e-8)) < 1e-9
+
+
+def test_count_stage_taper_and_slopes(orc):
+    """A jittered fcc cluster whose first shell straddles the taper (r_c 2.8,
+    taper 0.4), with bond and count widths chosen so that the dots and counts
+    lie on the logistics' slopes: n_i = sum_j f(r_ij) b(d_ij) per atom, c_i =
+    c(n_i), c'_i = c(1 - c)/w_c and s = sum_i c_i against the weights and
+    dots computed from the geometry.  A dropped weight, swapped widths or a
+    flipped sign each fail it."""
+    rng = np.random.default_rng(17)
+    ideal, _ = W.fcc_ideal(3, 3.615)
+    ideal = ideal[np.linalg.norm(ideal - ideal.mean(0), axis=1) < 5.5]
+    pos = ideal - ideal.mean(0) + 20.0 + rng.normal(0.0, 0.18, ideal.shape)
+    box = np.array([40.0, 40.0, 40.0])
+    rc, D, d0, wb, n0, wc = 2.8, 0.4, 0.6, 0.08, 4.0, 1.5
+    prm = orc.q6_params(rc, D, d0, wb, n0, wc)
+    nl = orc.neighbors(pos, box, rc + 0.4)
+    out = orc.q6_forward(pos, box, nl, prm)
+    n = len(pos)
+    nb_ref = np.zeros(n)
+    pairs, w = [], []
+    for i in range(n):
+        u, r = _shell(pos, box, i, rc)
+        d = pos - pos[i]
+        d -= box * np.rint(d / box)
+        js = [j for j in range(n) if j != i and np.linalg.norm(d[j]) < rc]
+        pairs += [(i, j) for j in js]
+        w += list(_taper(np.linalg.norm(d[js], axis=1), rc, D))
+    dots = _shell_dots(pos, box, rc, D, pairs)
+    w = np.array(w)
+    np.add.at(nb_ref, [i for i, _ in pairs], w * _logistic(dots, d0, wb))
+    c_ref = _logistic(nb_ref, n0, wc)
+    # the case exercises every term: weights inside the taper, dots and counts on the slopes
+    assert np.sum((w > 0.05) & (w < 0.95)) > 20
+    assert np.sum(np.abs(dots - d0) < 2 * wb) > 20
+    assert np.sum(np.abs(nb_ref - n0) < wc) > 5
+    assert np.max(np.abs(out["nb"] - nb_ref)) < 1e-12 * max(1.0, nb_ref.max())
+    assert np.max(np.abs(out["c"] - c_ref)) < 1e-12
+    assert np.max(np.abs(out["dc"] - c_ref * (1 - c_ref) / wc)) < 1e-12
+    assert abs(out["s"] - c_ref.sum()) < 1e-12 * n
