@@ -9,7 +9,11 @@ forces N(0, 1 eV/A)):
 i.e. 10 MD steps = 10 N atom-steps.  Inputs are resident in HBM before the
 timed region.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--graph] [--no-cpu]
+The line also carries the walker-serving workload (256 requests of 1k-200k
+atoms, continuous batching against sequential launches: p50/p99 latency and
+aggregate atom-steps/s) and the oracle timed on the host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--graph] [--no-cpu] [--no-serving]
 """
 from __future__ import annotations
 
@@ -23,8 +27,11 @@ import numpy as np
 
 MD_STEPS_PER_WINDOW = 10
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed FP32: 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz
-ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# MI355X's published FP32 vector peak (packed FP32: two lanes' FMAs per
+# instruction), and the ceiling without packed FP32, which this library's
+# kernels are built without: 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 157.3
+ALU_NONPACKED_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # Algorithmic flops of k_pass4 per ordered pair inside r_c (FMA = 2): pair
 # vector and r^2 8, 1/r and unit vector 5, g_i + g_j 13, E_m(z) 22, S and its
 # gradient by the complex recurrence 144, tangential projection and
@@ -46,6 +53,17 @@ P4_BYTES_PER_ATOM = 128
 # per-step cutoff rows (2 B per pair, written once and read three times,
 # counted as 8 B per pair) and the rebuild / 10
 STEP_BYTES_PER_ATOM = 36 + 80 + 72 + 128 + 128
+
+
+def model_bytes_per_atom_step(k_mean):
+    """The algorithmic HBM bytes of one q6 atom-step in the layout-independent
+    model: positions 16, force in + out 32, the neighbour list read once
+    4 (K + 1), the 13-float q-hat and adjoint rows written and read
+    (2 x 52 each), c' written and read (2 x 4), and the rebuild (positions 16,
+    cell id and permutation 12, list write 4 (K + 1)) over 10 steps; K is the
+    mean list length.  About 380 B at K = 24.5."""
+    nl = 4.0 * (k_mean + 1.0)
+    return 16 + 32 + nl + 2 * 52 + 2 * 4 + 2 * 52 + (16 + 12 + nl) / MD_STEPS_PER_WINDOW
 
 
 def kernel_digest():
@@ -95,8 +113,6 @@ def parse():
     ap.add_argument("--workload", default="wz1m")
     ap.add_argument("--graph", action="store_true", help="replay each window as a captured HIP graph")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--serving", action="store_true",
-                    help="also run the walker-serving workload (256 requests, continuous batching vs sequential)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving workload")
     ap.add_argument("--autograd", action="store_true",
                     help="only time the autograd wrappers (stored vs recompute) on the 262,144-atom 2-D CV")
@@ -106,6 +122,10 @@ def parse():
     ap.add_argument("--lds-kb", type=int, default=0, help="LDS staging budget per workgroup (KiB)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the walker-serving block of the default line")
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -193,10 +213,12 @@ def window(S, ev=None):
     timed("deposit_hill", pipe.deposit_hill)
 
 
-def cpu_baseline(wl_name="wz96k"):
-    """The oracle as it stands, single threaded, on the same recipe at 96,000
-    atoms: one neighbour build amortised over 10 steps plus one step of
-    forward, gradient, bias and force."""
+def cpu_leg(wl_name, seconds):
+    """One process of the CPU baseline: the oracle as it stands (plain C,
+    single threaded, FP64) on a workload's full input (all its hills):
+    repeated MD steps of the bias pipeline (a neighbour build amortised over
+    10 steps, q6 forward, bias, q6 gradient and forces) for about `seconds`,
+    at least one.  Runs in a child process of its own, with no GPU."""
     import oracle as orc
     import workloads as W
 
@@ -206,28 +228,83 @@ def cpu_baseline(wl_name="wz96k"):
     n = pos.shape[0]
     prm = orc.q6_params(wl["r_c"], wl["taper"], wl["bond_d0"], wl["bond_w"], wl["count_n0"], wl["count_w"])
     hp = wl["hills"]
-    cen = W.hill_centres(min(hp["k"], 2000), hp["lo"], hp["hi"], hp["seed"])
+    cen = W.hill_centres(hp["k"], hp["lo"], hp["hi"], hp["seed"])
     hts = np.full(cen.shape[0], wl["w0"])
+    F_in = W.external_forces(n, seed=wl.get("force_seed", 4))
     t_nl = t_step = 0.0
     reps = 0
     t_all = time.time()
-    while reps < 1 or time.time() - t_all < 10.0:
+    while reps < 1 or time.time() - t_all < seconds:
         t0 = time.time()
         nl = orc.neighbors(pos, box, wl["r_c"] + wl["skin"])
         t1 = time.time()
         s = orc.q6_forward(pos, box, nl, prm)["s"]
         _, dv = orc.bias(cen, hts, wl["sigma"], [s])
         g = orc.q6_gradient(pos, box, nl, prm)
-        orc.bias_forces(W.external_forces(n, seed=4), [g], dv)
+        orc.bias_forces(F_in, [g], dv)
         t2 = time.time()
         t_nl += t1 - t0
         t_step += t2 - t1
         reps += 1
     per_step = (t_nl / MD_STEPS_PER_WINDOW + t_step) / reps
-    return {"value": n / per_step, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{wl_name}: {n} atoms (same slab recipe as the 1,024,000-atom workload), "
-                      f"{reps} x (neighbour build / 10 + q6 forward + q6 gradient + bias + forces), "
-                      f"FP64, single thread, {time.time() - t_all:.1f} s"}
+    return {"workload": wl_name, "atoms": n, "hills": int(cen.shape[0]), "reps": reps,
+            "s_per_md_step": per_step, "atom_steps_per_s": n / per_step, "wall_s": time.time() - t_all}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
+def _run_legs(specs):
+    """Run `bench.py --cpu-leg` children concurrently; their JSON results."""
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", ROCR_VISIBLE_DEVICES="")
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-leg", wl, "--cpu-seconds",
+                               str(sec)], stdout=subprocess.PIPE, env=env) for wl, sec in specs]
+    out = []
+    for p in procs:
+        stdout, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"CPU baseline leg exited with {p.returncode}")
+        out.append(json.loads(stdout.decode().strip().splitlines()[-1]))
+    return out
+
+
+def cpu_baseline():
+    """The oracle timed on the host cores, in child processes (no GPU): one
+    thread on the 96,000-atom slab; one such process per core of this
+    process's CPU share (at most 16), concurrently (the oracle is single
+    threaded; independent processes on the same sample make the all-core
+    figure); and one MD step at the full 1,024,000 atoms.  `value` is the
+    all-core aggregate."""
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    procs = max(1, min(16, cores))
+    t = time.time()
+    one = _run_legs([("wz96k", 8.0)])[0]
+    many = _run_legs([("wz96k", 8.0)] * procs)
+    full = _run_legs([("wz1m", 0.0)])[0]
+    agg = sum(r["atom_steps_per_s"] for r in many)
+    return {"value": agg, "unit": "atom-steps/s", "cores": procs, "kind": "oracle",
+            "sample": f"wz96k: 96000 atoms (the slab recipe of the 1,024,000-atom workload, all 10,000 hills): "
+                      f"{procs} concurrent single-threaded processes x >= 8 s of MD steps (neighbour build / 10 + "
+                      f"q6 forward + bias + q6 gradient + forces), FP64; total {time.time() - t:.1f} s with the legs "
+                      f"below",
+            "cpu_model": cpu_model(), "cpu_share": cores,
+            "legs": {"one_thread_96k": round(one["atom_steps_per_s"], 1),
+                     "all_cores_96k": round(agg, 1), "all_cores_processes": procs,
+                     "one_thread_1m": round(full["atom_steps_per_s"], 1),
+                     "one_thread_1m_s_per_md_step": round(full["s_per_md_step"], 2),
+                     "one_thread_1m_hills": full["hills"]}}
 
 
 def autograd_bench(steps=20, warmup=3):
@@ -313,7 +390,7 @@ def serving(args):
     """p50/p99 request latency and aggregate atom-steps/s, batched vs sequential."""
     from paper_2510_06873_amd.serving import serve_batched, serve_sequential, summarize
 
-    reqs = serving_requests()
+    reqs = serving_requests(count=args.serving_requests)
     warm = serving_requests(count=4, seed=99, n_hi=5000)
     serve_batched(warm, hbm_budget=64 << 30)
     serve_sequential(warm)
@@ -335,6 +412,9 @@ def serving(args):
 
 def main():
     args = parse()
+    if args.cpu_leg:
+        print(json.dumps(cpu_leg(args.cpu_leg, args.cpu_seconds)), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -401,23 +481,28 @@ def main():
     roofline = None
     if "apply_bias_forces" in per_call_us:
         # Dominant launch: k_pass4 (apply_bias_forces, one launch per call), bound
-        # by FP32 VALU work.  Peak: 256 CUs x 64 FP32 lanes x 2 x 2.4 GHz
-        # (packed FP32 is not used).
+        # by FP32 VALU work: the fraction of the published FP32 peak, and of the
+        # ceiling without packed FP32 (which these kernels do not use).
         t_us = per_call_us["apply_bias_forces"]
         flops = FLOPS_PER_PAIR_P4 * cut_pairs
         achieved = flops / (t_us * 1e-6) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                    "peak_nonpacked": round(ALU_NONPACKED_TFLOPS, 1),
+                    "frac_nonpacked": round(achieved / ALU_NONPACKED_TFLOPS, 4),
                     "traffic": measured_traffic() if args.workload == "wz1m" else None,
                     "kernel": "k_pass4 (apply_bias_forces)", "avg_launch_us": round(t_us, 2),
                     "flops_per_launch": int(flops), "pairs_in_cutoff": int(cut_pairs),
                     "hbm_bytes_per_launch": int(n * P4_BYTES_PER_ATOM + 2 * cut_pairs)}
-    # Whole step against HBM: algorithmic bytes per atom-step (each array the
-    # dependency chain forces through memory, once per write and once per read).
-    step_bytes = n * STEP_BYTES_PER_ATOM + 2 * 4 * cut_pairs + n * (4 * (total_entries / n) + 40) / MD_STEPS_PER_WINDOW
-    step_hbm = step_bytes / (ms_per_window / MD_STEPS_PER_WINDOW * 1e-3) / 1e9
+    # Whole step against HBM: the layout-independent model's algorithmic bytes
+    # per atom-step, and beside it this layout's own (its 16-wide rows, cutoff
+    # rows and tables, each counted once per write and once per read).
+    step_s = ms_per_window / MD_STEPS_PER_WINDOW * 1e-3
+    bpas = model_bytes_per_atom_step(total_entries / n)
+    step_hbm = n * bpas / step_s / 1e9
+    layout_bytes = n * STEP_BYTES_PER_ATOM + 2 * 4 * cut_pairs + n * (4 * (total_entries / n) + 40) / MD_STEPS_PER_WINDOW
     out = {
-        "metric": "atom-steps/s for q6-CV+bias+force at 1.02M atoms (%HBM roofline)",
+        "metric": "atom-steps/s for q6-CV+bias+force at 1.02M atoms (%HBM roofline); p50/p99 req latency",
         "value": value,
         "unit": "atom-steps/s",
         "n_gpus": 1,
@@ -438,9 +523,12 @@ def main():
         "per_call_us": {k: round(v, 2) for k, v in per_call_us.items()},
         "roofline": roofline,
         "step_hbm": {"achieved_gbs": round(step_hbm, 1), "peak_gbs": HBM_PEAK_GBS,
-                     "frac": round(step_hbm / HBM_PEAK_GBS, 4), "bytes_per_step": int(step_bytes)},
+                     "frac": round(step_hbm / HBM_PEAK_GBS, 4), "bytes_per_atom_step": round(bpas, 1),
+                     "bytes_per_step": int(n * bpas), "layout_bytes_per_step": int(layout_bytes),
+                     "layout_frac": round(layout_bytes / step_s / 1e9 / HBM_PEAK_GBS, 4)},
     }
-    if args.serving:
+    if not args.no_serving and args.workload == "wz1m":
+        log("[bench] serving workload ...")
         out["serving"] = serving(args)
     if not args.no_cpu:
         log("[bench] timing the oracle on the host cores ...")

@@ -157,7 +157,9 @@ int gm_cv_forward(gm_ctx* ctx, const float* pos4, double* s_dev);
  * give V = 0. */
 int gm_bias_eval(gm_ctx* ctx, const double* s_dev, double* V_dev, double* dVds_dev);
 
-/* Adjoint of the last gm_cv_forward (same pos4).  Computes the per-atom
+/* Adjoint of the last gm_cv_forward, whose pos4 pointer it must be given
+ * again (GM_ERR_STATE otherwise; the kernels work from the positions that
+ * forward pass gathered, so the array must not have changed).  Computes the per-atom
  * adjoint state the force pass needs.  If grad4 != NULL it also writes
  *   grad4[i] = sum_d seed_d ds_d/dx_i
  * (dev [N][4] of the context precision, caller's atom order; lane 3 is left
@@ -170,7 +172,8 @@ int gm_cv_backward(gm_ctx* ctx, const float* pos4, const double* seed_dev, void*
  * caller's atom order):
  *   F_i <- F_i - sum_d dV/ds_d * ds_d/dx_i       (from U_b = U_0 + V_b)
  * dVds_dev: dev double[dims], e.g. from gm_bias_eval.  GM_ERR_STATE unless
- * gm_cv_backward ran since the last gm_cv_forward. */
+ * gm_cv_backward ran since the last gm_cv_forward, or if pos4 is not the
+ * pointer that forward pass was given (the force is that of its positions). */
 int gm_apply_bias_forces(gm_ctx* ctx, const float* pos4, const double* dVds_dev, void* force4);
 
 /* Deposit one hill at s_dev (dev double[dims]) with the well-tempered height
@@ -266,9 +269,11 @@ int gm_batch_step(gm_batch* batch);
 /* Deposit one well-tempered hill per walker at its current CV value. */
 int gm_batch_deposit(gm_batch* batch);
 
-/* Copy each walker's CV and bias (enqueued): s_dev dev double[count][2]
- * (second column 0 for 1-D CVs), V_dev dev double[count]; either may be NULL. */
-int gm_batch_values(gm_batch* batch, double* s_dev, double* V_dev);
+/* Copy each walker's CV, bias and bias gradient of its last step (enqueued):
+ * s_dev dev double[count][2] (second column 0 for 1-D CVs), V_dev dev
+ * double[count], dVds_dev dev double[count][2] (second column 0 for 1-D
+ * CVs); any may be NULL. */
+int gm_batch_values(gm_batch* batch, double* s_dev, double* V_dev, double* dVds_dev);
 
 /* Library version string. */
 /* ---- CVs of a few atoms ----------------------------------------------------

@@ -90,7 +90,7 @@ def _load() -> C.CDLL:
         "gm_batch_build": ([vp, dp], C.c_int),
         "gm_batch_step": ([vp], C.c_int),
         "gm_batch_deposit": ([vp], C.c_int),
-        "gm_batch_values": ([vp, vp, vp], C.c_int),
+        "gm_batch_values": ([vp, vp, vp, vp], C.c_int),
         "gm_torsions": ([vp, C.c_int64, vp, C.c_int32, dp, vp, vp], C.c_int),
         "gm_torsion_forces": ([vp, C.c_int64, vp, C.c_int32, dp, vp, vp, C.c_int32, vp], C.c_int),
         "gm_nearest_distance": ([vp, C.c_int64, C.c_int32, vp, C.c_int32, dp, vp, vp, vp], C.c_int),
@@ -400,6 +400,7 @@ class Batch:
         dev = self.pos4[0].device
         self.s = torch.zeros((w, 2), dtype=torch.float64, device=dev)
         self.V = torch.zeros(w, dtype=torch.float64, device=dev)
+        self.dVds = torch.zeros((w, 2), dtype=torch.float64, device=dev)
         cur = torch.cuda.current_stream()
         if cur != self.stream:
             self.stream.wait_stream(cur)
@@ -431,8 +432,13 @@ class Batch:
 
     def values(self):
         """(s[W, 2], V[W]) device tensors, enqueued on the batch stream."""
-        _check(_lib.gm_batch_values(self.h, self.s.data_ptr(), self.V.data_ptr()), "gm_batch_values")
+        _check(_lib.gm_batch_values(self.h, self.s.data_ptr(), self.V.data_ptr(), None), "gm_batch_values")
         return self.s, self.V
+
+    def gradients(self):
+        """dV/ds[W, 2] of every walker's last step (device tensor, enqueued on the batch stream)."""
+        _check(_lib.gm_batch_values(self.h, None, None, self.dVds.data_ptr()), "gm_batch_values")
+        return self.dVds
 
 
 def version() -> str:

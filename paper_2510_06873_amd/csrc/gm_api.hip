@@ -48,6 +48,7 @@ struct gm_ctx {
   int64_t* hill_count = nullptr;
 
   bool built = false, fwd = false, bwd = false;
+  const float* fwd_pos = nullptr;  // positions of the last forward pass
   int last_status = GM_OK;
   int64_t version = 0;  // bumped whenever the kernel arguments may change
   int lds_budget = 0;   // bytes of dynamic LDS for the staged halo
@@ -722,6 +723,7 @@ int gm_cv_forward(gm_ctx* c, const float* pos4, double* s_dev) {
   c->fwd = c->bwd = false;
   GM_TRY(c->fp64 ? cv_forward_t<double>(c, pos4, s_dev) : cv_forward_t<float>(c, pos4, s_dev));
   c->fwd = true;
+  c->fwd_pos = pos4;
   return GM_OK;
 }
 
@@ -745,7 +747,7 @@ int gm_cv_backward(gm_ctx* c, const float* pos4, const double* seed_dev, void* g
   if (!seed_dev && c->dims > 1 && grad4) return GM_ERR_INVALID_ARG;
   const size_t vs = c->fp64 ? 32 : 16;
   if (grad4 && !aligned(grad4, vs)) return GM_ERR_INVALID_ARG;
-  if (!c->fwd) return GM_ERR_STATE;
+  if (!c->fwd || pos4 != c->fwd_pos) return GM_ERR_STATE;
   if (c->has_q6) {
     if (c->fp64)
       GM_TRY(hip_rc(launch_q6_adjoint<double>(make_args<double>(c), c->stream)));
@@ -761,7 +763,7 @@ int gm_apply_bias_forces(gm_ctx* c, const float* pos4, const double* dVds_dev, v
   if (!c || !pos4 || !dVds_dev || !force4) return GM_ERR_INVALID_ARG;
   const size_t vs = c->fp64 ? 32 : 16;
   if (!aligned(force4, vs)) return GM_ERR_INVALID_ARG;
-  if (!c->bwd) return GM_ERR_STATE;
+  if (!c->bwd || pos4 != c->fwd_pos) return GM_ERR_STATE;
   return c->fp64 ? force_pass<double>(c, dVds_dev, force4, 0) : force_pass<float>(c, dVds_dev, force4, 0);
 }
 
@@ -1004,7 +1006,11 @@ int batch_step_t(gm_batch* B) {
     } else {
       GM_TRY(hip_rc(launch_pass_batch<T>(6, true, false, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
     }
-    for (int m : g.members) B->walkers[m]->fwd = B->walkers[m]->bwd = true;
+    for (int m : g.members) {
+      gm_ctx* c = B->walkers[m];
+      c->fwd = c->bwd = true;
+      c->fwd_pos = B->pos[m];
+    }
   }
   return GM_OK;
 }
@@ -1190,13 +1196,17 @@ int gm_batch_deposit(gm_batch* B) {
   return GM_OK;
 }
 
-int gm_batch_values(gm_batch* B, double* s_dev, double* V_dev) {
+int gm_batch_values(gm_batch* B, double* s_dev, double* V_dev, double* dVds_dev) {
   if (!B) return GM_ERR_INVALID_ARG;
+  if ((s_dev && !aligned(s_dev, 8)) || (V_dev && !aligned(V_dev, 8)) || (dVds_dev && !aligned(dVds_dev, 8)))
+    return GM_ERR_INVALID_ARG;
   for (size_t i = 0; i < B->walkers.size(); i++) {
     gm_ctx* c = B->walkers[i];
     if (s_dev && hipMemcpyAsync(s_dev + 2 * i, c->s_int, 16, hipMemcpyDeviceToDevice, B->stream) != hipSuccess)
       return GM_ERR_HIP;
     if (V_dev && hipMemcpyAsync(V_dev + i, c->V_int, 8, hipMemcpyDeviceToDevice, B->stream) != hipSuccess)
+      return GM_ERR_HIP;
+    if (dVds_dev && hipMemcpyAsync(dVds_dev + 2 * i, c->dV_int, 16, hipMemcpyDeviceToDevice, B->stream) != hipSuccess)
       return GM_ERR_HIP;
   }
   return GM_OK;

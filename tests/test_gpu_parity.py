@@ -459,6 +459,14 @@ def test_errors_and_call_order():
     F = torch.zeros((n, 4), dtype=torch.float32, device=dev())
     with pytest.raises(GmError, match="STATE"):
         pipe.apply_bias_forces(p4, F)
+    # backward and the force pass need the positions of the last forward
+    other = p4.clone()
+    with pytest.raises(GmError, match="STATE"):
+        pipe.cv_backward(other)
+    pipe.cv_backward(p4)
+    with pytest.raises(GmError, match="STATE"):
+        pipe.apply_bias_forces(other, F)
+    pipe.apply_bias_forces(p4, F)
     bad = p4.clone()
     bad[3, 1] = float("nan")
     pipe.cv_forward(bad)
