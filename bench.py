@@ -364,7 +364,9 @@ def autograd_bench(steps=20, warmup=3):
         e1.record()
         e1.synchronize()
         out[name + "_ms"] = round(e0.elapsed_time(e1) / steps, 4)
-        log(f"[bench] autograd {name}: {out[name + '_ms']} ms")
+        # device memory the context holds between two calls
+        out[name + "_context_bytes"] = pipe.device_bytes()
+        log(f"[bench] autograd {name}: {out[name + '_ms']} ms, context holds {out[name + '_context_bytes']} B")
     pipe.check()
     return out
 

@@ -212,6 +212,22 @@ const char* gm_strerror(int code);
  * first one).  Any output pointer may be NULL (synchronous). */
 int gm_neighbor_stats(gm_ctx* ctx, int32_t* max_count, int64_t* total, int64_t* cutoff_pairs);
 
+/* Release the per-atom q6 rows of the context (the q-hat rows the forward
+ * pass writes and the adjoint rows of gm_cv_backward: 2 x 16 values per atom
+ * of the context precision) back to the library's pool, in stream order (no
+ * wait); the next gm_cv_forward (or batch step) allocates them again.  For a
+ * caller that recomputes the forward pass before each backward (the
+ * differentiation's "recompute" mode: paper, Results, "Frameworks of
+ * GPU-MetaD", forces by differentiating the CV), so that the context holds
+ * no per-atom CV state between calls.  Backward and the force pass then need
+ * a new gm_cv_forward (GM_ERR_STATE otherwise).  No effect on a coordination
+ * context, which has no such rows. */
+int gm_release_rows(gm_ctx* ctx);
+
+/* Bytes of device memory the context holds now (its buffers in the pool;
+ * host value, no device work). */
+int gm_device_bytes(gm_ctx* ctx, int64_t* bytes);
+
 /* Set the neighbour-list row width (rounded up to a multiple of 4) and
  * reallocate in stream order (no wait); the lists must be rebuilt afterwards. */
 int gm_reserve_neighbors(gm_ctx* ctx, int32_t max_neighbors);

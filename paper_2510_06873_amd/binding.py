@@ -28,7 +28,8 @@ ATOM_Q6, ATOM_NB, ATOM_C, ATOM_CN = 1, 2, 3, 4
 EXPORTS = (
     "gm_create", "gm_destroy", "gm_set_stream", "gm_build_neighbors", "gm_cv_forward", "gm_bias_eval",
     "gm_cv_backward", "gm_apply_bias_forces", "gm_deposit_hill", "gm_hills_get", "gm_hills_set", "gm_status",
-    "gm_strerror", "gm_neighbor_stats", "gm_reserve_neighbors", "gm_copy_cell_list", "gm_copy_neighbors",
+    "gm_strerror", "gm_neighbor_stats", "gm_release_rows", "gm_device_bytes", "gm_reserve_neighbors",
+    "gm_copy_cell_list", "gm_copy_neighbors",
     "gm_atom_values", "gm_version", "gm_batch_create", "gm_batch_destroy", "gm_batch_build", "gm_batch_step",
     "gm_batch_deposit", "gm_batch_values", "gm_torsions", "gm_torsion_forces", "gm_nearest_distance",
     "gm_nearest_distance_forces", "gm_lattice_virial", "gm_fes_reweight", "gm_fes_hills",
@@ -80,6 +81,8 @@ def _load() -> C.CDLL:
         "gm_strerror": ([C.c_int], C.c_char_p),
         "gm_neighbor_stats": ([vp, ip32, ip64, ip64], C.c_int),
         "gm_reserve_neighbors": ([vp, C.c_int32], C.c_int),
+        "gm_release_rows": ([vp], C.c_int),
+        "gm_device_bytes": ([vp, vp], C.c_int),
         "gm_copy_cell_list": ([vp, vp, vp, ip32], C.c_int),
         "gm_copy_neighbors": ([vp, vp, vp, ip32], C.c_int),
         "gm_atom_values": ([vp, C.c_int, vp], C.c_int),
@@ -308,6 +311,16 @@ class Pipeline:
         _check(_lib.gm_neighbor_stats(self.h, C.byref(m), C.byref(t), C.byref(cp) if cutoff_pairs else None),
                "gm_neighbor_stats")
         return (m.value, t.value, cp.value) if cutoff_pairs else (m.value, t.value)
+
+    def release_rows(self):
+        """Give the per-atom q6 rows back to the pool until the next forward."""
+        _check(_lib.gm_release_rows(self.h), "gm_release_rows")
+
+    def device_bytes(self) -> int:
+        """Bytes of device memory the context holds now."""
+        b = C.c_int64()
+        _check(_lib.gm_device_bytes(self.h, C.byref(b)), "gm_device_bytes")
+        return int(b.value)
 
     def reserve_neighbors(self, kmax: int):
         _check(_lib.gm_reserve_neighbors(self.h, int(kmax)), "gm_reserve_neighbors")
@@ -547,3 +560,4 @@ def fes_reweight(s, V, lo, hi, nbins, kBT, F=None, stream=None):
                                 lo_c, hi_c, nb_c, float(kBT), _ptr(F, total, torch.float64, "F"), _stream(stream)),
            "gm_fes_reweight")
     return F
+

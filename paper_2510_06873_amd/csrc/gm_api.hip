@@ -6,6 +6,7 @@
 
 #include <mutex>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include <cmath>
@@ -47,6 +48,8 @@ struct gm_ctx {
   double *centres = nullptr, *heights = nullptr, *bias_part = nullptr;
   int64_t* hill_count = nullptr;
 
+  std::unordered_map<void*, size_t> held;  // device allocations of the context and their sizes
+  size_t held_bytes = 0;
   bool built = false, fwd = false, bwd = false;
   const float* fwd_pos = nullptr;  // positions of the last forward pass
   int last_status = GM_OK;
@@ -117,6 +120,30 @@ template <typename P>
 void dfree(hipStream_t st, P*& p) {
   if (p) (void)hipFreeAsync(reinterpret_cast<void*>(p), st);
   p = nullptr;
+}
+
+// The same for a context's own buffers, which it counts (gm_device_bytes).
+template <typename P>
+int dalloc_c(gm_ctx* c, P** p, size_t bytes) {
+  const int rc = dalloc(c->stream, p, bytes);
+  if (rc == GM_OK) {
+    const size_t b = bytes == 0 ? 16 : bytes;
+    c->held[reinterpret_cast<void*>(*p)] = b;
+    c->held_bytes += b;
+  }
+  return rc;
+}
+
+template <typename P>
+void dfree_c(gm_ctx* c, P*& p) {
+  if (p) {
+    auto it = c->held.find(reinterpret_cast<void*>(p));
+    if (it != c->held.end()) {
+      c->held_bytes -= it->second;
+      c->held.erase(it);
+    }
+  }
+  dfree(c->stream, p);
 }
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? GM_OK : GM_ERR_HIP; }
@@ -415,42 +442,42 @@ BiasArgs make_bias(gm_ctx* c, const double* s, int deposit) {
 }
 
 void free_all(gm_ctx* c) {
-  dfree(c->stream, c->cell);
-  dfree(c->stream, c->count);
-  dfree(c->stream, c->start);
-  dfree(c->stream, c->fill);
-  dfree(c->stream, c->scan_tmp);
-  dfree(c->stream, c->perm);
-  dfree(c->stream, c->brick_H);
-  dfree(c->stream, c->brick_O);
-  dfree(c->stream, c->brick_hb);
-  dfree(c->stream, c->brick_ob);
-  dfree(c->stream, c->brick_hp);
-  dfree(c->stream, c->halo_rank);
-  dfree(c->stream, c->owned_slot);
-  dfree(c->stream, c->owned_rank);
-  dfree(c->stream, c->owned_hcell);
-  dfree(c->stream, c->nbr);
-  dfree(c->stream, c->cut);
-  dfree(c->stream, c->cnt);
-  dfree(c->stream, c->ccnt);
-  dfree(c->stream, c->order);
-  dfree(c->stream, c->err);
-  dfree(c->stream, c->stats);
-  dfree(c->stream, c->pos_s);
-  dfree(c->stream, c->qrow);
-  dfree(c->stream, c->grow);
-  dfree(c->stream, c->nb);
-  dfree(c->stream, c->cn_atom);
-  dfree(c->stream, c->part_a);
-  dfree(c->stream, c->part_b);
-  dfree(c->stream, c->s_int);
-  dfree(c->stream, c->V_int);
-  dfree(c->stream, c->dV_int);
-  dfree(c->stream, c->centres);
-  dfree(c->stream, c->heights);
-  dfree(c->stream, c->bias_part);
-  dfree(c->stream, c->hill_count);
+  dfree_c(c, c->cell);
+  dfree_c(c, c->count);
+  dfree_c(c, c->start);
+  dfree_c(c, c->fill);
+  dfree_c(c, c->scan_tmp);
+  dfree_c(c, c->perm);
+  dfree_c(c, c->brick_H);
+  dfree_c(c, c->brick_O);
+  dfree_c(c, c->brick_hb);
+  dfree_c(c, c->brick_ob);
+  dfree_c(c, c->brick_hp);
+  dfree_c(c, c->halo_rank);
+  dfree_c(c, c->owned_slot);
+  dfree_c(c, c->owned_rank);
+  dfree_c(c, c->owned_hcell);
+  dfree_c(c, c->nbr);
+  dfree_c(c, c->cut);
+  dfree_c(c, c->cnt);
+  dfree_c(c, c->ccnt);
+  dfree_c(c, c->order);
+  dfree_c(c, c->err);
+  dfree_c(c, c->stats);
+  dfree_c(c, c->pos_s);
+  dfree_c(c, c->qrow);
+  dfree_c(c, c->grow);
+  dfree_c(c, c->nb);
+  dfree_c(c, c->cn_atom);
+  dfree_c(c, c->part_a);
+  dfree_c(c, c->part_b);
+  dfree_c(c, c->s_int);
+  dfree_c(c, c->V_int);
+  dfree_c(c, c->dV_int);
+  dfree_c(c, c->centres);
+  dfree_c(c, c->heights);
+  dfree_c(c, c->bias_part);
+  dfree_c(c, c->hill_count);
 }
 
 int status_from_bits(int32_t bits) {
@@ -467,6 +494,16 @@ int status_from_bits(int32_t bits) {
   } while (0)
 
 }  // namespace
+
+// The per-atom q6 rows (q-hat, adjoint), allocated again after gm_release_rows.
+static int ensure_rows(gm_ctx* c) {
+  if (!c->has_q6 || (c->qrow && c->grow)) return GM_OK;
+  const size_t bytes = (size_t)c->n * 16 * (c->fp64 ? 8 : 4);
+  if (!c->qrow) GM_TRY(dalloc_c(c, &c->qrow, bytes));
+  if (!c->grow) GM_TRY(dalloc_c(c, &c->grow, bytes));
+  c->version++;
+  return GM_OK;
+}
 
 template <typename T>
 static int cv_forward_t(gm_ctx* c, const float* pos4, double* s_dev) {
@@ -552,30 +589,30 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   const size_t n = c->external ? 1 : (size_t)n_atoms, T = c->fp64 ? 8 : 4;  // no atom buffers for external CVs
   const size_t cap = (size_t)(params->hill_capacity > 0 ? params->hill_capacity : 1);
   int rc = GM_OK;
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->cell, n * 4);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->perm, n * 4);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->owned_slot, n * 4);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->owned_rank, n * 4);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->owned_hcell, n * 4);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->cnt, n * 4);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->ccnt, n * 4 * 4);  // up to 4 parts per atom
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->order, n * 16);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->nbr, n * (size_t)(c->kmax + 32) * 2);  // tpa sub-rows of kpart entries
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->cut, n * (size_t)(c->kmax + 32) * 2);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->pos_s, n * 4 * T);
-  if (rc == GM_OK && c->has_q6) rc = dalloc(c->stream, &c->qrow, n * 16 * T);
-  if (rc == GM_OK && c->has_q6) rc = dalloc(c->stream, &c->grow, n * 16 * T);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->nb, n * T);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->cn_atom, n * T);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->s_int, 16);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->V_int, 16);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->dV_int, 16);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->err, 16);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->stats, 32);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->centres, cap * c->dims * 8);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->heights, cap * 8);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->hill_count, 16);
-  if (rc == GM_OK) rc = dalloc(c->stream, &c->bias_part, (size_t)c->bias_blocks * 3 * 8);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->cell, n * 4);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->perm, n * 4);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->owned_slot, n * 4);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->owned_rank, n * 4);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->owned_hcell, n * 4);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->cnt, n * 4);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->ccnt, n * 4 * 4);  // up to 4 parts per atom
+  if (rc == GM_OK) rc = dalloc_c(c, &c->order, n * 16);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->nbr, n * (size_t)(c->kmax + 32) * 2);  // tpa sub-rows of kpart entries
+  if (rc == GM_OK) rc = dalloc_c(c, &c->cut, n * (size_t)(c->kmax + 32) * 2);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->pos_s, n * 4 * T);
+  if (rc == GM_OK && c->has_q6) rc = dalloc_c(c, &c->qrow, n * 16 * T);
+  if (rc == GM_OK && c->has_q6) rc = dalloc_c(c, &c->grow, n * 16 * T);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->nb, n * T);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->cn_atom, n * T);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->s_int, 16);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->V_int, 16);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->dV_int, 16);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->err, 16);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->stats, 32);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->centres, cap * c->dims * 8);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->heights, cap * 8);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->hill_count, 16);
+  if (rc == GM_OK) rc = dalloc_c(c, &c->bias_part, (size_t)c->bias_blocks * 3 * 8);
   if (rc == GM_OK) {
     hipStream_t st = c->stream;
     bool ok = hipMemsetAsync(c->err, 0, 16, st) == hipSuccess &&
@@ -614,31 +651,31 @@ static int reserve_bricks(gm_ctx* c) {
   const bool grow_b = nbk > c->nbricks_cap, grow_h = hbound > c->halo_cap, grow_p = blocks > c->blocks_cap;
   if (!(grow_b || grow_h || grow_p)) return GM_OK;
   if (grow_b) {
-    dfree(c->stream, c->brick_H);
-    dfree(c->stream, c->brick_O);
-    dfree(c->stream, c->brick_hb);
-    dfree(c->stream, c->brick_ob);
-    dfree(c->stream, c->brick_hp);
+    dfree_c(c, c->brick_H);
+    dfree_c(c, c->brick_O);
+    dfree_c(c, c->brick_hb);
+    dfree_c(c, c->brick_ob);
+    dfree_c(c, c->brick_hp);
     c->nbricks_cap = 0;
-    GM_TRY(dalloc(c->stream, &c->brick_H, (size_t)nbk * 4));
-    GM_TRY(dalloc(c->stream, &c->brick_O, (size_t)nbk * 4));
-    GM_TRY(dalloc(c->stream, &c->brick_hb, (size_t)(nbk + 1) * 4));
-    GM_TRY(dalloc(c->stream, &c->brick_ob, (size_t)(nbk + 1) * 4));
-    GM_TRY(dalloc(c->stream, &c->brick_hp, (size_t)nbk * (kHaloCells + 1) * 4));
+    GM_TRY(dalloc_c(c, &c->brick_H, (size_t)nbk * 4));
+    GM_TRY(dalloc_c(c, &c->brick_O, (size_t)nbk * 4));
+    GM_TRY(dalloc_c(c, &c->brick_hb, (size_t)(nbk + 1) * 4));
+    GM_TRY(dalloc_c(c, &c->brick_ob, (size_t)(nbk + 1) * 4));
+    GM_TRY(dalloc_c(c, &c->brick_hp, (size_t)nbk * (kHaloCells + 1) * 4));
     c->nbricks_cap = nbk;
   }
   if (grow_h) {
-    dfree(c->stream, c->halo_rank);
+    dfree_c(c, c->halo_rank);
     c->halo_cap = 0;
-    GM_TRY(dalloc(c->stream, &c->halo_rank, (size_t)hbound * 4));
+    GM_TRY(dalloc_c(c, &c->halo_rank, (size_t)hbound * 4));
     c->halo_cap = hbound;
   }
   if (grow_p) {
-    dfree(c->stream, c->part_a);
-    dfree(c->stream, c->part_b);
+    dfree_c(c, c->part_a);
+    dfree_c(c, c->part_b);
     c->blocks_cap = 0;
-    GM_TRY(dalloc(c->stream, &c->part_a, (size_t)blocks * 8));
-    GM_TRY(dalloc(c->stream, &c->part_b, (size_t)blocks * 8));
+    GM_TRY(dalloc_c(c, &c->part_a, (size_t)blocks * 8));
+    GM_TRY(dalloc_c(c, &c->part_b, (size_t)blocks * 8));
     c->blocks_cap = blocks;
   }
   return GM_OK;
@@ -657,21 +694,21 @@ int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
   }
   const int64_t ncells = (int64_t)nc[0] * nc[1] * nc[2];
   if (ncells > c->ncells_cap) {
-    dfree(c->stream, c->count);
-    dfree(c->stream, c->start);
-    dfree(c->stream, c->fill);
+    dfree_c(c, c->count);
+    dfree_c(c, c->start);
+    dfree_c(c, c->fill);
     c->ncells_cap = 0;
-    GM_TRY(dalloc(c->stream, &c->count, (size_t)ncells * 4));
-    GM_TRY(dalloc(c->stream, &c->start, (size_t)(ncells + 1) * 4));
-    GM_TRY(dalloc(c->stream, &c->fill, (size_t)ncells * 4));
+    GM_TRY(dalloc_c(c, &c->count, (size_t)ncells * 4));
+    GM_TRY(dalloc_c(c, &c->start, (size_t)(ncells + 1) * 4));
+    GM_TRY(dalloc_c(c, &c->fill, (size_t)ncells * 4));
     c->ncells_cap = ncells;
   }
   c->ncells = ncells;
   const int64_t tiles = (ncells + 1023) / 1024 + 1;
   if (tiles > c->scan_tmp_cap) {
-    dfree(c->stream, c->scan_tmp);
+    dfree_c(c, c->scan_tmp);
     c->scan_tmp_cap = 0;
-    GM_TRY(dalloc(c->stream, &c->scan_tmp, (size_t)tiles * 4));
+    GM_TRY(dalloc_c(c, &c->scan_tmp, (size_t)tiles * 4));
     c->scan_tmp_cap = tiles;
   }
   for (int a = 0; a < 3; a++) {
@@ -721,6 +758,7 @@ int gm_cv_forward(gm_ctx* c, const float* pos4, double* s_dev) {
   if (!c || !pos4 || !aligned(pos4, 16) || (s_dev && !aligned(s_dev, 8))) return GM_ERR_INVALID_ARG;
   if (!c->built) return GM_ERR_STATE;
   c->fwd = c->bwd = false;
+  GM_TRY(ensure_rows(c));
   GM_TRY(c->fp64 ? cv_forward_t<double>(c, pos4, s_dev) : cv_forward_t<float>(c, pos4, s_dev));
   c->fwd = true;
   c->fwd_pos = pos4;
@@ -812,6 +850,22 @@ int gm_status(gm_ctx* c, int sync) {
   return c->last_status;
 }
 
+int gm_release_rows(gm_ctx* c) {
+  if (!c) return GM_ERR_INVALID_ARG;
+  if (c->external) return GM_ERR_STATE;
+  if (c->qrow || c->grow) c->version++;
+  dfree_c(c, c->qrow);
+  dfree_c(c, c->grow);
+  c->fwd = c->bwd = false;
+  return GM_OK;
+}
+
+int gm_device_bytes(gm_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return GM_ERR_INVALID_ARG;
+  *bytes = (int64_t)c->held_bytes;
+  return GM_OK;
+}
+
 int gm_neighbor_stats(gm_ctx* c, int32_t* max_count, int64_t* total, int64_t* cutoff_pairs) {
   if (!c) return GM_ERR_INVALID_ARG;
   if (!c->built) return GM_ERR_STATE;
@@ -841,13 +895,13 @@ int gm_neighbor_stats(gm_ctx* c, int32_t* max_count, int64_t* total, int64_t* cu
 int gm_reserve_neighbors(gm_ctx* c, int32_t max_neighbors) {
   if (c && c->external) return GM_ERR_STATE;
   if (!c || max_neighbors < 1 || max_neighbors > 4096) return GM_ERR_INVALID_ARG;
-  dfree(c->stream, c->nbr);
-  dfree(c->stream, c->cut);
+  dfree_c(c, c->nbr);
+  dfree_c(c, c->cut);
   c->kmax = (max_neighbors + 3) / 4 * 4;
   c->built = c->fwd = c->bwd = false;
   c->version++;
-  GM_TRY(dalloc(c->stream, &c->nbr, (size_t)c->n * (c->kmax + 32) * 2));
-  return dalloc(c->stream, &c->cut, (size_t)c->n * (c->kmax + 32) * 2);
+  GM_TRY(dalloc_c(c, &c->nbr, (size_t)c->n * (c->kmax + 32) * 2));
+  return dalloc_c(c, &c->cut, (size_t)c->n * (c->kmax + 32) * 2);
 }
 
 int gm_copy_cell_list(gm_ctx* c, int32_t* perm_dev, int32_t* cell_start_dev, int32_t* ncell) {
@@ -944,6 +998,7 @@ int refresh_group(gm_batch* B, gm_batch::Group& g, bool force) {
   for (int m : g.members) {
     gm_ctx* c = B->walkers[m];
     if (!c->built) return GM_ERR_STATE;
+    GM_TRY(ensure_rows(c));
     CvArgs<T> a = make_args<T>(c);
     a.s_out = nullptr;
     a.seed = c->dV_int;

@@ -515,6 +515,47 @@ def test_autograd_2d_bias_gradient(orc, mode, precision, tol):
     assert np.all(g[:, 3] == 0)
 
 
+def test_recompute_mode_holds_no_rows_between_calls():
+    """The "recompute" autograd mode gives the per-atom q6 rows back after the
+    forward and after the backward, so the context holds 2 x 16 floats per
+    atom less between calls, and its gradient equals the stored mode's bit
+    for bit (the same kernels on the same state)."""
+    from paper_2510_06873_amd.autograd import bias_energy
+
+    wl = dict(W.WORKLOADS["wz2048"], precision="fp32")
+    d = W.structure(wl["structure"])
+    pos, box = d["pos"], d["box"]
+    n = len(pos)
+    grads, held = {}, {}
+    for mode in ("stored", "recompute"):
+        pipe = make_pipe(wl, n)
+        p4 = to_dev(W.as_float4(pos))
+        pipe.build_neighbors_checked(p4, box)
+        s0 = pipe.cv_forward(p4).cpu().numpy().copy()
+        sig = np.array(wl["sigma"])
+        pipe.hills_set(W.hill_centres(100, s0 - 2 * sig, s0 + 2 * sig, seed=19), np.full(100, wl["w0"]))
+        x = p4.clone().requires_grad_(True)
+        before = pipe.device_bytes()
+        V = bias_energy(x, pipe, mode)
+        between = pipe.device_bytes()
+        V.backward()
+        torch.cuda.synchronize()
+        held[mode] = (before, between, pipe.device_bytes())
+        grads[mode] = x.grad.cpu().numpy().copy()
+        assert pipe.status(True) == 0
+        # a forward after the release allocates the rows again
+        pipe.step(p4, torch.zeros((n, 4), dtype=torch.float32, device=dev()))
+        torch.cuda.synchronize()
+        assert pipe.status(True) == 0
+        pipe.close()
+    rows = 2 * 16 * 4 * n
+    b, m, a = held["stored"]
+    assert b == m == a
+    b_r, m_r, a_r = held["recompute"]
+    assert b_r == b and m_r == b - rows and a_r == b - rows
+    assert np.array_equal(grads["stored"], grads["recompute"])
+
+
 def test_autograd_against_finite_differences_of_the_gpu_path():
     """d V(s(x)) / dx from the autograd wrappers against central differences
     of the GPU path itself (FP64 context, 2-D CV, 2,048 atoms): coordinates
