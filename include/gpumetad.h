@@ -63,6 +63,7 @@ extern "C" {
 #define GM_ERR_HILL_CAPACITY (-6)     /* sticky: deposit into a full hill buffer */
 #define GM_ERR_NONFINITE (-7)         /* sticky: NaN/Inf position, CV, bias or force */
 #define GM_ERR_STATE (-8)             /* call order violated (see each call) */
+#define GM_ERR_TOO_LARGE (-9)         /* size beyond the fixed scratch of an allocation-free call */
 
 /* ---- collective variables ----------------------------------------------- */
 /* GM_CV_COORD   s = (1/N) sum_i sum_{j: r_ij < r_c} 1/(1 + (r_ij/r0)^6)
@@ -351,6 +352,20 @@ int gm_lattice_virial(const double* box, const double* dVdL, int32_t dims, doubl
  * comes from the stream-ordered allocator. */
 int gm_fes_reweight(const double* s_dev, const double* V_dev, int64_t T, int32_t dims, const double* lo,
                     const double* hi, const int32_t* nbins, double kBT, double* F_dev, void* hip_stream);
+
+/* gm_fes_reweight for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops that forbid allocation): the same kernels,
+ * arguments and results, with the per-workgroup partials and per-bin sums in
+ * a fixed scratch array of the library (about 530 KiB per device, held from
+ * the first call on a device until the process ends) instead of the
+ * stream-ordered allocator.  No device memory is allocated or freed.
+ * At most 65536 bins (prod nbins); a larger grid returns GM_ERR_TOO_LARGE
+ * before any device work.  Every call on one device shares its scratch:
+ * calls that overlap on a device (on different streams, or from different
+ * threads without ordering) race and give wrong results; calls ordered on one
+ * stream are safe, since each call overwrites the scratch before reading it. */
+int gm_fes_reweight_noalloc(const double* s_dev, const double* V_dev, int64_t T, int32_t dims, const double* lo,
+                            const double* hi, const int32_t* nbins, double kBT, double* F_dev, void* hip_stream);
 
 /* The free energy from the context's hills on the grid of bin centres
  * (lo_d + (i_d + 1/2) w_d): F = -V (plain metadynamics) or

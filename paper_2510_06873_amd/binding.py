@@ -19,6 +19,7 @@ GM_OK = 0
 ERRORS = {
     -1: "GM_ERR_INVALID_ARG", -2: "GM_ERR_OOM", -3: "GM_ERR_HIP", -4: "GM_ERR_BOX_TOO_SMALL",
     -5: "GM_ERR_NEIGHBOR_OVERFLOW", -6: "GM_ERR_HILL_CAPACITY", -7: "GM_ERR_NONFINITE", -8: "GM_ERR_STATE",
+    -9: "GM_ERR_TOO_LARGE",
 }
 CV_COORD, CV_Q6COUNT, CV_COORD_Q6, CV_EXTERNAL = 1, 2, 3, 4
 FP32, FP64 = 0, 1
@@ -32,7 +33,8 @@ EXPORTS = (
     "gm_copy_cell_list", "gm_copy_neighbors",
     "gm_atom_values", "gm_version", "gm_batch_create", "gm_batch_destroy", "gm_batch_build", "gm_batch_step",
     "gm_batch_deposit", "gm_batch_values", "gm_torsions", "gm_torsion_forces", "gm_nearest_distance",
-    "gm_nearest_distance_forces", "gm_lattice_virial", "gm_fes_reweight", "gm_fes_hills",
+    "gm_nearest_distance_forces", "gm_lattice_virial", "gm_fes_reweight", "gm_fes_reweight_noalloc",
+    "gm_fes_hills",
 )
 
 
@@ -101,6 +103,7 @@ def _load() -> C.CDLL:
                                        C.c_int),
         "gm_lattice_virial": ([dp, dp, C.c_int32, dp], C.c_int),
         "gm_fes_reweight": ([vp, vp, C.c_int64, C.c_int32, dp, dp, ip32, C.c_double, vp, vp], C.c_int),
+        "gm_fes_reweight_noalloc": ([vp, vp, C.c_int64, C.c_int32, dp, dp, ip32, C.c_double, vp, vp], C.c_int),
         "gm_fes_hills": ([vp, dp, dp, ip32, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -561,3 +564,20 @@ def fes_reweight(s, V, lo, hi, nbins, kBT, F=None, stream=None):
            "gm_fes_reweight")
     return F
 
+
+def fes_reweight_noalloc(s, V, lo, hi, nbins, kBT, F, stream=None):
+    """fes_reweight into the caller's F (dev double [prod nbins]) with no device
+    allocation (the library's fixed scratch; at most 65536 bins)."""
+    import torch
+
+    T = V.shape[0]
+    dims = 1 if s.dim() == 1 else s.shape[1]
+    lo_c, hi_c, nb_c = _grid(lo, hi, nbins, dims)
+    total = 1
+    for i in range(dims):
+        total *= nb_c[i]
+    _check(_lib.gm_fes_reweight_noalloc(_ptr(s, T * dims, torch.float64, "s"), _ptr(V, T, torch.float64, "V"), T,
+                                        dims, lo_c, hi_c, nb_c, float(kBT), _ptr(F, total, torch.float64, "F"),
+                                        _stream(stream)),
+           "gm_fes_reweight_noalloc")
+    return F

@@ -540,6 +540,7 @@ const char* gm_strerror(int code) {
     case GM_ERR_HILL_CAPACITY: return "hill buffer full";
     case GM_ERR_NONFINITE: return "non-finite position, CV, bias or force";
     case GM_ERR_STATE: return "call out of order";
+    case GM_ERR_TOO_LARGE: return "size beyond the fixed scratch of an allocation-free call";
     default: return "unknown error";
   }
 }
@@ -1158,13 +1159,27 @@ int gm_fes_reweight(const double* s_dev, const double* V_dev, int64_t T, int32_t
     total *= nbins[d];
   }
   if (total > kMaxFesBins) return GM_ERR_INVALID_ARG;
-  static bool lds_ready = false;
-  if (!lds_ready) {
-    allow_fes_lds();
-    lds_ready = true;
-  }
+  static std::once_flag lds_once;
+  std::call_once(lds_once, allow_fes_lds);
   return hip_rc(launch_fes_reweight(s_dev, V_dev, T, dims, lo, hi, nbins, kBT, F_dev,
                                     reinterpret_cast<hipStream_t>(hip_stream)));
+}
+
+int gm_fes_reweight_noalloc(const double* s_dev, const double* V_dev, int64_t T, int32_t dims, const double* lo,
+                            const double* hi, const int32_t* nbins, double kBT, double* F_dev, void* hip_stream) {
+  if (!s_dev || !V_dev || !F_dev || !lo || !hi || !nbins || T < 1 || (dims != 1 && dims != 2) || !(kBT > 0.0) ||
+      !aligned(s_dev, 8) || !aligned(V_dev, 8) || !aligned(F_dev, 8))
+    return GM_ERR_INVALID_ARG;
+  int64_t total = 1;
+  for (int d = 0; d < dims; d++) {
+    if (nbins[d] < 1 || !(hi[d] > lo[d]) || !isfinite(lo[d]) || !isfinite(hi[d])) return GM_ERR_INVALID_ARG;
+    total *= nbins[d];
+    if (total > kFesNoAllocMaxBins) return GM_ERR_TOO_LARGE;
+  }
+  static std::once_flag lds_once;
+  std::call_once(lds_once, allow_fes_lds);
+  return hip_rc(launch_fes_reweight_noalloc(s_dev, V_dev, T, dims, lo, hi, nbins, kBT, F_dev,
+                                            reinterpret_cast<hipStream_t>(hip_stream)));
 }
 
 int gm_fes_hills(gm_ctx* c, const double* lo, const double* hi, const int32_t* nbins, double* F_dev) {

@@ -12,6 +12,8 @@
 // These are latency-bound, so each is a small launch in FP64 on the FP32
 // coordinates.  Atom indices are device arrays; an index outside [0, n)
 // gives NaN for the CV it belongs to and no force (it is never dereferenced).
+#include <mutex>
+
 #include "gm_device.h"
 
 namespace gm {
@@ -334,8 +336,17 @@ hipError_t launch_nearest(const float4* pos, int64_t n, int32_t centre, const in
   return hipGetLastError();
 }
 
-hipError_t launch_fes_reweight(const double* s, const double* V, int64_t T, int32_t dims, const double* lo,
-                               const double* hi, const int32_t* nb, double kBT, double* F, hipStream_t st) {
+// Scratch of the allocation-free reweighting: one array per device for the
+// life of the process, shared by every call on that device (calls that
+// overlap on one device race on it).  Host code uses only the device address
+// hipGetSymbolAddress returns for it, looked up once per device.
+constexpr size_t kFesScratchDoubles = 2 * 1024 + (size_t)kFesNoAllocMaxBins;
+static __device__ __align__(256) double scratch[kFesScratchDoubles];
+
+namespace {
+
+FesArgs fes_args(const double* s, const double* V, int64_t T, int32_t dims, const double* lo, const double* hi,
+                 const int32_t* nb, double kBT, double* F) {
   FesArgs a{};
   a.s = s;
   a.V = V;
@@ -350,12 +361,20 @@ hipError_t launch_fes_reweight(const double* s, const double* V, int64_t T, int3
   }
   a.kBT = kBT;
   a.F = F;
-  const unsigned blocks = grid_for(T, kSmallBlock, 1024);
-  void* scratch = nullptr;
-  const size_t bytes = (2 * (size_t)blocks + (size_t)a.nbins) * sizeof(double);
-  hipError_t e = hipMallocAsync(&scratch, bytes, st);
-  if (e != hipSuccess) return e;
-  a.vmax_part = reinterpret_cast<double*>(scratch);
+  return a;
+}
+
+// Workgroups of the sample passes and the doubles of scratch they need: the
+// per-workgroup maxima and denominators, then the per-bin numerators.
+unsigned fes_blocks(int64_t T) { return grid_for(T, kSmallBlock, 1024); }
+size_t fes_scratch_doubles(int64_t T, int32_t nbins) { return 2 * (size_t)fes_blocks(T) + (size_t)nbins; }
+
+// The reweighting kernels over a scratch of fes_scratch_doubles(T, nbins)
+// doubles; every value of it that they read is written first (the
+// numerators by k_zero_f64, the partials by one workgroup each).
+hipError_t enqueue_fes_reweight(FesArgs a, double* scratch, hipStream_t st) {
+  const unsigned blocks = fes_blocks(a.T);
+  a.vmax_part = scratch;
   a.den_part = a.vmax_part + blocks;
   a.num = a.den_part + blocks;
   k_zero_f64<<<grid_for(a.nbins, kSmallBlock, 4096), kSmallBlock, 0, st>>>(a.num, a.nbins);
@@ -365,9 +384,53 @@ hipError_t launch_fes_reweight(const double* s, const double* V, int64_t T, int3
   else
     k_fes_accum<false><<<blocks, kSmallBlock, 0, st>>>(a, (int32_t)blocks);
   k_fes_out<<<grid_for(a.nbins, kSmallBlock, 4096), kSmallBlock, 0, st>>>(a, (int32_t)blocks);
-  e = hipGetLastError();
-  const hipError_t f = hipFreeAsync(scratch, st);
+  return hipGetLastError();
+}
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxScratchDevices] = {};
+
+hipError_t scratch_on_current_device(double** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = reinterpret_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_fes_reweight(const double* s, const double* V, int64_t T, int32_t dims, const double* lo,
+                               const double* hi, const int32_t* nb, double kBT, double* F, hipStream_t st) {
+  const FesArgs a = fes_args(s, V, T, dims, lo, hi, nb, kBT, F);
+  void* buf = nullptr;
+  hipError_t e = hipMallocAsync(&buf, fes_scratch_doubles(T, a.nbins) * sizeof(double), st);
+  if (e != hipSuccess) return e;
+  e = enqueue_fes_reweight(a, reinterpret_cast<double*>(buf), st);
+  const hipError_t f = hipFreeAsync(buf, st);
   return e != hipSuccess ? e : f;
+}
+
+hipError_t launch_fes_reweight_noalloc(const double* s, const double* V, int64_t T, int32_t dims, const double* lo,
+                                       const double* hi, const int32_t* nb, double kBT, double* F, hipStream_t st) {
+  const FesArgs a = fes_args(s, V, T, dims, lo, hi, nb, kBT, F);
+  if (a.nbins > kFesNoAllocMaxBins || fes_scratch_doubles(T, a.nbins) > kFesScratchDoubles)
+    return hipErrorInvalidValue;  // the caller checks the grid size first
+  double* buf = nullptr;
+  const hipError_t e = scratch_on_current_device(&buf);
+  if (e != hipSuccess) return e;
+  return enqueue_fes_reweight(a, buf, st);
 }
 
 hipError_t launch_fes_hills(const BiasArgs& b, const double* lo, const double* hi, const int32_t* nb, double scale,

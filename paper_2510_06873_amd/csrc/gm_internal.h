@@ -17,6 +17,7 @@ constexpr int kBuildMaxSplit = 32;      // most workgroups sharing one brick in 
 constexpr int kXcd = 8;      // workgroups are dealt to the 8 XCDs round-robin
 constexpr int32_t kMaxTorsions = 1 << 16;   // torsion forces are summed by one thread in order
 constexpr int64_t kMaxFesBins = 1 << 24;
+constexpr int32_t kFesNoAllocMaxBins = 1 << 16;  // bins of the allocation-free reweighting
 
 // Sticky device error bits (read by gm_status).
 constexpr int32_t kErrOverflow = 1;
@@ -224,6 +225,10 @@ hipError_t launch_nearest(const float4* pos, int64_t n, int32_t centre, const in
                           hipStream_t st);
 hipError_t launch_fes_reweight(const double* s, const double* V, int64_t T, int32_t dims, const double* lo,
                                const double* hi, const int32_t* nb, double kBT, double* F, hipStream_t st);
+// The same kernels over the library's fixed per-device scratch (no allocation);
+// at most kFesNoAllocMaxBins bins.
+hipError_t launch_fes_reweight_noalloc(const double* s, const double* V, int64_t T, int32_t dims, const double* lo,
+                                       const double* hi, const int32_t* nb, double kBT, double* F, hipStream_t st);
 hipError_t launch_fes_hills(const BiasArgs& b, const double* lo, const double* hi, const int32_t* nb, double scale,
                             double* F, hipStream_t st);
 void allow_fes_lds();

@@ -29,7 +29,7 @@ def test_strerror_and_version():
     import paper_2510_06873_amd as P
 
     lib = P.lib()
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         assert lib.gm_strerror(code)
     assert b"gfx950" in lib.gm_version()
 
@@ -101,6 +101,16 @@ def test_small_cv_calls_reject_bad_arguments_on_host():
     big = (C.c_int32 * 2)(1 << 13, 1 << 12)
     assert lib.gm_fes_reweight(fake, fake, 100, 2, lo, hi, big, 1.0, fake, None) == -1
     assert lib.gm_fes_hills(None, lo, hi, nb, fake) == -1
+    # the allocation-free variant: the same argument checks, then its scratch limit
+    assert lib.gm_fes_reweight_noalloc(fake, fake, 100, 3, lo, hi, nb, 1.0, fake, None) == -1
+    assert lib.gm_fes_reweight_noalloc(fake, fake, 0, 2, lo, hi, nb, 1.0, fake, None) == -1
+    assert lib.gm_fes_reweight_noalloc(None, fake, 100, 2, lo, hi, nb, 1.0, fake, None) == -1
+    assert lib.gm_fes_reweight_noalloc(fake, fake, 100, 2, hi, lo, nb, 1.0, fake, None) == -1
+    assert lib.gm_fes_reweight_noalloc(fake, fake, 100, 2, lo, hi, big, 1.0, fake, None) == -9
+    over = (C.c_int32 * 2)(257, 256)  # 65,792 bins, just past the 65,536 of the fixed scratch
+    assert lib.gm_fes_reweight_noalloc(fake, fake, 100, 2, lo, hi, over, 1.0, fake, None) == -9
+    over1 = (C.c_int32 * 1)(65537)
+    assert lib.gm_fes_reweight_noalloc(fake, fake, 100, 1, lo, hi, over1, 1.0, fake, None) == -9
 
 
 def test_lattice_virial_on_host():
