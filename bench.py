@@ -116,6 +116,7 @@ def parse():
     ap.add_argument("--serving-only", action="store_true", help="run only the serving workload")
     ap.add_argument("--autograd", action="store_true",
                     help="only time the autograd wrappers (stored vs recompute) on the 262,144-atom 2-D CV")
+    ap.add_argument("--fes", action="store_true", help="only time the free energy from hills on a grid")
     ap.add_argument("--autotune", action="store_true",
                     help="time candidate brick shapes / LDS budgets on this system first and use the fastest")
     ap.add_argument("--brick", default=None, help="force the brick shape, e.g. 3x3x4")
@@ -371,6 +372,38 @@ def autograd_bench(steps=20, warmup=3):
     return out
 
 
+def fes_bench(steps=5, warmup=1):
+    """The free energy from deposited hills on a grid (gm_fes_hills): 20,000
+    hills of a 2-D periodic CV (torsion-like, sigma 0.35 rad) on a 256 x 256
+    grid of bin centres."""
+    import math
+
+    import torch
+
+    import workloads as W
+    from paper_2510_06873_amd import CV_EXTERNAL, Params, Pipeline
+
+    prm = Params(cv_kind=CV_EXTERNAL, external_dims=2, sigma=[0.35, 0.35], w0=1.2, gamma=10.0, kBT=W.KBT_KJMOL,
+                 hill_capacity=20000, period=[2 * math.pi, 2 * math.pi])
+    pipe = Pipeline(0, prm)
+    cen = W.hill_centres(20000, [-math.pi, -math.pi], [math.pi, math.pi], seed=21)
+    pipe.hills_set(cen, np.full(len(cen), 1.2))
+    lo, hi, nb = [-math.pi, -math.pi], [math.pi, math.pi], [256, 256]
+    F = torch.empty(nb[0] * nb[1], dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        pipe.fes_hills(lo, hi, nb, F)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pipe.fes_hills(lo, hi, nb, F)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"workload": "2-D periodic CV, 20000 hills, 256 x 256 grid", "ms_per_grid": round(ms, 3),
+            "hill_evaluations_per_s": 20000 * nb[0] * nb[1] / (ms * 1e-3)}
+
+
 def serving_requests(count=256, seed=7, n_hi=200000):
     """The serving workload as library requests."""
     import workloads as W
@@ -431,6 +464,9 @@ def main():
         return
     if args.autograd:
         print(json.dumps({"autograd": autograd_bench()}), flush=True)
+        return
+    if args.fes:
+        print(json.dumps({"fes_hills": fes_bench()}), flush=True)
         return
     S = setup(args.workload, args)
     n = S["n"]

@@ -272,27 +272,44 @@ __global__ __launch_bounds__(kSmallBlock) void k_zero_f64(double* p, int64_t n) 
     p[i] = 0.0;
 }
 
-// F = -scale V on the grid of bin centres, hills in index order.
+// F = -scale V on the grid of bin centres, hills in index order.  Every
+// grid point of a workgroup reads every hill, so the hills pass through LDS
+// in tiles (one coalesced read of each hill per workgroup instead of one per
+// wave).
+constexpr int kHillTile = 512;
+
 __global__ __launch_bounds__(kSmallBlock) void k_fes_hills(BiasArgs b, double lo0, double lo1, double w0,
                                                            double w1, int32_t nb0, int32_t nbins, double scale,
                                                            double* F) {
+  __shared__ double tc0[kHillTile], tc1[kHillTile], th[kHillTile];
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nbins) return;
-  const double g0 = lo0 + ((i % nb0) + 0.5) * w0, g1 = lo1 + ((i / nb0) + 0.5) * w1;
+  const int32_t ic = i < nbins ? i : nbins - 1;  // threads past the grid help stage, store nothing
+  const double g0 = lo0 + ((ic % nb0) + 0.5) * w0, g1 = lo1 + ((ic / nb0) + 0.5) * w1;
   const int64_t K = *b.count;
+  const bool two = b.dims > 1;
   double v = 0.0;
-  for (int64_t k = 0; k < K; k++) {
-    double x = g0 - b.centres[k * b.dims];
-    if (b.period[0] > 0.0) x -= b.period[0] * rint(x / b.period[0]);
-    double arg = x * x * b.inv2s2[0];
-    if (b.dims > 1) {
-      double y = g1 - b.centres[k * b.dims + 1];
-      if (b.period[1] > 0.0) y -= b.period[1] * rint(y / b.period[1]);
-      arg += y * y * b.inv2s2[1];
+  for (int64_t t0 = 0; t0 < K; t0 += kHillTile) {
+    const int32_t n = (int32_t)(K - t0 < kHillTile ? K - t0 : kHillTile);
+    __syncthreads();  // the previous tile is no longer read
+    for (int32_t q = threadIdx.x; q < n; q += blockDim.x) {
+      tc0[q] = b.centres[(t0 + q) * b.dims];
+      tc1[q] = two ? b.centres[(t0 + q) * b.dims + 1] : 0.0;
+      th[q] = b.heights[t0 + q];
     }
-    v += b.heights[k] * exp(-arg);
+    __syncthreads();
+    for (int32_t q = 0; q < n; q++) {
+      double x = g0 - tc0[q];
+      if (b.period[0] > 0.0) x -= b.period[0] * rint(x / b.period[0]);
+      double arg = x * x * b.inv2s2[0];
+      if (two) {
+        double y = g1 - tc1[q];
+        if (b.period[1] > 0.0) y -= b.period[1] * rint(y / b.period[1]);
+        arg += y * y * b.inv2s2[1];
+      }
+      v += th[q] * exp(-arg);
+    }
   }
-  F[i] = -scale * v;
+  if (i < nbins) F[i] = -scale * v;
 }
 
 unsigned grid_for(int64_t n, int block, int64_t cap) {
