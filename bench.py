@@ -159,7 +159,7 @@ def setup(wl_name, args=None):
 
         p4 = torch.from_numpy(W.as_float4(d["pos"], d["species"])).to(torch.device("cuda", 0))
         prm, timings = autotune(p4, d["box"], prm, steps=3, limit=16)
-        tuned = {"brick": list(prm.brick), "lds_kb": prm.lds_kb, "ms_per_md_step": timings}
+        tuned = {"brick": list(prm.brick), "lds_kb": prm.lds_kb, "tpa": prm.tpa, "ms_per_md_step": timings}
         log(f"[bench] autotune: {tuned}")
     stream = torch.cuda.Stream()
     dev = torch.device("cuda", 0)

@@ -112,6 +112,8 @@ typedef struct gm_params {
                             0 = not periodic                                  */
   int32_t dims;          /* CV dimensions of a GM_CV_EXTERNAL context (1 or 2);
                             ignored by the other kinds                        */
+  int32_t tpa;           /* lanes that share one atom's neighbour rows in the
+                            CV passes (1, 2 or 4); 0 = chosen per build       */
 } gm_params;
 
 typedef struct gm_ctx gm_ctx;
@@ -199,6 +201,20 @@ int gm_hills_get(gm_ctx* ctx, double* centres, double* heights, int64_t cap, int
  * 0 <= k <= hill_capacity.  Bias sums run in hill index order, so a restored
  * history reproduces V bit for bit. */
 int gm_hills_set(gm_ctx* ctx, const double* centres, const double* heights, int64_t k);
+
+/* gm_hills_set from device arrays, enqueued and not waited for: centres_dev
+ * dev double[k*dims], heights_dev dev double[k] (read by the copies on the
+ * context's stream; keep them alive until that work has run).  For callers
+ * that admit walkers while others run on the device (a serving loop) and so
+ * must not block on a host copy. */
+int gm_hills_set_device(gm_ctx* ctx, const double* centres_dev, const double* heights_dev, int64_t k);
+
+/* Enqueue a copy of the sticky device error word (not cleared) into dst:
+ * device memory or page-locked host memory (a pageable destination makes the
+ * copy wait).  Once the stream has passed this point, gm_status_decode(*dst)
+ * gives the GM_* code gm_status would return, without a synchronisation. */
+int gm_status_copy(gm_ctx* ctx, int32_t* dst);
+int gm_status_decode(int32_t word);
 
 /* Read and clear the sticky device error word.  sync != 0 waits for the
  * stream first (synchronous); sync == 0 returns the code seen at the last

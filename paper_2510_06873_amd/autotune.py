@@ -1,11 +1,16 @@
-"""Autotuner for the brick decomposition and the LDS staging budget.
+"""Autotuner for the brick decomposition, the LDS staging budget and the
+lanes per atom.
 
 Each CV pass runs one workgroup per brick of cells and stages the brick's halo
 in LDS.  Bigger bricks re-load fewer halo atoms and fill more lanes, but need
-more LDS per workgroup (fewer workgroups per CU).  The tuner enumerates the
-brick shapes whose expected halo fits a budget, times a few pipeline steps of
-each on the real system, and keeps the fastest; results are cached by a key of
-the CV kind, precision and atoms per cell.
+more LDS per workgroup (fewer workgroups per CU); more lanes per atom split
+each neighbour row over more lanes (more parallelism per brick, shorter rows
+per lane, more combining of partial sums).  The tuner enumerates the brick
+shapes whose expected halo fits a budget with the lane counts that fit a
+workgroup, times a few pipeline steps of each on the real system, and keeps
+the fastest; results are cached by a key of the CV kind, precision, atoms per
+cell and size class (``size_class``), so that walkers of one class in a
+serving loop share a tuning.
 """
 from __future__ import annotations
 
@@ -26,12 +31,17 @@ def cells_per_axis(box: Sequence[float], r_list: float) -> Tuple[int, int, int]:
     return tuple(int(math.floor(b / r_list)) for b in box)
 
 
+# lanes of one CV-pass workgroup (FP32, FP64)
+BLOCK = {0: 512, 1: 256}
+
+
 def candidates(n_atoms: int, box: Sequence[float], params: Params, lds_kb: Sequence[int] = (40, 48, 56, 64),
-               limit: int = 10) -> List[Tuple[Tuple[int, int, int], int]]:
-    """Feasible (brick, lds_kb) pairs, most owned atoms first."""
+               limit: int = 10, tpas: Sequence[int] = (1, 2, 4)) -> List[Tuple[Tuple[int, int, int], int, int]]:
+    """Feasible (brick, lds_kb, lanes per atom) triples, most busy lanes first."""
     nc = cells_per_axis(box, params.r_c + params.skin)
     rho = n_atoms / float(np.prod(nc))
     rec = SLOT_BYTES[(params.precision, params.cv_kind != 1)]
+    blk = BLOCK[params.precision]
     out = []
     for kb in lds_kb:
         cap = (kb * 1024 - 2048) // rec
@@ -42,21 +52,32 @@ def candidates(n_atoms: int, box: Sequence[float], params: Params, lds_kb: Seque
                     own = bx * by * bz * rho
                     # slots past the LDS capacity are read from global memory,
                     # so a halo somewhat above the capacity is still a candidate
-                    if halo > 1.25 * cap or own > 1.2 * 256:
+                    if halo > 1.25 * cap:
                         continue
-                    out.append(((bx, by, bz), kb, own, halo / own))
-    # prefer many owned atoms per workgroup up to one 256-thread pass, then low halo re-loads
-    out.sort(key=lambda c: (-min(c[2], 240.0), c[3], c[1]))
+                    for tpa in tpas:
+                        # at most about one workgroup's worth of lanes
+                        if own * tpa > 1.2 * blk:
+                            continue
+                        out.append(((bx, by, bz), kb, tpa, own * tpa, halo / own))
+    # prefer many busy lanes per workgroup up to one pass over the workgroup,
+    # then low halo re-loads, fewer lanes per atom, then the smaller budget
+    out.sort(key=lambda c: (-min(c[3], 0.94 * blk), c[4], c[2], c[1]))
     seen, picked = set(), []
-    for b, kb, own, ratio in out:
-        key = (tuple(sorted(b)), kb)
+    for b, kb, tpa, lanes, ratio in out:
+        key = (tuple(sorted(b)), kb, tpa)
         if key in seen:
             continue
         seen.add(key)
-        picked.append((b, kb))
+        picked.append((b, kb, tpa))
         if len(picked) >= limit:
             break
     return picked
+
+
+def size_class(n_atoms: int) -> int:
+    """Walker size class for tuning: 0 below 4,000 atoms, 1 below 32,000,
+    2 below 200,000, 3 above."""
+    return 0 if n_atoms < 4000 else (1 if n_atoms < 32000 else (2 if n_atoms < 200000 else 3))
 
 
 def _time_steps(pipe: Pipeline, pos4, force4, box, steps: int) -> float:
@@ -80,49 +101,49 @@ def _time_steps(pipe: Pipeline, pos4, force4, box, steps: int) -> float:
 def cache_key(n_atoms: int, box: Sequence[float], params: Params) -> str:
     nc = cells_per_axis(box, params.r_c + params.skin)
     rho = n_atoms / float(np.prod(nc))
-    return f"kind{params.cv_kind}-p{params.precision}-rho{rho:.1f}-big{int(n_atoms >= 200000)}"
+    return f"kind{params.cv_kind}-p{params.precision}-rho{rho:.1f}-rc{params.r_c:g}-size{size_class(n_atoms)}"
 
 
 def autotune(pos4, box, params: Params, steps: int = 3, cache: Optional[str] = None,
              limit: int = 10) -> Tuple[Params, Dict[str, float]]:
-    """Return params with the fastest (brick, lds_kb) and the timings (ms/step)."""
+    """Return params with the fastest (brick, lds_kb, tpa) and the timings (ms/step)."""
     n = pos4.shape[0]
     key = cache_key(n, box, params)
     if cache and os.path.exists(cache):
         with open(cache) as f:
             known = json.load(f)
         if key in known:
-            b, kb = known[key]["brick"], known[key]["lds_kb"]
-            return replace(params, brick=tuple(b), lds_kb=kb), known[key]["timings"]
+            e = known[key]
+            return replace(params, brick=tuple(e["brick"]), lds_kb=e["lds_kb"], tpa=e.get("tpa", 0)), e["timings"]
     import torch
 
     timings: Dict[str, float] = {}
     best = None
     force4 = torch.zeros((n, 4), dtype=torch.float64 if params.precision == 1 else torch.float32,
                          device=pos4.device)
-    # the library's own choice (brick (0, 0, 0), default LDS budget) is always timed
-    trials = [((0, 0, 0), 0)] + [c for c in candidates(n, box, params, limit=limit)
-                                 if c != (tuple(params.brick), params.lds_kb)]
-    for b, kb in trials:
-        trial = replace(params, brick=b, lds_kb=kb)
+    # the library's own choice (brick (0, 0, 0), default LDS budget and lanes) is always timed
+    trials = [((0, 0, 0), 0, 0)] + [c for c in candidates(n, box, params, limit=limit)
+                                    if c != (tuple(params.brick), params.lds_kb, params.tpa)]
+    for b, kb, tpa in trials:
+        trial = replace(params, brick=b, lds_kb=kb, tpa=tpa)
         pipe = Pipeline(n, trial)
         pipe.hills_set(np.zeros((1, trial.dims)), np.zeros(1))
         try:
             ms = _time_steps(pipe, pos4, force4, box, steps)
         finally:
             pipe.close()
-        timings["default" if kb == 0 else f"{b[0]}x{b[1]}x{b[2]}@{kb}KiB"] = ms
+        timings["default" if kb == 0 else f"{b[0]}x{b[1]}x{b[2]}@{kb}KiB/tpa{tpa}"] = ms
         if best is None or ms < best[0]:
-            best = (ms, b, kb)
+            best = (ms, b, kb, tpa)
     if best is None:
         return params, timings
-    tuned = replace(params, brick=best[1], lds_kb=best[2])
+    tuned = replace(params, brick=best[1], lds_kb=best[2], tpa=best[3])
     if cache:
         known = {}
         if os.path.exists(cache):
             with open(cache) as f:
                 known = json.load(f)
-        known[key] = {"brick": list(best[1]), "lds_kb": best[2], "timings": timings}
+        known[key] = {"brick": list(best[1]), "lds_kb": best[2], "tpa": best[3], "timings": timings}
         tmp = cache + ".tmp"
         with open(tmp, "w") as f:
             json.dump(known, f, indent=1)

@@ -29,7 +29,8 @@ ATOM_Q6, ATOM_NB, ATOM_C, ATOM_CN = 1, 2, 3, 4
 EXPORTS = (
     "gm_create", "gm_destroy", "gm_set_stream", "gm_build_neighbors", "gm_cv_forward", "gm_bias_eval",
     "gm_cv_backward", "gm_apply_bias_forces", "gm_deposit_hill", "gm_hills_get", "gm_hills_set", "gm_status",
-    "gm_strerror", "gm_neighbor_stats", "gm_release_rows", "gm_device_bytes", "gm_reserve_neighbors",
+    "gm_strerror", "gm_neighbor_stats", "gm_release_rows", "gm_device_bytes", "gm_hills_set_device",
+    "gm_status_copy", "gm_status_decode", "gm_reserve_neighbors",
     "gm_copy_cell_list", "gm_copy_neighbors",
     "gm_atom_values", "gm_version", "gm_batch_create", "gm_batch_destroy", "gm_batch_build", "gm_batch_step",
     "gm_batch_deposit", "gm_batch_values", "gm_torsions", "gm_torsion_forces", "gm_nearest_distance",
@@ -52,7 +53,7 @@ class GmParams(C.Structure):
         ("bond_d0", C.c_double), ("bond_w", C.c_double), ("count_n0", C.c_double), ("count_w", C.c_double),
         ("sigma", C.c_double * 2), ("w0", C.c_double), ("gamma", C.c_double), ("kBT", C.c_double),
         ("hill_capacity", C.c_int64), ("max_neighbors", C.c_int32), ("brick", C.c_int32 * 3), ("lds_kb", C.c_int32),
-        ("period", C.c_double * 2), ("dims", C.c_int32),
+        ("period", C.c_double * 2), ("dims", C.c_int32), ("tpa", C.c_int32),
     ]
 
 
@@ -84,6 +85,9 @@ def _load() -> C.CDLL:
         "gm_neighbor_stats": ([vp, ip32, ip64, ip64], C.c_int),
         "gm_reserve_neighbors": ([vp, C.c_int32], C.c_int),
         "gm_release_rows": ([vp], C.c_int),
+        "gm_hills_set_device": ([vp, vp, vp, C.c_int64], C.c_int),
+        "gm_status_copy": ([vp, vp], C.c_int),
+        "gm_status_decode": ([C.c_int32], C.c_int),
         "gm_device_bytes": ([vp, vp], C.c_int),
         "gm_copy_cell_list": ([vp, vp, vp, ip32], C.c_int),
         "gm_copy_neighbors": ([vp, vp, vp, ip32], C.c_int),
@@ -163,6 +167,7 @@ class Params:
     lds_kb: int = 0                   # LDS staging budget per workgroup; 0 = auto
     period: Sequence[float] = (0.0, 0.0)  # per CV dimension; 0 = not periodic (2 pi for an angle)
     external_dims: int = 1            # CV dimensions of a CV_EXTERNAL context
+    tpa: int = 0                      # lanes per atom in the CV passes (1, 2, 4); 0 = chosen per build
 
     @property
     def dims(self) -> int:
@@ -177,7 +182,7 @@ class Params:
                         self.bond_d0, self.bond_w, self.count_n0, self.count_w, (C.c_double * 2)(*sig[:2]),
                         self.w0, self.gamma, self.kBT, self.hill_capacity, self.max_neighbors,
                         (C.c_int32 * 3)(*[int(b) for b in self.brick]), int(self.lds_kb),
-                        (C.c_double * 2)(*[float(x) for x in per[:2]]), int(self.external_dims))
+                        (C.c_double * 2)(*[float(x) for x in per[:2]]), int(self.external_dims), int(self.tpa))
 
 
 class Pipeline:
@@ -314,6 +319,25 @@ class Pipeline:
         _check(_lib.gm_neighbor_stats(self.h, C.byref(m), C.byref(t), C.byref(cp) if cutoff_pairs else None),
                "gm_neighbor_stats")
         return (m.value, t.value, cp.value) if cutoff_pairs else (m.value, t.value)
+
+    def hills_set_device(self, centres, heights):
+        """Hill history from device tensors (double [k, dims] and [k]), enqueued
+        without waiting; the tensors must stay alive until the stream has run it."""
+        k = int(heights.shape[0])
+        _check(_lib.gm_hills_set_device(self.h, _ptr(centres, k * self.dims, self.torch.float64, "centres"),
+                                        _ptr(heights, k, self.torch.float64, "heights"), k), "gm_hills_set_device")
+
+    def status_copy(self, dst):
+        """Enqueue a copy of the sticky error word into dst (int32 tensor of one
+        element, device or pinned host); decode it with status_decode once the
+        stream has passed this point."""
+        if dst.dtype != self.torch.int32 or dst.numel() < 1:
+            raise ValueError("dst must hold one int32")
+        _check(_lib.gm_status_copy(self.h, C.c_void_p(dst.data_ptr())), "gm_status_copy")
+
+    @staticmethod
+    def status_decode(word: int) -> int:
+        return _lib.gm_status_decode(int(word))
 
     def release_rows(self):
         """Give the per-atom q6 rows back to the pool until the next forward."""

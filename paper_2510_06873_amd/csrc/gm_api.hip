@@ -255,6 +255,7 @@ int validate(const gm_params* p, int64_t n) {
     if (p->brick[a] < 0 || p->brick[a] > kMaxBrick) return GM_ERR_INVALID_ARG;
   if ((p->brick[0] == 0) != (p->brick[1] == 0) || (p->brick[0] == 0) != (p->brick[2] == 0)) return GM_ERR_INVALID_ARG;
   if (p->lds_kb < 0 || p->lds_kb > 160) return GM_ERR_INVALID_ARG;
+  if (p->tpa != 0 && p->tpa != 1 && p->tpa != 2 && p->tpa != 4) return GM_ERR_INVALID_ARG;
   return GM_OK;
 }
 
@@ -345,7 +346,8 @@ void choose_bricks(gm_ctx* c, const int32_t nc[3]) {
         const double own = (double)bx * by * bz * rho;
         if (!fixed && halo * 1.05 > cap) continue;
         for (int tpa = 1; tpa <= 4; tpa *= 2) {
-          if (own * tpa > 0.92 * blk && !(fixed && tpa == 1)) continue;
+          if (c->p.tpa > 0 && tpa != c->p.tpa) continue;
+          if (own * tpa > 0.92 * blk && !(fixed && tpa == (c->p.tpa > 0 ? c->p.tpa : 1))) continue;
           const double score = own * tpa * (1.0 - 0.02 * halo / own);
           if (score > best_score) {
             best_score = score;
@@ -356,6 +358,7 @@ void choose_bricks(gm_ctx* c, const int32_t nc[3]) {
           }
         }
       }
+  if (best_score < 0.0 && c->p.tpa > 0) best_tpa = c->p.tpa;  // no brick fits the lanes: 1x1x1
   BrickGeom& g = c->bg;
   for (int a = 0; a < 3; a++) {
     g.nc[a] = nc[a];
@@ -838,6 +841,26 @@ int gm_hills_set(gm_ctx* c, const double* centres, const double* heights, int64_
   if (hipMemcpyAsync(c->hill_count, &k, 8, hipMemcpyHostToDevice, st) != hipSuccess) return GM_ERR_HIP;
   return hipStreamSynchronize(st) == hipSuccess ? GM_OK : GM_ERR_HIP;
 }
+
+int gm_hills_set_device(gm_ctx* c, const double* centres_dev, const double* heights_dev, int64_t k) {
+  if (!c || k < 0 || k > c->p.hill_capacity) return GM_ERR_INVALID_ARG;
+  if (k > 0 && (!centres_dev || !heights_dev || !aligned(centres_dev, 8) || !aligned(heights_dev, 8)))
+    return GM_ERR_INVALID_ARG;
+  hipStream_t st = c->stream;
+  if (k && hipMemcpyAsync(c->centres, centres_dev, (size_t)k * c->dims * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return GM_ERR_HIP;
+  if (k && hipMemcpyAsync(c->heights, heights_dev, (size_t)k * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return GM_ERR_HIP;
+  // the count goes in through the kernel arguments: nothing waits for the host
+  return hip_rc(launch_upload(c->hill_count, &k, 8, st));
+}
+
+int gm_status_copy(gm_ctx* c, int32_t* dst) {
+  if (!c || !dst || !aligned(dst, 4)) return GM_ERR_INVALID_ARG;
+  return hip_rc(hipMemcpyAsync(dst, c->err, 4, hipMemcpyDefault, c->stream));
+}
+
+int gm_status_decode(int32_t word) { return status_from_bits(word); }
 
 int gm_status(gm_ctx* c, int sync) {
   if (!c) return GM_ERR_INVALID_ARG;

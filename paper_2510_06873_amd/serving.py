@@ -8,13 +8,19 @@ tick boundaries while a slot and HBM budget are free, and advances every
 active walker by one step per tick with one launch per pass for all of them
 (``Batch``).  Finished walkers free their slot and memory for the queue.
 
-The batch stream never waits for the host: admissions (context creation, the
-hill and position uploads, the first build and its overflow check) run on an
-admission stream whose synchronous calls wait for admission work only, and a
-finished walker's CV, bias and forces are copied to pinned host memory behind
-an event that the loop polls; its status check and release follow once the
-event has completed.  The library's buffers come from a stream-ordered pool,
-so creating and releasing walkers does not stall the device either.
+Nothing in the loop waits for the device while walkers run.  A request's
+arrays are page-locked before the run (the server receives them into pinned
+host buffers), so an admission is a chain of enqueued work on an admission
+stream: context creation, the position, force and hill uploads and the first
+neighbour build, closed by an event.  The walker joins the batch at once; the
+batch stream waits for that event only (not for later admissions), so no
+host thread waits for the admission either.  A finished walker's CV, bias,
+forces and (sticky) error word are copied to pinned memory behind an event
+that the loop polls, and its buffers go back to the library's stream-ordered
+pool in stream order.  The error word is checked only then: a walker whose
+neighbour rows overflowed (the row width carries a margin, so this is rare)
+has its result discarded and its request queued again with rows twice as
+wide.
 
 Walkers are prepared ahead: while a tick's step runs on the device, the loop
 admits queued requests (within the HBM budget, which counts them) into a
@@ -47,10 +53,25 @@ class Request:
     forces: np.ndarray          # (N, 4) external forces (float32)
     steps: int = 100
     pace: int = 10
+    pinned: Optional[dict] = None  # page-locked copies of the arrays (pin())
 
     @property
     def n(self) -> int:
         return self.pos.shape[0]
+
+    def pin(self, torch):
+        """Page-locked host copies of the request's arrays, so that its
+        uploads are enqueued without a host wait."""
+        if self.pinned is None:
+            dims = self.params.dims
+            self.pinned = {
+                "pos": torch.from_numpy(np.ascontiguousarray(self.pos, np.float32)).pin_memory(),
+                "forces": torch.from_numpy(np.ascontiguousarray(self.forces, np.float32)).pin_memory(),
+                "centres": torch.from_numpy(np.ascontiguousarray(np.reshape(self.centres, (-1, dims)),
+                                                                 np.float64)).pin_memory(),
+                "heights": torch.from_numpy(np.ascontiguousarray(self.heights, np.float64)).pin_memory(),
+            }
+        return self.pinned
 
 
 @dataclass
@@ -87,12 +108,25 @@ def device_bytes(req: Request) -> int:
 
 
 class _Walker:
+    """An admitted request: its context, resident arrays and hill history,
+    all enqueued on `stream` (the current stream while this runs), ending
+    with the first neighbour build, a copy of the error word and `ready`."""
+
     def __init__(self, req: Request, dev, torch, stream):
         self.req = req
+        h = req.pin(torch)
         self.pipe = Pipeline(req.n, req.params, stream=stream)
-        self.pos = torch.from_numpy(req.pos).to(dev)
-        self.F = torch.from_numpy(req.forces).to(device=dev, dtype=self.pipe.fdtype)
-        self.pipe.hills_set(req.centres, req.heights)
+        self.pos = h["pos"].to(dev, non_blocking=True)
+        self.F = h["forces"].to(device=dev, non_blocking=True)
+        if self.pipe.fdtype != torch.float32:
+            self.F = self.F.to(self.pipe.fdtype)
+        self.cen = h["centres"].to(dev, non_blocking=True)
+        self.hts = h["heights"].to(dev, non_blocking=True)
+        self.pipe.hills_set_device(self.cen, self.hts)
+        self.pipe.build_neighbors(self.pos, req.box)
+        self.ready = torch.cuda.Event()
+        self.ready.record(stream)
+        self.err = torch.zeros(1, dtype=torch.int32, pin_memory=True)
         self.done = 0
         self.bytes = device_bytes(req)
 
@@ -108,8 +142,8 @@ def _finish(w: _Walker, t: float, admitted: float, keep_forces: bool) -> Result:
 
 @dataclass
 class _Retiring:
-    """Walkers that finished at one tick: host copies of their results land
-    behind ``event`` on the batch stream."""
+    """Walkers that finished at one tick: host copies of their results and
+    error words land behind ``event`` on the batch stream."""
     event: object
     walkers: list
     s: object                   # pinned (W, 2) CVs of the whole batch at that tick
@@ -137,6 +171,13 @@ def _rebuild_concurrently(walkers, stream, aux):
         stream.wait_stream(s)
 
 
+def _wider(req: Request) -> Request:
+    """The same request with neighbour rows twice as wide."""
+    from dataclasses import replace
+
+    return replace(req, params=replace(req.params, max_neighbors=2 * max(int(req.params.max_neighbors), 4)))
+
+
 def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64, keep_forces: bool = False,
                   device=None, rebuild_streams: int = 3, stage_ahead: Optional[int] = None):
     """Run the requests with continuous batching; returns (results, stats).
@@ -150,14 +191,18 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
                              f"more than the whole budget of {hbm_budget}")
     import torch
 
+    from .binding import GmError
+
     dev = device or torch.device("cuda", 0)
+    for r in requests:
+        r.pin(torch)
     stream = torch.cuda.Stream(device=dev)
     adm = torch.cuda.Stream(device=dev)
     aux = [torch.cuda.Stream(device=dev) for _ in range(rebuild_streams)]
     pending = sorted(requests, key=lambda r: r.arrival)
     active: List[_Walker] = []
     staged: List[_Walker] = []
-    stage_cap = max_slots if stage_ahead is None else int(stage_ahead)
+    stage_cap = max(max_slots if stage_ahead is None else int(stage_ahead), 1)
     retiring: List[_Retiring] = []
     admitted_at = {}
     results: List[Result] = []
@@ -170,18 +215,21 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
 
     def retire(entry: _Retiring):
         nonlocal used
-        entry.event.synchronize()
+        entry.event.synchronize()  # completed already unless the loop is idle
         t = time.perf_counter() - t0
         for w, k, F in zip(entry.walkers, entry.rows, entry.forces):
-            # the event covers every use of the walker on the batch stream, so
-            # its status read and its release go to the admission stream
-            w.pipe.set_stream(adm)
-            w.pipe.check()
+            code = Pipeline.status_decode(int(w.err[0]))
+            used -= w.bytes
+            if code == -5:  # rows overflowed: run the request again with wider rows
+                w.close()
+                pending.insert(0, _wider(w.req))
+                continue
+            if code != 0:
+                raise GmError(code, f"walker {w.req.rid}")
             results.append(Result(w.req.rid, w.req.n, w.req.arrival, admitted_at[w.req.rid], t,
                                   entry.s[k, :w.pipe.dims].numpy().copy(), float(entry.V[k]),
                                   F.numpy().copy() if F is not None else None))
-            used -= w.bytes
-            w.close()
+            w.close()  # buffers back to the pool in order on the batch stream
 
     def can_prepare():
         return (pending and pending[0].arrival <= time.perf_counter() - t0
@@ -192,7 +240,6 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
         req = pending.pop(0)
         with torch.cuda.stream(adm):
             w = _Walker(req, dev, torch, adm)
-            w.pipe.build_neighbors_checked(w.pos, req.box)  # waits for admission work only
         w.pos.record_stream(stream)
         w.F.record_stream(stream)
         used += w.bytes
@@ -203,15 +250,13 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
         while pending or active or retiring or staged:
             while retiring and retiring[0].event.query():
                 retire(retiring.pop(0))
-            # free slots take the staged walkers first, then fresh admissions
-            joined = False
+            # free slots take the staged walkers first, then fresh admissions;
+            # the batch stream waits for each one's admission work
             while len(active) < max_slots and (staged or can_prepare()):
                 w = staged.pop(0) if staged else prepare()
+                stream.wait_event(w.ready)
                 active.append(w)
-                joined = True
                 admitted_at[w.req.rid] = time.perf_counter() - t0
-            if joined:
-                stream.wait_stream(adm)
             if not active:
                 if retiring:
                     retire(retiring.pop(0))
@@ -249,6 +294,7 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
                 V_h.copy_(V, non_blocking=True)
                 forces = []
                 for w in finished:
+                    w.pipe.status_copy(w.err)
                     if keep_forces:
                         F_h = torch.empty(w.F.shape, dtype=w.F.dtype, pin_memory=True)
                         F_h.copy_(w.F, non_blocking=True)
@@ -273,6 +319,8 @@ def serve_sequential(requests: List[Request], keep_forces: bool = False, device=
     import torch
 
     dev = device or torch.device("cuda", 0)
+    for r in requests:
+        r.pin(torch)
     stream = torch.cuda.Stream(device=dev)
     results = []
     t0 = time.perf_counter()
@@ -283,7 +331,10 @@ def serve_sequential(requests: List[Request], keep_forces: bool = False, device=
                 time.sleep(req.arrival - now)
             admitted = time.perf_counter() - t0
             w = _Walker(req, dev, torch, stream)
-            w.pipe.build_neighbors_checked(w.pos, req.box)
+            if w.pipe.status(True) == -5:  # the first build overflowed its rows
+                w.close()
+                w = _Walker(_wider(req), dev, torch, stream)
+            w.pipe.check()
             for step in range(req.steps):
                 if step > 0 and step % req.pace == 0:
                     w.pipe.build_neighbors(w.pos, req.box)

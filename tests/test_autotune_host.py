@@ -38,18 +38,19 @@ def test_candidates_are_feasible_ordered_and_unique(at):
     assert 0 < len(cands) <= 8
     keys = set()
     owns = []
-    for (bx, by, bz), kb in cands:
-        assert kb in (40, 48, 56, 64)
+    for (bx, by, bz), kb, tpa in cands:
+        assert kb in (40, 48, 56, 64) and tpa in (1, 2, 4)
         assert 1 <= bx <= min(4, nc[0]) and 1 <= by <= min(4, nc[1]) and 1 <= bz <= min(4, nc[2])
         cap = (kb * 1024 - 2048) // 80  # q6 slots: position and a 16-float row
         assert (bx + 2) * (by + 2) * (bz + 2) * rho <= 1.25 * cap
         own = bx * by * bz * rho
-        assert own <= 1.2 * 256
-        owns.append(min(own, 240.0))
-        key = (tuple(sorted((bx, by, bz))), kb)
-        assert key not in keys  # one brick shape per permutation and budget
+        assert own * tpa <= 1.2 * 512  # lanes of one FP32 workgroup
+        owns.append(min(own * tpa, 0.94 * 512))
+        key = (tuple(sorted((bx, by, bz))), kb, tpa)
+        assert key not in keys  # one brick shape per permutation, budget and lane count
         keys.add(key)
-    assert owns == sorted(owns, reverse=True)  # most owned atoms first
+    assert owns == sorted(owns, reverse=True)  # most busy lanes first
+    assert len({c[2] for c in at.candidates(n, box, prm, limit=40)}) > 1  # lane counts are searched
 
 
 def test_cache_key_separates_kind_precision_and_density(at):
@@ -60,3 +61,6 @@ def test_cache_key_separates_kind_precision_and_density(at):
     k = at.cache_key(5000, box, a)
     assert k == at.cache_key(5000, box, a)
     assert len({k, at.cache_key(5000, box, b), at.cache_key(5000, box, c), at.cache_key(9000, box, a)}) == 4
+    # walkers of one size class share a key; the classes differ
+    assert at.cache_key(5000, box, a) == at.cache_key(5010, box, a)
+    assert [at.size_class(n) for n in (1000, 5000, 50000, 500000)] == [0, 1, 2, 3]

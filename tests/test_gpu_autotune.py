@@ -28,11 +28,14 @@ def test_autotune_choice_cache_and_parity(orc, tmp_path):
     tuned, timings = autotune(p4, box, prm, steps=1, cache=cache, limit=3)
     assert "default" in timings and len(timings) >= 2 and all(t > 0 for t in timings.values())
     again, timings2 = autotune(p4, box, prm, steps=1, cache=cache, limit=3)
-    assert (again.brick, again.lds_kb) == (tuned.brick, tuned.lds_kb) and timings2 == timings
+    assert (again.brick, again.lds_kb, again.tpa) == (tuned.brick, tuned.lds_kb, tuned.tpa) and timings2 == timings
     s_ref, g_ref, _ = oracle_cvs(orc, pos, box, Q6CV)
     F_in = W.external_forces(n, seed=9)
-    geoms = [tuned] + [dataclasses.replace(prm, brick=b, lds_kb=kb) for b, kb in candidates(n, box, prm, limit=3)]
+    geoms = [tuned] + [dataclasses.replace(prm, brick=b, lds_kb=kb, tpa=t)
+                       for b, kb, t in candidates(n, box, prm, limit=3)]
+    # every lane count, with the library's brick choice
+    geoms += [dataclasses.replace(prm, tpa=t) for t in (1, 2, 4)]
     for trial in geoms:
         s, F = run_step(Pipeline(n, trial), pos, sp, box, F_in, [0.37])
-        assert abs(s[0] - s_ref[0]) <= 1e-5 * abs(s_ref[0]), (trial.brick, trial.lds_kb)
-        assert rel_force_err(F[:, :3] - F_in[:, :3].astype(np.float64), -0.37 * g_ref[0]) <= 1e-4, trial.brick
+        assert abs(s[0] - s_ref[0]) <= 1e-5 * abs(s_ref[0]), (trial.brick, trial.lds_kb, trial.tpa)
+        assert rel_force_err(F[:, :3] - F_in[:, :3].astype(np.float64), -0.37 * g_ref[0]) <= 1e-4, trial.tpa
