@@ -48,6 +48,7 @@ struct gm_ctx {
   double *centres = nullptr, *heights = nullptr, *bias_part = nullptr;
   int64_t* hill_count = nullptr;
 
+  unsigned char* arena = nullptr;  // the fixed-size buffers below, carved from one allocation
   std::unordered_map<void*, size_t> held;  // device allocations of the context and their sizes
   size_t held_bytes = 0;
   bool built = false, fwd = false, bwd = false;
@@ -445,6 +446,14 @@ BiasArgs make_bias(gm_ctx* c, const double* s, int deposit) {
 }
 
 void free_all(gm_ctx* c) {
+  // buffers carved from the arena go with it
+  dfree_c(c, c->arena);
+  c->cell = c->perm = c->owned_slot = c->owned_rank = c->owned_hcell = c->cnt = c->ccnt = nullptr;
+  c->err = c->stats = nullptr;
+  c->order = nullptr;
+  c->pos_s = c->nb = c->cn_atom = nullptr;
+  c->s_int = c->V_int = c->dV_int = c->centres = c->heights = c->bias_part = nullptr;
+  c->hill_count = nullptr;
   dfree_c(c, c->cell);
   dfree_c(c, c->count);
   dfree_c(c, c->start);
@@ -592,40 +601,41 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
 
   const size_t n = c->external ? 1 : (size_t)n_atoms, T = c->fp64 ? 8 : 4;  // no atom buffers for external CVs
   const size_t cap = (size_t)(params->hill_capacity > 0 ? params->hill_capacity : 1);
-  int rc = GM_OK;
-  if (rc == GM_OK) rc = dalloc_c(c, &c->cell, n * 4);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->perm, n * 4);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->owned_slot, n * 4);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->owned_rank, n * 4);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->owned_hcell, n * 4);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->cnt, n * 4);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->ccnt, n * 4 * 4);  // up to 4 parts per atom
-  if (rc == GM_OK) rc = dalloc_c(c, &c->order, n * 16);
+  // The buffers whose size is fixed for the life of the context share one
+  // allocation (so creating and destroying a context costs one pool call
+  // each); the ones that start at zero come first and are cleared by one
+  // memset.  Each piece starts on a 256-byte boundary.
+  struct Piece {
+    void** p;
+    size_t bytes;
+  };
+  const Piece pieces[] = {
+      {(void**)&c->s_int, 16},       {(void**)&c->V_int, 16},      {(void**)&c->dV_int, 16},
+      {(void**)&c->err, 16},         {(void**)&c->stats, 32},      {(void**)&c->hill_count, 16},
+      {(void**)&c->nb, n * T},       {(void**)&c->cn_atom, n * T},  // zeroed up to here
+      {(void**)&c->cell, n * 4},     {(void**)&c->perm, n * 4},    {(void**)&c->owned_slot, n * 4},
+      {(void**)&c->owned_rank, n * 4}, {(void**)&c->owned_hcell, n * 4}, {(void**)&c->cnt, n * 4},
+      {(void**)&c->ccnt, n * 4 * 4},  // up to 4 parts per atom
+      {(void**)&c->order, n * 16},   {(void**)&c->pos_s, n * 4 * T},
+      {(void**)&c->centres, cap * c->dims * 8}, {(void**)&c->heights, cap * 8},
+      {(void**)&c->bias_part, (size_t)c->bias_blocks * 3 * 8},
+  };
+  constexpr int kZeroed = 8;
+  size_t off[sizeof(pieces) / sizeof(pieces[0])], total = 0, zero_end = 0;
+  for (size_t i = 0; i < sizeof(pieces) / sizeof(pieces[0]); i++) {
+    off[i] = total;
+    total += (pieces[i].bytes + 255) / 256 * 256;
+    if ((int)i == kZeroed - 1) zero_end = total;
+  }
+  int rc = dalloc_c(c, &c->arena, total);
+  if (rc == GM_OK) {
+    for (size_t i = 0; i < sizeof(pieces) / sizeof(pieces[0]); i++) *pieces[i].p = c->arena + off[i];
+    if (hipMemsetAsync(c->arena, 0, zero_end, c->stream) != hipSuccess) rc = GM_ERR_HIP;
+  }
   if (rc == GM_OK) rc = dalloc_c(c, &c->nbr, n * (size_t)(c->kmax + 32) * 2);  // tpa sub-rows of kpart entries
   if (rc == GM_OK) rc = dalloc_c(c, &c->cut, n * (size_t)(c->kmax + 32) * 2);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->pos_s, n * 4 * T);
   if (rc == GM_OK && c->has_q6) rc = dalloc_c(c, &c->qrow, n * 16 * T);
   if (rc == GM_OK && c->has_q6) rc = dalloc_c(c, &c->grow, n * 16 * T);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->nb, n * T);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->cn_atom, n * T);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->s_int, 16);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->V_int, 16);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->dV_int, 16);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->err, 16);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->stats, 32);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->centres, cap * c->dims * 8);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->heights, cap * 8);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->hill_count, 16);
-  if (rc == GM_OK) rc = dalloc_c(c, &c->bias_part, (size_t)c->bias_blocks * 3 * 8);
-  if (rc == GM_OK) {
-    hipStream_t st = c->stream;
-    bool ok = hipMemsetAsync(c->err, 0, 16, st) == hipSuccess &&
-              hipMemsetAsync(c->hill_count, 0, 16, st) == hipSuccess &&
-              hipMemsetAsync(c->stats, 0, 32, st) == hipSuccess && hipMemsetAsync(c->s_int, 0, 16, st) == hipSuccess &&
-              hipMemsetAsync(c->V_int, 0, 16, st) == hipSuccess && hipMemsetAsync(c->dV_int, 0, 16, st) == hipSuccess &&
-              hipMemsetAsync(c->cn_atom, 0, n * T, st) == hipSuccess && hipMemsetAsync(c->nb, 0, n * T, st) == hipSuccess;
-    if (!ok) rc = GM_ERR_HIP;
-  }
   if (rc != GM_OK) {
     free_all(c);
     delete c;
@@ -980,9 +990,13 @@ struct gm_batch {
     void *d_cv = nullptr, *d_gather = nullptr, *d_bias = nullptr, *d_dep = nullptr;
     int32_t *d_blk_cv = nullptr, *d_blk_gather = nullptr, *d_blk_bias = nullptr;
     int32_t blocks_cv = 0, blocks_gather = 0, blocks_bias = 0, cap = 0;
+    // per member: its entries of the four tables (recomputed when its version changes)
+    std::vector<std::vector<unsigned char>> e_cv, e_ga, e_bi, e_de;
+    size_t c_cv = 0, c_ga = 0, c_bi = 0, c_de = 0;  // capacities of the device tables
   };
   std::vector<Group> groups;
   bool fp64 = false;
+  void* d_vals = nullptr;  // per walker: its s, V and dV/ds buffers (pointers)
 };
 
 namespace {
@@ -1000,6 +1014,19 @@ int upload(std::vector<unsigned char>& host, void** dev, hipStream_t st) {
   return hip_rc(launch_upload(*dev, host.data(), host.size(), st));
 }
 
+// The same into a buffer of `*cap` bytes kept across calls (grown when too
+// small), so that a table whose size does not change keeps its address.
+int upload_into(std::vector<unsigned char>& host, void** dev, size_t* cap, hipStream_t st) {
+  const size_t need = (host.size() + 3) / 4 * 4;
+  if (!*dev || need > *cap) {
+    dfree(st, *dev);
+    *cap = 0;
+    GM_TRY(dalloc(st, dev, need));
+    *cap = need;
+  }
+  return hip_rc(launch_upload(*dev, host.data(), host.size(), st));
+}
+
 int upload_i32(const std::vector<int32_t>& v, int32_t** dev, hipStream_t st) {
   std::vector<unsigned char> h(reinterpret_cast<const unsigned char*>(v.data()),
                                reinterpret_cast<const unsigned char*>(v.data()) + v.size() * 4);
@@ -1009,46 +1036,65 @@ int upload_i32(const std::vector<int32_t>& v, int32_t** dev, hipStream_t st) {
   return rc;
 }
 
-// Rebuild the device tables of a group if any walker changed since the last time.
+// Bring the device tables of a group up to date: the entries of members whose
+// context changed since the last call are recomputed, and a table is uploaded
+// only if its bytes changed (into the same device buffer when it fits).
 template <typename T>
 int refresh_group(gm_batch* B, gm_batch::Group& g, bool force) {
-  bool stale = force || g.versions.size() != g.members.size();
-  for (size_t i = 0; !stale && i < g.members.size(); i++) stale = g.versions[i] != B->walkers[g.members[i]]->version;
+  const size_t W = g.members.size();
+  bool stale = force || g.versions.size() != W;
+  for (size_t i = 0; !stale && i < W; i++) stale = g.versions[i] != B->walkers[g.members[i]]->version;
   if (!stale) return GM_OK;
-  std::vector<unsigned char> cv, ga, bi, de;
+  if (g.versions.size() != W) {
+    g.versions.assign(W, -1);
+    g.e_cv.assign(W, {});
+    g.e_ga.assign(W, {});
+    g.e_bi.assign(W, {});
+    g.e_de.assign(W, {});
+  }
   std::vector<int32_t> bcv{0}, bga{0}, bbi{0};
-  g.versions.clear();
   g.cap = 0;
-  for (int m : g.members) {
-    gm_ctx* c = B->walkers[m];
+  for (size_t i = 0; i < W; i++) {
+    gm_ctx* c = B->walkers[g.members[i]];
     if (!c->built) return GM_ERR_STATE;
     GM_TRY(ensure_rows(c));
-    CvArgs<T> a = make_args<T>(c);
-    a.s_out = nullptr;
-    a.seed = c->dV_int;
-    a.mode = 0;
-    a.out4 = B->force[m];
-    append(cv, a);
-    GatherArgs gth = gather_args(c, B->pos[m]);
-    append(ga, gth);
-    BiasArgs ev = make_bias(c, c->s_int, 0);
-    ev.V_out = c->V_int;
-    ev.dV_out = c->dV_int;
-    append(bi, ev);
-    append(de, make_bias(c, c->s_int, 1));
+    if (force || g.versions[i] != c->version) {
+      CvArgs<T> a = make_args<T>(c);
+      a.s_out = nullptr;
+      a.seed = c->dV_int;
+      a.mode = 0;
+      a.out4 = B->force[g.members[i]];
+      g.e_cv[i].clear();
+      append(g.e_cv[i], a);
+      g.e_ga[i].clear();
+      append(g.e_ga[i], gather_args(c, B->pos[g.members[i]]));
+      BiasArgs ev = make_bias(c, c->s_int, 0);
+      ev.V_out = c->V_int;
+      ev.dV_out = c->dV_int;
+      g.e_bi[i].clear();
+      append(g.e_bi[i], ev);
+      g.e_de[i].clear();
+      append(g.e_de[i], make_bias(c, c->s_int, 1));
+      g.versions[i] = c->version;
+    }
     bcv.push_back(bcv.back() + c->bg.blocks);
     bga.push_back(bga.back() + (int32_t)((c->n + kBlock - 1) / kBlock));
     bbi.push_back(bbi.back() + c->bias_blocks);
     g.cap = c->bg.cap > g.cap ? c->bg.cap : g.cap;
-    g.versions.push_back(c->version);
   }
+  auto join = [](const std::vector<std::vector<unsigned char>>& parts) {
+    std::vector<unsigned char> out;
+    for (const auto& p : parts) out.insert(out.end(), p.begin(), p.end());
+    return out;
+  };
+  std::vector<unsigned char> cv = join(g.e_cv), ga = join(g.e_ga), bi = join(g.e_bi), de = join(g.e_de);
   g.blocks_cv = bcv.back();
   g.blocks_gather = bga.back();
   g.blocks_bias = bbi.back();
-  if (force || cv != g.h_cv) GM_TRY(upload(cv, &g.d_cv, B->stream));
-  if (force || ga != g.h_gather) GM_TRY(upload(ga, &g.d_gather, B->stream));
-  if (force || bi != g.h_bias) GM_TRY(upload(bi, &g.d_bias, B->stream));
-  if (force || de != g.h_dep) GM_TRY(upload(de, &g.d_dep, B->stream));
+  if (force || cv != g.h_cv) GM_TRY(upload_into(cv, &g.d_cv, &g.c_cv, B->stream));
+  if (force || ga != g.h_gather) GM_TRY(upload_into(ga, &g.d_gather, &g.c_ga, B->stream));
+  if (force || bi != g.h_bias) GM_TRY(upload_into(bi, &g.d_bias, &g.c_bi, B->stream));
+  if (force || de != g.h_dep) GM_TRY(upload_into(de, &g.d_dep, &g.c_de, B->stream));
   if (force || bcv != g.h_blk_cv) GM_TRY(upload_i32(bcv, &g.d_blk_cv, B->stream));
   if (force || bga != g.h_blk_gather) GM_TRY(upload_i32(bga, &g.d_blk_gather, B->stream));
   if (force || bbi != g.h_blk_bias) GM_TRY(upload_i32(bbi, &g.d_blk_bias, B->stream));
@@ -1095,6 +1141,7 @@ int batch_step_t(gm_batch* B) {
 }
 
 void free_batch(gm_batch* B) {
+  dfree(B->stream, B->d_vals);
   for (auto& g : B->groups) {
     dfree(B->stream, g.d_cv);
     dfree(B->stream, g.d_gather);
@@ -1254,6 +1301,20 @@ int gm_batch_create(gm_batch** out, gm_ctx* const* walkers, int32_t count, const
     c->stream = B->stream;
     c->version++;
   }
+  {
+    std::vector<unsigned char> vals;
+    for (gm_ctx* c : B->walkers) {
+      append(vals, c->s_int);
+      append(vals, c->V_int);
+      append(vals, c->dV_int);
+    }
+    const int rc = upload(vals, &B->d_vals, B->stream);
+    if (rc != GM_OK) {
+      free_batch(B);
+      delete B;
+      return rc;
+    }
+  }
   *out = B;
   return GM_OK;
 }
@@ -1293,16 +1354,9 @@ int gm_batch_values(gm_batch* B, double* s_dev, double* V_dev, double* dVds_dev)
   if (!B) return GM_ERR_INVALID_ARG;
   if ((s_dev && !aligned(s_dev, 8)) || (V_dev && !aligned(V_dev, 8)) || (dVds_dev && !aligned(dVds_dev, 8)))
     return GM_ERR_INVALID_ARG;
-  for (size_t i = 0; i < B->walkers.size(); i++) {
-    gm_ctx* c = B->walkers[i];
-    if (s_dev && hipMemcpyAsync(s_dev + 2 * i, c->s_int, 16, hipMemcpyDeviceToDevice, B->stream) != hipSuccess)
-      return GM_ERR_HIP;
-    if (V_dev && hipMemcpyAsync(V_dev + i, c->V_int, 8, hipMemcpyDeviceToDevice, B->stream) != hipSuccess)
-      return GM_ERR_HIP;
-    if (dVds_dev && hipMemcpyAsync(dVds_dev + 2 * i, c->dV_int, 16, hipMemcpyDeviceToDevice, B->stream) != hipSuccess)
-      return GM_ERR_HIP;
-  }
-  return GM_OK;
+  if (!s_dev && !V_dev && !dVds_dev) return GM_OK;
+  return hip_rc(launch_batch_values(reinterpret_cast<const double* const*>(B->d_vals), (int32_t)B->walkers.size(),
+                                    s_dev, V_dev, dVds_dev, B->stream));
 }
 
 }  // extern "C"

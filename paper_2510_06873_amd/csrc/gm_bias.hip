@@ -108,6 +108,31 @@ hipError_t launch_bias_batch(const BiasArgs* tab, const int32_t* blk_start, int3
   return hipGetLastError();
 }
 
+// CV, bias and dV/ds of every walker of a batch into dense arrays (second
+// columns hold the contexts' zero second entries for 1-D CVs).
+__global__ __launch_bounds__(kBlock) void k_batch_values(const double* const* __restrict__ tab, int32_t W, double* s,
+                                                         double* V, double* dV) {
+  const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  const double* sw = tab[3 * w];
+  const double* vw = tab[3 * w + 1];
+  const double* dw = tab[3 * w + 2];
+  if (s) {
+    s[2 * w] = sw[0];
+    s[2 * w + 1] = sw[1];
+  }
+  if (V) V[w] = vw[0];
+  if (dV) {
+    dV[2 * w] = dw[0];
+    dV[2 * w + 1] = dw[1];
+  }
+}
+
+hipError_t launch_batch_values(const double* const* tab, int32_t W, double* s, double* V, double* dV, hipStream_t st) {
+  k_batch_values<<<(unsigned)((W + kBlock - 1) / kBlock), kBlock, 0, st>>>(tab, W, s, V, dV);
+  return hipGetLastError();
+}
+
 hipError_t launch_bias(const BiasArgs& a, int blocks, hipStream_t st) {
   k_bias<<<(unsigned)blocks, kBlock, 0, st>>>(a);
   k_bias_finish<<<1, kBlock, 0, st>>>(a, blocks);

@@ -385,6 +385,54 @@ __device__ __forceinline__ void rank_owned(const CvArgs<T>& a, const Brick& k, i
     a.order[k.ob + start[key] + hist[w * kRankBins + key] + below] = make_int4(t, sr[2 * t], sr[2 * t + 1], 0);
 }
 
+
+// With two lanes per atom, the lanes even out the in-cutoff rows they write:
+// the lane with more entries hands its newest ones (still in its shift
+// register) to the other, which appends them, so the two parts differ by at
+// most one entry (up to 8 move).  The lanes of a wave then walk rows of more
+// equal length in passes 2-4 (the parts of one atom are filtered from
+// interleaved halves of its list, which split the pairs inside r_c unevenly).
+// Both lanes of the pair call this.
+__device__ __forceinline__ uint32_t slot_at(const uint4& b, int p) {
+  const uint32_t w = p < 2 ? b.x : (p < 4 ? b.y : (p < 6 ? b.z : b.w));
+  return (w >> ((p & 1) * 16)) & 0xffffu;
+}
+
+__device__ __forceinline__ void balance_pair(SlotWriter& wr) {
+  const int32_t mine = wr.n;
+  const int32_t other = quad_xor<kQuadXor1>(mine);
+  uint4 ob;
+  ob.x = (uint32_t)quad_xor<kQuadXor1>((int32_t)wr.buf.x);
+  ob.y = (uint32_t)quad_xor<kQuadXor1>((int32_t)wr.buf.y);
+  ob.z = (uint32_t)quad_xor<kQuadXor1>((int32_t)wr.buf.z);
+  ob.w = (uint32_t)quad_xor<kQuadXor1>((int32_t)wr.buf.w);
+  const int32_t give = min(mine > other + 1 ? (mine - other) >> 1 : 0, 8);
+  const int32_t take = min(other > mine + 1 ? (other - mine) >> 1 : 0, 8);
+  for (int32_t e = 8 - take; e < 8; e++) wr.push((int32_t)slot_at(ob, e));
+  if (give == 0) {
+    wr.flush();
+    return;
+  }
+  // drop the newest `give`: the partial chunk, if it is still the current one,
+  // is written with the kept entries only
+  const int32_t keep = mine - give;
+  const int32_t r = keep & 7;
+  if (r != 0 && (keep >> 3) == (mine >> 3)) {
+    uint4 b = wr.buf;
+    for (int k = mine & 7; k < 8; k++) {  // the chunk's entries down to the front
+      b.x = __builtin_amdgcn_alignbit(b.y, b.x, 16);
+      b.y = __builtin_amdgcn_alignbit(b.z, b.y, 16);
+      b.z = __builtin_amdgcn_alignbit(b.w, b.z, 16);
+      b.w = b.w >> 16;
+    }
+    uint32_t w[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+      if (q >= r) w[q >> 1] &= (q & 1) ? 0x0000ffffu : 0xffff0000u;
+    wr.dst[keep >> 3] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  wr.n = keep;
+}
 // --------------------------------------------------------------------------
 // Pass 1
 // --------------------------------------------------------------------------
@@ -409,7 +457,10 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
       T dx, dy, dz;
       if (pair_vec<WRAP>(pi, pj, a, dx, dy, dz) < a.rc2) wr.push(s);
     });
-    wr.flush();
+    if (TPA == 2)
+      balance_pair(wr);
+    else
+      wr.flush();
     const int32_t nc = wr.n;
     a.ccnt[(int64_t)(k.ob + o) * TPA + part] = nc;
     int32_t longest = nc;

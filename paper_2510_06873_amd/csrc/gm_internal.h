@@ -216,6 +216,8 @@ hipError_t launch_neighbor_ranks(const uint16_t* nbr, const int32_t* cnt, const 
                                  const BrickIndex& bi, int32_t kmax, int32_t* nbr_out, int32_t* cnt_out,
                                  hipStream_t st);
 hipError_t launch_bias(const BiasArgs& a, int blocks, hipStream_t st);
+// tab[3 w + 0..2]: the CV, bias and dV/ds buffers of walker w (2, 1, 2 doubles).
+hipError_t launch_batch_values(const double* const* tab, int32_t W, double* s, double* V, double* dV, hipStream_t st);
 hipError_t launch_torsions(const float4* pos, int64_t n, const int32_t* quads, int32_t count, const double* box,
                            double* phi, hipStream_t st);
 hipError_t launch_torsion_forces(const float4* pos, int64_t n, const int32_t* quads, int32_t count, const double* box,

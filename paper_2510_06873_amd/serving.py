@@ -288,10 +288,12 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
             finished = [w for w in active if w.done >= w.req.steps]
             if finished:
                 s, V = batch.values()
-                s_h = torch.empty(s.shape, dtype=s.dtype, pin_memory=True)
-                V_h = torch.empty(V.shape, dtype=V.dtype, pin_memory=True)
-                s_h.copy_(s, non_blocking=True)
-                V_h.copy_(V, non_blocking=True)
+                # pinned buffers of one size for every retirement, so that the
+                # host allocator serves them from its cache
+                s_h = torch.empty((max_slots, 2), dtype=s.dtype, pin_memory=True)
+                V_h = torch.empty((max_slots,), dtype=V.dtype, pin_memory=True)
+                s_h[:s.shape[0]].copy_(s, non_blocking=True)
+                V_h[:V.shape[0]].copy_(V, non_blocking=True)
                 forces = []
                 for w in finished:
                     w.pipe.status_copy(w.err)
@@ -331,9 +333,9 @@ def serve_sequential(requests: List[Request], keep_forces: bool = False, device=
                 time.sleep(req.arrival - now)
             admitted = time.perf_counter() - t0
             w = _Walker(req, dev, torch, stream)
-            if w.pipe.status(True) == -5:  # the first build overflowed its rows
+            while w.pipe.status(True) == -5:  # the first build overflowed its rows
                 w.close()
-                w = _Walker(_wider(req), dev, torch, stream)
+                w = _Walker(_wider(w.req), dev, torch, stream)
             w.pipe.check()
             for step in range(req.steps):
                 if step > 0 and step % req.pace == 0:

@@ -42,3 +42,28 @@ def test_admission_respects_budget():
     rb, sb = serve_batched(reqs, hbm_budget=budget, max_slots=8)
     assert len(rb) == len(reqs)
     assert sb["peak_bytes"] <= budget
+
+
+def test_overflowing_walker_is_run_again_with_wider_rows():
+    """A request whose neighbour rows are far too narrow (8 entries for some
+    17-30 neighbours): the batched loop finds the overflow in the error word
+    at retirement, discards that result and runs the request again with rows
+    twice as wide until it fits; the results equal the sequential run's."""
+    from dataclasses import replace
+
+    from paper_2510_06873_amd.serving import serve_batched, serve_sequential
+
+    reqs = requests(5)
+    for r in reqs:
+        r.steps = 12
+    narrow = [i for i, r in enumerate(reqs) if r.params.cv_kind == 2][:1] or [0]
+    for i in narrow:
+        reqs[i].params = replace(reqs[i].params, max_neighbors=8)
+    rb, _ = serve_batched(reqs, hbm_budget=64 << 30, max_slots=3, keep_forces=True)
+    rs, _ = serve_sequential(reqs, keep_forces=True)
+    assert sorted(r.rid for r in rb) == sorted(r.rid for r in reqs)
+    alone = {r.rid: r for r in rs}
+    for r in rb:
+        a = alone[r.rid]
+        assert np.array_equal(r.s, a.s) and r.V == a.V, r.rid
+        assert np.array_equal(r.forces, a.forces), r.rid
