@@ -291,6 +291,17 @@ int gm_batch_create(gm_batch** out, gm_ctx* const* walkers, int32_t count, const
  * walkers stay bound to that stream. */
 int gm_batch_destroy(gm_batch* batch);
 
+/* Replace the batch's members (same argument meaning as gm_batch_create;
+ * count may be 0).  The batch keeps its device tables (grown only when a
+ * larger member list needs it) and the table entries of the walkers that
+ * stay, so a serving loop whose active set changes every few steps neither
+ * frees nor reallocates device memory per change.  A context must be removed
+ * by an update (or the batch destroyed) before the context is destroyed.
+ * On GM_ERR_INVALID_ARG the batch keeps its previous members.  Every member
+ * must have the batch's precision; new members are bound to its stream. */
+int gm_batch_update(gm_batch* batch, gm_ctx* const* walkers, int32_t count, const float* const* pos4,
+                    void* const* force4);
+
 /* Rebuild every walker's cell and neighbour lists; boxes: host double[count][3]. */
 int gm_batch_build(gm_batch* batch, const double* boxes);
 
@@ -301,6 +312,13 @@ int gm_batch_step(gm_batch* batch);
 
 /* Deposit one well-tempered hill per walker at its current CV value. */
 int gm_batch_deposit(gm_batch* batch);
+
+/* The same for some walkers only (each deposit as gm_deposit_hill would make
+ * it, bitwise): which = host array of count distinct member indices (the
+ * order of the last create or update); two launches per 64 walkers.
+ * GM_ERR_INVALID_ARG for an index out of range or repeated, GM_ERR_STATE for a
+ * walker not yet stepped (no CV value to deposit at). */
+int gm_batch_deposit_some(gm_batch* batch, const int32_t* which, int32_t count);
 
 /* Copy each walker's CV, bias and bias gradient of its last step (enqueued):
  * s_dev dev double[count][2] (second column 0 for 1-D CVs), V_dev dev

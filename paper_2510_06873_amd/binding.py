@@ -32,8 +32,9 @@ EXPORTS = (
     "gm_strerror", "gm_neighbor_stats", "gm_release_rows", "gm_device_bytes", "gm_hills_set_device",
     "gm_status_copy", "gm_status_decode", "gm_reserve_neighbors",
     "gm_copy_cell_list", "gm_copy_neighbors",
-    "gm_atom_values", "gm_version", "gm_batch_create", "gm_batch_destroy", "gm_batch_build", "gm_batch_step",
-    "gm_batch_deposit", "gm_batch_values", "gm_torsions", "gm_torsion_forces", "gm_nearest_distance",
+    "gm_atom_values", "gm_version", "gm_batch_create", "gm_batch_destroy", "gm_batch_update", "gm_batch_build",
+    "gm_batch_step", "gm_batch_deposit", "gm_batch_deposit_some", "gm_batch_values", "gm_torsions",
+    "gm_torsion_forces", "gm_nearest_distance",
     "gm_nearest_distance_forces", "gm_lattice_virial", "gm_fes_reweight", "gm_fes_reweight_noalloc",
     "gm_fes_hills",
 )
@@ -96,9 +97,12 @@ def _load() -> C.CDLL:
         "gm_batch_create": ([C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p),
                              C.POINTER(C.c_void_p), vp], C.c_int),
         "gm_batch_destroy": ([vp], C.c_int),
+        "gm_batch_update": ([vp, C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)],
+                            C.c_int),
         "gm_batch_build": ([vp, dp], C.c_int),
         "gm_batch_step": ([vp], C.c_int),
         "gm_batch_deposit": ([vp], C.c_int),
+        "gm_batch_deposit_some": ([vp, C.POINTER(C.c_int32), C.c_int32], C.c_int),
         "gm_batch_values": ([vp, vp, vp, vp], C.c_int),
         "gm_torsions": ([vp, C.c_int64, vp, C.c_int32, dp, vp, vp], C.c_int),
         "gm_torsion_forces": ([vp, C.c_int64, vp, C.c_int32, dp, vp, vp, C.c_int32, vp], C.c_int),
@@ -419,31 +423,57 @@ class Batch:
         import torch
 
         self.torch = torch
-        self.pipes = list(pipes)
-        self.pos4 = list(pos4)
-        self.force4 = list(force4)
-        w = len(self.pipes)
-        if not (len(self.pos4) == len(self.force4) == w) or w == 0:
-            raise ValueError("one position and one force array per walker")
-        for p, x, f in zip(self.pipes, self.pos4, self.force4):
-            p._pos(x)
-            p._arr4(f, "force4")
+        pipes, pos4, force4 = self._members(pipes, pos4, force4)
+        if not pipes:
+            raise ValueError("a batch starts with at least one walker")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        hs = (C.c_void_p * w)(*[p.h.value for p in self.pipes])
-        xs = (C.c_void_p * w)(*[x.data_ptr() for x in self.pos4])
-        fs = (C.c_void_p * w)(*[f.data_ptr() for f in self.force4])
+        w, hs, xs, fs = self._tables(pipes, pos4, force4)
         h = C.c_void_p()
         _check(_lib.gm_batch_create(C.byref(h), hs, w, xs, fs, C.c_void_p(self.stream.cuda_stream)), "gm_batch_create")
         self.h = h
-        for p in self.pipes:
-            p.stream = self.stream
-        dev = self.pos4[0].device
-        self.s = torch.zeros((w, 2), dtype=torch.float64, device=dev)
-        self.V = torch.zeros(w, dtype=torch.float64, device=dev)
-        self.dVds = torch.zeros((w, 2), dtype=torch.float64, device=dev)
+        self._adopt(pipes, pos4, force4)
         cur = torch.cuda.current_stream()
         if cur != self.stream:
             self.stream.wait_stream(cur)
+
+    @staticmethod
+    def _members(pipes, pos4, force4):
+        pipes, pos4, force4 = list(pipes), list(pos4), list(force4)
+        if not (len(pos4) == len(force4) == len(pipes)):
+            raise ValueError("one position and one force array per walker")
+        for p, x, f in zip(pipes, pos4, force4):
+            p._pos(x)
+            p._arr4(f, "force4")
+        return pipes, pos4, force4
+
+    @staticmethod
+    def _tables(pipes, pos4, force4):
+        w = len(pipes)
+        hs = (C.c_void_p * max(w, 1))(*[p.h.value for p in pipes])
+        xs = (C.c_void_p * max(w, 1))(*[x.data_ptr() for x in pos4])
+        fs = (C.c_void_p * max(w, 1))(*[f.data_ptr() for f in force4])
+        return w, hs, xs, fs
+
+    def _adopt(self, pipes, pos4, force4):
+        torch = self.torch
+        self.pipes, self.pos4, self.force4 = pipes, pos4, force4
+        for p in pipes:
+            p.stream = self.stream
+        w = len(pipes)
+        if getattr(self, "s", None) is None or self.s.shape[0] != w:
+            dev = pos4[0].device if pos4 else self.s.device
+            self.s = torch.zeros((w, 2), dtype=torch.float64, device=dev)
+            self.V = torch.zeros(w, dtype=torch.float64, device=dev)
+            self.dVds = torch.zeros((w, 2), dtype=torch.float64, device=dev)
+
+    def update(self, pipes, pos4, force4):
+        """Replace the members (gm_batch_update): the device tables and the
+        entries of walkers that stay are kept.  Remove a walker this way
+        before closing its Pipeline."""
+        pipes, pos4, force4 = self._members(pipes, pos4, force4)
+        w, hs, xs, fs = self._tables(pipes, pos4, force4)
+        _check(_lib.gm_batch_update(self.h, hs, w, xs, fs), "gm_batch_update")
+        self._adopt(pipes, pos4, force4)
 
     def close(self):
         if getattr(self, "h", None):
@@ -467,8 +497,13 @@ class Batch:
         for p in self.pipes:
             p.generation += 1
 
-    def deposit(self):
-        _check(_lib.gm_batch_deposit(self.h), "gm_batch_deposit")
+    def deposit(self, which=None):
+        """One hill per walker, or only for the member indices in `which`."""
+        if which is None:
+            _check(_lib.gm_batch_deposit(self.h), "gm_batch_deposit")
+            return
+        idx = (C.c_int32 * max(len(which), 1))(*[int(i) for i in which])
+        _check(_lib.gm_batch_deposit_some(self.h, idx, len(which)), "gm_batch_deposit_some")
 
     def values(self):
         """(s[W, 2], V[W]) device tensors, enqueued on the batch stream."""

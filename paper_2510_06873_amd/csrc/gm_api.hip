@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <unordered_map>
@@ -35,7 +36,6 @@ struct gm_ctx {
   // cell list (canonical sorted order)
   int32_t *cell = nullptr, *count = nullptr, *start = nullptr, *fill = nullptr, *perm = nullptr;
   int32_t* scan_tmp = nullptr;  // tile sums of the prefix scans
-  int64_t scan_tmp_cap = 0;
   // bricks
   int32_t *brick_H = nullptr, *brick_O = nullptr, *brick_hb = nullptr, *brick_ob = nullptr, *brick_hp = nullptr;
   int32_t *halo_rank = nullptr, *owned_slot = nullptr, *owned_rank = nullptr, *owned_hcell = nullptr;
@@ -49,12 +49,17 @@ struct gm_ctx {
   int64_t* hill_count = nullptr;
 
   unsigned char* arena = nullptr;  // the fixed-size buffers below, carved from one allocation
+  // buffers that grow or go together, one allocation each: the neighbour and
+  // in-cutoff rows; the q-hat and adjoint rows; the cell tables (counts,
+  // starts, fill, scan tiles); the brick tables and per-workgroup partials
+  unsigned char *rows_blk = nullptr, *qg_blk = nullptr, *cells_blk = nullptr, *bricks_blk = nullptr;
   std::unordered_map<void*, size_t> held;  // device allocations of the context and their sizes
   size_t held_bytes = 0;
   bool built = false, fwd = false, bwd = false;
   const float* fwd_pos = nullptr;  // positions of the last forward pass
   int last_status = GM_OK;
   int64_t version = 0;  // bumped whenever the kernel arguments may change
+  uint64_t serial = 0;  // unique per context created in this process
   int lds_budget = 0;   // bytes of dynamic LDS for the staged halo
   YCoef<float> ycf;
   YCoef<double> ycd;
@@ -145,6 +150,37 @@ void dfree_c(gm_ctx* c, P*& p) {
     }
   }
   dfree(c->stream, p);
+}
+
+#define GM_TRY(x)               \
+  do {                          \
+    int _rc = (x);              \
+    if (_rc != GM_OK) return _rc; \
+  } while (0)
+
+// Pieces of one allocation, each on a 256-byte boundary: *p of every piece
+// points into *base.  zero_pieces: how many leading pieces are cleared (in
+// stream order).  Fewer allocations make creating and destroying a context
+// cheaper (a stream-ordered free costs tens of microseconds of host time).
+struct Piece {
+  void** p;
+  size_t bytes;
+};
+
+int carve(gm_ctx* c, unsigned char** base, const Piece* pieces, int k, int zero_pieces = 0) {
+  size_t total = 0, zero_end = 0;
+  for (int i = 0; i < k; i++) {
+    total += (pieces[i].bytes + 255) / 256 * 256;
+    if (i == zero_pieces - 1) zero_end = total;
+  }
+  GM_TRY(dalloc_c(c, base, total));
+  size_t off = 0;
+  for (int i = 0; i < k; i++) {
+    *pieces[i].p = *base + off;
+    off += (pieces[i].bytes + 255) / 256 * 256;
+  }
+  if (zero_end && hipMemsetAsync(*base, 0, zero_end, c->stream) != hipSuccess) return GM_ERR_HIP;
+  return GM_OK;
 }
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? GM_OK : GM_ERR_HIP; }
@@ -446,50 +482,32 @@ BiasArgs make_bias(gm_ctx* c, const double* s, int deposit) {
 }
 
 void free_all(gm_ctx* c) {
-  // buffers carved from the arena go with it
+  // every device buffer of a context is carved from one of these
   dfree_c(c, c->arena);
+  dfree_c(c, c->rows_blk);
+  dfree_c(c, c->qg_blk);
+  dfree_c(c, c->cells_blk);
+  dfree_c(c, c->bricks_blk);
+  dfree_c(c, c->halo_rank);
   c->cell = c->perm = c->owned_slot = c->owned_rank = c->owned_hcell = c->cnt = c->ccnt = nullptr;
   c->err = c->stats = nullptr;
   c->order = nullptr;
-  c->pos_s = c->nb = c->cn_atom = nullptr;
+  c->pos_s = c->nb = c->cn_atom = c->qrow = c->grow = nullptr;
   c->s_int = c->V_int = c->dV_int = c->centres = c->heights = c->bias_part = nullptr;
+  c->part_a = c->part_b = nullptr;
   c->hill_count = nullptr;
-  dfree_c(c, c->cell);
-  dfree_c(c, c->count);
-  dfree_c(c, c->start);
-  dfree_c(c, c->fill);
-  dfree_c(c, c->scan_tmp);
-  dfree_c(c, c->perm);
-  dfree_c(c, c->brick_H);
-  dfree_c(c, c->brick_O);
-  dfree_c(c, c->brick_hb);
-  dfree_c(c, c->brick_ob);
-  dfree_c(c, c->brick_hp);
-  dfree_c(c, c->halo_rank);
-  dfree_c(c, c->owned_slot);
-  dfree_c(c, c->owned_rank);
-  dfree_c(c, c->owned_hcell);
-  dfree_c(c, c->nbr);
-  dfree_c(c, c->cut);
-  dfree_c(c, c->cnt);
-  dfree_c(c, c->ccnt);
-  dfree_c(c, c->order);
-  dfree_c(c, c->err);
-  dfree_c(c, c->stats);
-  dfree_c(c, c->pos_s);
-  dfree_c(c, c->qrow);
-  dfree_c(c, c->grow);
-  dfree_c(c, c->nb);
-  dfree_c(c, c->cn_atom);
-  dfree_c(c, c->part_a);
-  dfree_c(c, c->part_b);
-  dfree_c(c, c->s_int);
-  dfree_c(c, c->V_int);
-  dfree_c(c, c->dV_int);
-  dfree_c(c, c->centres);
-  dfree_c(c, c->heights);
-  dfree_c(c, c->bias_part);
-  dfree_c(c, c->hill_count);
+  c->nbr = c->cut = nullptr;
+  c->count = c->start = c->fill = c->scan_tmp = nullptr;
+  c->brick_H = c->brick_O = c->brick_hb = c->brick_ob = c->brick_hp = nullptr;
+}
+
+// The neighbour and in-cutoff rows (tpa sub-rows of kpart entries each).
+int alloc_rows(gm_ctx* c) {
+  dfree_c(c, c->rows_blk);
+  c->nbr = c->cut = nullptr;
+  const size_t bytes = (size_t)c->n * (size_t)(c->kmax + 32) * 2;
+  const Piece pieces[] = {{(void**)&c->nbr, bytes}, {(void**)&c->cut, bytes}};
+  return carve(c, &c->rows_blk, pieces, 2);
 }
 
 int status_from_bits(int32_t bits) {
@@ -499,22 +517,16 @@ int status_from_bits(int32_t bits) {
   return GM_OK;
 }
 
-#define GM_TRY(x)               \
-  do {                          \
-    int _rc = (x);              \
-    if (_rc != GM_OK) return _rc; \
-  } while (0)
 
 }  // namespace
 
 // The per-atom q6 rows (q-hat, adjoint), allocated again after gm_release_rows.
 static int ensure_rows(gm_ctx* c) {
-  if (!c->has_q6 || (c->qrow && c->grow)) return GM_OK;
+  if (!c->has_q6 || c->qg_blk) return GM_OK;
   const size_t bytes = (size_t)c->n * 16 * (c->fp64 ? 8 : 4);
-  if (!c->qrow) GM_TRY(dalloc_c(c, &c->qrow, bytes));
-  if (!c->grow) GM_TRY(dalloc_c(c, &c->grow, bytes));
+  const Piece pieces[] = {{&c->qrow, bytes}, {&c->grow, bytes}};
   c->version++;
-  return GM_OK;
+  return carve(c, &c->qg_blk, pieces, 2);
 }
 
 template <typename T>
@@ -561,8 +573,10 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   if (!out) return GM_ERR_INVALID_ARG;
   *out = nullptr;
   GM_TRY(validate(params, n_atoms));
+  static std::atomic<uint64_t> next_serial{1};
   gm_ctx* c = new (std::nothrow) gm_ctx();
   if (!c) return GM_ERR_OOM;
+  c->serial = next_serial.fetch_add(1);
   c->p = *params;
   c->n = n_atoms;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -602,13 +616,8 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
   const size_t n = c->external ? 1 : (size_t)n_atoms, T = c->fp64 ? 8 : 4;  // no atom buffers for external CVs
   const size_t cap = (size_t)(params->hill_capacity > 0 ? params->hill_capacity : 1);
   // The buffers whose size is fixed for the life of the context share one
-  // allocation (so creating and destroying a context costs one pool call
-  // each); the ones that start at zero come first and are cleared by one
-  // memset.  Each piece starts on a 256-byte boundary.
-  struct Piece {
-    void** p;
-    size_t bytes;
-  };
+  // allocation; the ones that start at zero come first and are cleared by
+  // one memset.
   const Piece pieces[] = {
       {(void**)&c->s_int, 16},       {(void**)&c->V_int, 16},      {(void**)&c->dV_int, 16},
       {(void**)&c->err, 16},         {(void**)&c->stats, 32},      {(void**)&c->hill_count, 16},
@@ -620,22 +629,9 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
       {(void**)&c->centres, cap * c->dims * 8}, {(void**)&c->heights, cap * 8},
       {(void**)&c->bias_part, (size_t)c->bias_blocks * 3 * 8},
   };
-  constexpr int kZeroed = 8;
-  size_t off[sizeof(pieces) / sizeof(pieces[0])], total = 0, zero_end = 0;
-  for (size_t i = 0; i < sizeof(pieces) / sizeof(pieces[0]); i++) {
-    off[i] = total;
-    total += (pieces[i].bytes + 255) / 256 * 256;
-    if ((int)i == kZeroed - 1) zero_end = total;
-  }
-  int rc = dalloc_c(c, &c->arena, total);
-  if (rc == GM_OK) {
-    for (size_t i = 0; i < sizeof(pieces) / sizeof(pieces[0]); i++) *pieces[i].p = c->arena + off[i];
-    if (hipMemsetAsync(c->arena, 0, zero_end, c->stream) != hipSuccess) rc = GM_ERR_HIP;
-  }
-  if (rc == GM_OK) rc = dalloc_c(c, &c->nbr, n * (size_t)(c->kmax + 32) * 2);  // tpa sub-rows of kpart entries
-  if (rc == GM_OK) rc = dalloc_c(c, &c->cut, n * (size_t)(c->kmax + 32) * 2);
-  if (rc == GM_OK && c->has_q6) rc = dalloc_c(c, &c->qrow, n * 16 * T);
-  if (rc == GM_OK && c->has_q6) rc = dalloc_c(c, &c->grow, n * 16 * T);
+  int rc = carve(c, &c->arena, pieces, (int)(sizeof(pieces) / sizeof(pieces[0])), 8);
+  if (rc == GM_OK && !c->external) rc = alloc_rows(c);
+  if (rc == GM_OK && c->has_q6) rc = ensure_rows(c);
   if (rc != GM_OK) {
     free_all(c);
     delete c;
@@ -662,35 +658,27 @@ int gm_set_stream(gm_ctx* c, void* hip_stream) {
 // (Re)allocate the brick tables for the current brick geometry.
 static int reserve_bricks(gm_ctx* c) {
   const int64_t nbk = c->bg.nbricks, blocks = c->bg.blocks, hbound = halo_bound(c);
-  const bool grow_b = nbk > c->nbricks_cap, grow_h = hbound > c->halo_cap, grow_p = blocks > c->blocks_cap;
-  if (!(grow_b || grow_h || grow_p)) return GM_OK;
+  const bool grow_b = nbk > c->nbricks_cap || blocks > c->blocks_cap, grow_h = hbound > c->halo_cap;
   if (grow_b) {
-    dfree_c(c, c->brick_H);
-    dfree_c(c, c->brick_O);
-    dfree_c(c, c->brick_hb);
-    dfree_c(c, c->brick_ob);
-    dfree_c(c, c->brick_hp);
-    c->nbricks_cap = 0;
-    GM_TRY(dalloc_c(c, &c->brick_H, (size_t)nbk * 4));
-    GM_TRY(dalloc_c(c, &c->brick_O, (size_t)nbk * 4));
-    GM_TRY(dalloc_c(c, &c->brick_hb, (size_t)(nbk + 1) * 4));
-    GM_TRY(dalloc_c(c, &c->brick_ob, (size_t)(nbk + 1) * 4));
-    GM_TRY(dalloc_c(c, &c->brick_hp, (size_t)nbk * (kHaloCells + 1) * 4));
-    c->nbricks_cap = nbk;
+    dfree_c(c, c->bricks_blk);
+    const int64_t nb = nbk > c->nbricks_cap ? nbk : c->nbricks_cap;
+    const int64_t np = blocks > c->blocks_cap ? blocks : c->blocks_cap;
+    c->nbricks_cap = c->blocks_cap = 0;
+    const Piece pieces[] = {
+        {(void**)&c->brick_H, (size_t)nb * 4},        {(void**)&c->brick_O, (size_t)nb * 4},
+        {(void**)&c->brick_hb, (size_t)(nb + 1) * 4}, {(void**)&c->brick_ob, (size_t)(nb + 1) * 4},
+        {(void**)&c->brick_hp, (size_t)nb * (kHaloCells + 1) * 4},
+        {(void**)&c->part_a, (size_t)np * 8},          {(void**)&c->part_b, (size_t)np * 8},
+    };
+    GM_TRY(carve(c, &c->bricks_blk, pieces, 7));
+    c->nbricks_cap = nb;
+    c->blocks_cap = np;
   }
   if (grow_h) {
     dfree_c(c, c->halo_rank);
     c->halo_cap = 0;
     GM_TRY(dalloc_c(c, &c->halo_rank, (size_t)hbound * 4));
     c->halo_cap = hbound;
-  }
-  if (grow_p) {
-    dfree_c(c, c->part_a);
-    dfree_c(c, c->part_b);
-    c->blocks_cap = 0;
-    GM_TRY(dalloc_c(c, &c->part_a, (size_t)blocks * 8));
-    GM_TRY(dalloc_c(c, &c->part_b, (size_t)blocks * 8));
-    c->blocks_cap = blocks;
   }
   return GM_OK;
 }
@@ -708,23 +696,15 @@ int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
   }
   const int64_t ncells = (int64_t)nc[0] * nc[1] * nc[2];
   if (ncells > c->ncells_cap) {
-    dfree_c(c, c->count);
-    dfree_c(c, c->start);
-    dfree_c(c, c->fill);
+    dfree_c(c, c->cells_blk);
     c->ncells_cap = 0;
-    GM_TRY(dalloc_c(c, &c->count, (size_t)ncells * 4));
-    GM_TRY(dalloc_c(c, &c->start, (size_t)(ncells + 1) * 4));
-    GM_TRY(dalloc_c(c, &c->fill, (size_t)ncells * 4));
+    const int64_t tiles = (ncells + 1023) / 1024 + 1;  // tile sums of the prefix scans
+    const Piece pieces[] = {{(void**)&c->count, (size_t)ncells * 4}, {(void**)&c->start, (size_t)(ncells + 1) * 4},
+                            {(void**)&c->fill, (size_t)ncells * 4}, {(void**)&c->scan_tmp, (size_t)tiles * 4}};
+    GM_TRY(carve(c, &c->cells_blk, pieces, 4));
     c->ncells_cap = ncells;
   }
   c->ncells = ncells;
-  const int64_t tiles = (ncells + 1023) / 1024 + 1;
-  if (tiles > c->scan_tmp_cap) {
-    dfree_c(c, c->scan_tmp);
-    c->scan_tmp_cap = 0;
-    GM_TRY(dalloc_c(c, &c->scan_tmp, (size_t)tiles * 4));
-    c->scan_tmp_cap = tiles;
-  }
   for (int a = 0; a < 3; a++) {
     c->box[a] = box[a];
     c->geom.L[a] = box[a];
@@ -887,9 +867,9 @@ int gm_status(gm_ctx* c, int sync) {
 int gm_release_rows(gm_ctx* c) {
   if (!c) return GM_ERR_INVALID_ARG;
   if (c->external) return GM_ERR_STATE;
-  if (c->qrow || c->grow) c->version++;
-  dfree_c(c, c->qrow);
-  dfree_c(c, c->grow);
+  if (c->qg_blk) c->version++;
+  dfree_c(c, c->qg_blk);
+  c->qrow = c->grow = nullptr;
   c->fwd = c->bwd = false;
   return GM_OK;
 }
@@ -929,13 +909,10 @@ int gm_neighbor_stats(gm_ctx* c, int32_t* max_count, int64_t* total, int64_t* cu
 int gm_reserve_neighbors(gm_ctx* c, int32_t max_neighbors) {
   if (c && c->external) return GM_ERR_STATE;
   if (!c || max_neighbors < 1 || max_neighbors > 4096) return GM_ERR_INVALID_ARG;
-  dfree_c(c, c->nbr);
-  dfree_c(c, c->cut);
   c->kmax = (max_neighbors + 3) / 4 * 4;
   c->built = c->fwd = c->bwd = false;
   c->version++;
-  GM_TRY(dalloc_c(c, &c->nbr, (size_t)c->n * (c->kmax + 32) * 2));
-  return dalloc_c(c, &c->cut, (size_t)c->n * (c->kmax + 32) * 2);
+  return alloc_rows(c);
 }
 
 int gm_copy_cell_list(gm_ctx* c, int32_t* perm_dev, int32_t* cell_start_dev, int32_t* ncell) {
@@ -981,22 +958,33 @@ struct gm_batch {
   std::vector<gm_ctx*> walkers;
   std::vector<const float*> pos;
   std::vector<void*> force;
+  // A member's entries of the four argument tables, kept while it stays in
+  // the batch and recomputed when its context changes (version) or when the
+  // entry belongs to another context at the same address (serial).
+  struct Entry {
+    uint64_t serial = 0;
+    int64_t version = -1;
+    const float* pos = nullptr;
+    void* force = nullptr;
+    std::vector<unsigned char> cv, ga, bi, de;
+  };
   struct Group {
     int kind = 0;                 // GM_CV_*
     std::vector<int> members;     // indices into walkers
-    std::vector<int64_t> versions;
+    bool dirty = true;            // members changed since the tables were built
+    std::unordered_map<const gm_ctx*, Entry> cache;
     std::vector<unsigned char> h_cv, h_gather, h_bias, h_dep;  // host images of the tables
     std::vector<int32_t> h_blk_cv, h_blk_gather, h_blk_bias;
     void *d_cv = nullptr, *d_gather = nullptr, *d_bias = nullptr, *d_dep = nullptr;
-    int32_t *d_blk_cv = nullptr, *d_blk_gather = nullptr, *d_blk_bias = nullptr;
+    void *d_blk_cv = nullptr, *d_blk_gather = nullptr, *d_blk_bias = nullptr;
     int32_t blocks_cv = 0, blocks_gather = 0, blocks_bias = 0, cap = 0;
-    // per member: its entries of the four tables (recomputed when its version changes)
-    std::vector<std::vector<unsigned char>> e_cv, e_ga, e_bi, e_de;
-    size_t c_cv = 0, c_ga = 0, c_bi = 0, c_de = 0;  // capacities of the device tables
+    // capacities of the device tables (kept across membership changes)
+    size_t c_cv = 0, c_ga = 0, c_bi = 0, c_de = 0, c_bcv = 0, c_bga = 0, c_bbi = 0;
   };
-  std::vector<Group> groups;
+  std::vector<Group> groups;      // one per CV kind that ever had a member
   bool fp64 = false;
   void* d_vals = nullptr;  // per walker: its s, V and dV/ds buffers (pointers)
+  size_t c_vals = 0;
 };
 
 namespace {
@@ -1007,15 +995,9 @@ void append(std::vector<unsigned char>& v, const T& x) {
   v.insert(v.end(), p, p + sizeof(T));
 }
 
-// Replace a device table with a host image, in stream order on st (no wait).
-int upload(std::vector<unsigned char>& host, void** dev, hipStream_t st) {
-  dfree(st, *dev);
-  GM_TRY(dalloc(st, dev, (host.size() + 3) / 4 * 4));
-  return hip_rc(launch_upload(*dev, host.data(), host.size(), st));
-}
-
-// The same into a buffer of `*cap` bytes kept across calls (grown when too
-// small), so that a table whose size does not change keeps its address.
+// Replace a device table with a host image, in stream order on st (no wait),
+// in a buffer of `*cap` bytes kept across calls (grown when too small), so
+// that a table whose size does not change keeps its address.
 int upload_into(std::vector<unsigned char>& host, void** dev, size_t* cap, hipStream_t st) {
   const size_t need = (host.size() + 3) / 4 * 4;
   if (!*dev || need > *cap) {
@@ -1027,13 +1009,10 @@ int upload_into(std::vector<unsigned char>& host, void** dev, size_t* cap, hipSt
   return hip_rc(launch_upload(*dev, host.data(), host.size(), st));
 }
 
-int upload_i32(const std::vector<int32_t>& v, int32_t** dev, hipStream_t st) {
+int upload_into_i32(const std::vector<int32_t>& v, void** dev, size_t* cap, hipStream_t st) {
   std::vector<unsigned char> h(reinterpret_cast<const unsigned char*>(v.data()),
                                reinterpret_cast<const unsigned char*>(v.data()) + v.size() * 4);
-  void* d = *dev;
-  int rc = upload(h, &d, st);
-  *dev = reinterpret_cast<int32_t*>(d);
-  return rc;
+  return upload_into(h, dev, cap, st);
 }
 
 // Bring the device tables of a group up to date: the entries of members whose
@@ -1042,52 +1021,55 @@ int upload_i32(const std::vector<int32_t>& v, int32_t** dev, hipStream_t st) {
 template <typename T>
 int refresh_group(gm_batch* B, gm_batch::Group& g, bool force) {
   const size_t W = g.members.size();
-  bool stale = force || g.versions.size() != W;
-  for (size_t i = 0; !stale && i < W; i++) stale = g.versions[i] != B->walkers[g.members[i]]->version;
-  if (!stale) return GM_OK;
-  if (g.versions.size() != W) {
-    g.versions.assign(W, -1);
-    g.e_cv.assign(W, {});
-    g.e_ga.assign(W, {});
-    g.e_bi.assign(W, {});
-    g.e_de.assign(W, {});
+  bool stale = force || g.dirty;
+  for (size_t i = 0; !stale && i < W; i++) {
+    const int m = g.members[i];
+    const gm_ctx* c = B->walkers[m];
+    auto it = g.cache.find(c);
+    stale = it == g.cache.end() || it->second.serial != c->serial || it->second.version != c->version ||
+            it->second.pos != B->pos[m] || it->second.force != B->force[m];
   }
+  if (!stale) return GM_OK;
   std::vector<int32_t> bcv{0}, bga{0}, bbi{0};
+  std::vector<unsigned char> cv, ga, bi, de;
   g.cap = 0;
   for (size_t i = 0; i < W; i++) {
-    gm_ctx* c = B->walkers[g.members[i]];
+    const int m = g.members[i];
+    gm_ctx* c = B->walkers[m];
     if (!c->built) return GM_ERR_STATE;
     GM_TRY(ensure_rows(c));
-    if (force || g.versions[i] != c->version) {
+    gm_batch::Entry& e = g.cache[c];
+    if (force || e.serial != c->serial || e.version != c->version || e.pos != B->pos[m] || e.force != B->force[m]) {
       CvArgs<T> a = make_args<T>(c);
       a.s_out = nullptr;
       a.seed = c->dV_int;
       a.mode = 0;
-      a.out4 = B->force[g.members[i]];
-      g.e_cv[i].clear();
-      append(g.e_cv[i], a);
-      g.e_ga[i].clear();
-      append(g.e_ga[i], gather_args(c, B->pos[g.members[i]]));
+      a.out4 = B->force[m];
+      e.cv.clear();
+      append(e.cv, a);
+      e.ga.clear();
+      append(e.ga, gather_args(c, B->pos[m]));
       BiasArgs ev = make_bias(c, c->s_int, 0);
       ev.V_out = c->V_int;
       ev.dV_out = c->dV_int;
-      g.e_bi[i].clear();
-      append(g.e_bi[i], ev);
-      g.e_de[i].clear();
-      append(g.e_de[i], make_bias(c, c->s_int, 1));
-      g.versions[i] = c->version;
+      e.bi.clear();
+      append(e.bi, ev);
+      e.de.clear();
+      append(e.de, make_bias(c, c->s_int, 1));
+      e.serial = c->serial;
+      e.version = c->version;
+      e.pos = B->pos[m];
+      e.force = B->force[m];
     }
+    cv.insert(cv.end(), e.cv.begin(), e.cv.end());
+    ga.insert(ga.end(), e.ga.begin(), e.ga.end());
+    bi.insert(bi.end(), e.bi.begin(), e.bi.end());
+    de.insert(de.end(), e.de.begin(), e.de.end());
     bcv.push_back(bcv.back() + c->bg.blocks);
     bga.push_back(bga.back() + (int32_t)((c->n + kBlock - 1) / kBlock));
     bbi.push_back(bbi.back() + c->bias_blocks);
     g.cap = c->bg.cap > g.cap ? c->bg.cap : g.cap;
   }
-  auto join = [](const std::vector<std::vector<unsigned char>>& parts) {
-    std::vector<unsigned char> out;
-    for (const auto& p : parts) out.insert(out.end(), p.begin(), p.end());
-    return out;
-  };
-  std::vector<unsigned char> cv = join(g.e_cv), ga = join(g.e_ga), bi = join(g.e_bi), de = join(g.e_de);
   g.blocks_cv = bcv.back();
   g.blocks_gather = bga.back();
   g.blocks_bias = bbi.back();
@@ -1095,9 +1077,9 @@ int refresh_group(gm_batch* B, gm_batch::Group& g, bool force) {
   if (force || ga != g.h_gather) GM_TRY(upload_into(ga, &g.d_gather, &g.c_ga, B->stream));
   if (force || bi != g.h_bias) GM_TRY(upload_into(bi, &g.d_bias, &g.c_bi, B->stream));
   if (force || de != g.h_dep) GM_TRY(upload_into(de, &g.d_dep, &g.c_de, B->stream));
-  if (force || bcv != g.h_blk_cv) GM_TRY(upload_i32(bcv, &g.d_blk_cv, B->stream));
-  if (force || bga != g.h_blk_gather) GM_TRY(upload_i32(bga, &g.d_blk_gather, B->stream));
-  if (force || bbi != g.h_blk_bias) GM_TRY(upload_i32(bbi, &g.d_blk_bias, B->stream));
+  if (force || bcv != g.h_blk_cv) GM_TRY(upload_into_i32(bcv, &g.d_blk_cv, &g.c_bcv, B->stream));
+  if (force || bga != g.h_blk_gather) GM_TRY(upload_into_i32(bga, &g.d_blk_gather, &g.c_bga, B->stream));
+  if (force || bbi != g.h_blk_bias) GM_TRY(upload_into_i32(bbi, &g.d_blk_bias, &g.c_bbi, B->stream));
   g.h_blk_cv.swap(bcv);
   g.h_blk_gather.swap(bga);
   g.h_blk_bias.swap(bbi);
@@ -1105,31 +1087,35 @@ int refresh_group(gm_batch* B, gm_batch::Group& g, bool force) {
   g.h_gather.swap(ga);
   g.h_bias.swap(bi);
   g.h_dep.swap(de);
+  g.dirty = false;
   return GM_OK;
 }
 
 template <typename T>
 int batch_step_t(gm_batch* B) {
   for (auto& g : B->groups) {
+    if (g.members.empty()) continue;
     GM_TRY(refresh_group<T>(B, g, false));
     const int32_t W = (int32_t)g.members.size();
     auto* tab = reinterpret_cast<const CvArgs<T>*>(g.d_cv);
+    const auto* bcv = static_cast<const int32_t*>(g.d_blk_cv);
     const bool q6 = g.kind != GM_CV_COORD, cn = g.kind != GM_CV_Q6COUNT;
     hipStream_t st = B->stream;
-    GM_TRY(hip_rc(launch_gather_batch<T>(reinterpret_cast<const GatherArgs*>(g.d_gather), g.d_blk_gather, W,
-                                         g.blocks_gather, st)));
+    GM_TRY(hip_rc(launch_gather_batch<T>(reinterpret_cast<const GatherArgs*>(g.d_gather),
+                                         static_cast<const int32_t*>(g.d_blk_gather), W, g.blocks_gather, st)));
     if (q6) {
-      GM_TRY(hip_rc(launch_pass_batch<T>(1, cn, true, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
-      GM_TRY(hip_rc(launch_pass_batch<T>(2, cn, true, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
+      GM_TRY(hip_rc(launch_pass_batch<T>(1, cn, true, tab, bcv, W, g.blocks_cv, g.cap, st)));
+      GM_TRY(hip_rc(launch_pass_batch<T>(2, cn, true, tab, bcv, W, g.blocks_cv, g.cap, st)));
     } else {
-      GM_TRY(hip_rc(launch_pass_batch<T>(5, true, false, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
+      GM_TRY(hip_rc(launch_pass_batch<T>(5, true, false, tab, bcv, W, g.blocks_cv, g.cap, st)));
     }
-    GM_TRY(hip_rc(launch_bias_batch(reinterpret_cast<const BiasArgs*>(g.d_bias), g.d_blk_bias, W, g.blocks_bias, st)));
+    GM_TRY(hip_rc(launch_bias_batch(reinterpret_cast<const BiasArgs*>(g.d_bias),
+                                    static_cast<const int32_t*>(g.d_blk_bias), W, g.blocks_bias, st)));
     if (q6) {
-      GM_TRY(hip_rc(launch_pass_batch<T>(3, cn, true, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
-      GM_TRY(hip_rc(launch_pass_batch<T>(4, cn, true, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
+      GM_TRY(hip_rc(launch_pass_batch<T>(3, cn, true, tab, bcv, W, g.blocks_cv, g.cap, st)));
+      GM_TRY(hip_rc(launch_pass_batch<T>(4, cn, true, tab, bcv, W, g.blocks_cv, g.cap, st)));
     } else {
-      GM_TRY(hip_rc(launch_pass_batch<T>(6, true, false, tab, g.d_blk_cv, W, g.blocks_cv, g.cap, st)));
+      GM_TRY(hip_rc(launch_pass_batch<T>(6, true, false, tab, bcv, W, g.blocks_cv, g.cap, st)));
     }
     for (int m : g.members) {
       gm_ctx* c = B->walkers[m];
@@ -1264,59 +1250,92 @@ int gm_fes_hills(gm_ctx* c, const double* lo, const double* hi, const int32_t* n
   return hip_rc(launch_fes_hills(make_bias(c, nullptr, 0), lo, hi, nbins, scale, F_dev, c->stream));
 }
 
+}  // extern "C"
+
+namespace {
+
+// Validate a member list (distinct internal-CV contexts of the batch's
+// precision, aligned arrays) and make it the batch's: groups by CV kind keep
+// their device tables and the cached entries of members that stay; walkers
+// are bound to the batch stream; the table of value pointers is re-uploaded.
+int set_members(gm_batch* B, gm_ctx* const* walkers, int32_t count, const float* const* pos4, void* const* force4) {
+  const size_t vs = B->fp64 ? 32 : 16;
+  for (int32_t i = 0; i < count; i++) {
+    gm_ctx* c = walkers[i];
+    if (!c || c->external || !pos4[i] || !force4[i] || c->fp64 != B->fp64 || !aligned(pos4[i], 16) ||
+        !aligned(force4[i], vs))
+      return GM_ERR_INVALID_ARG;
+    for (int32_t j = 0; j < i; j++)
+      if (walkers[j] == c) return GM_ERR_INVALID_ARG;
+  }
+  B->walkers.assign(walkers, walkers + count);
+  B->pos.assign(pos4, pos4 + count);
+  B->force.assign(force4, force4 + count);
+  for (int kind = GM_CV_COORD; kind <= GM_CV_COORD_Q6; kind++) {
+    gm_batch::Group* g = nullptr;
+    for (auto& h : B->groups)
+      if (h.kind == kind) g = &h;
+    std::vector<int> members;
+    for (int32_t i = 0; i < count; i++)
+      if (walkers[i]->p.cv_kind == kind) members.push_back(i);
+    if (!g) {
+      if (members.empty()) continue;
+      B->groups.emplace_back();
+      g = &B->groups.back();
+      g->kind = kind;
+    }
+    g->members.swap(members);
+    g->dirty = true;
+    // forget the entries of contexts that left (they may be destroyed, and a
+    // new context may later take the same address)
+    for (auto it = g->cache.begin(); it != g->cache.end();) {
+      bool stays = false;
+      for (int m : g->members) stays = stays || B->walkers[m] == it->first;
+      it = stays ? std::next(it) : g->cache.erase(it);
+    }
+  }
+  for (gm_ctx* c : B->walkers)
+    if (c->stream != B->stream) {
+      c->stream = B->stream;
+      c->version++;
+    }
+  if (count == 0) return GM_OK;
+  std::vector<unsigned char> vals;
+  for (gm_ctx* c : B->walkers) {
+    append(vals, c->s_int);
+    append(vals, c->V_int);
+    append(vals, c->dV_int);
+  }
+  return upload_into(vals, &B->d_vals, &B->c_vals, B->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
 int gm_batch_create(gm_batch** out, gm_ctx* const* walkers, int32_t count, const float* const* pos4,
                     void* const* force4, void* hip_stream) {
   if (!out) return GM_ERR_INVALID_ARG;
   *out = nullptr;
-  if (!walkers || !pos4 || !force4 || count < 1) return GM_ERR_INVALID_ARG;
+  if (!walkers || !pos4 || !force4 || count < 1 || !walkers[0]) return GM_ERR_INVALID_ARG;
   gm_batch* B = new (std::nothrow) gm_batch();
   if (!B) return GM_ERR_OOM;
   B->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  B->fp64 = walkers[0] && walkers[0]->fp64;
-  for (int32_t i = 0; i < count; i++) {
-    gm_ctx* c = walkers[i];
-    const size_t vs = B->fp64 ? 32 : 16;
-    if (!c || c->external || !pos4[i] || !force4[i] || c->fp64 != B->fp64 || !aligned(pos4[i], 16) ||
-        !aligned(force4[i], vs)) {
-      delete B;
-      return GM_ERR_INVALID_ARG;
-    }
-    for (int32_t j = 0; j < i; j++)
-      if (walkers[j] == c) {
-        delete B;
-        return GM_ERR_INVALID_ARG;
-      }
-    B->walkers.push_back(c);
-    B->pos.push_back(pos4[i]);
-    B->force.push_back(force4[i]);
-  }
-  for (int kind = GM_CV_COORD; kind <= GM_CV_COORD_Q6; kind++) {
-    gm_batch::Group g;
-    g.kind = kind;
-    for (int32_t i = 0; i < count; i++)
-      if (walkers[i]->p.cv_kind == kind) g.members.push_back(i);
-    if (!g.members.empty()) B->groups.push_back(std::move(g));
-  }
-  for (gm_ctx* c : B->walkers) {
-    c->stream = B->stream;
-    c->version++;
-  }
-  {
-    std::vector<unsigned char> vals;
-    for (gm_ctx* c : B->walkers) {
-      append(vals, c->s_int);
-      append(vals, c->V_int);
-      append(vals, c->dV_int);
-    }
-    const int rc = upload(vals, &B->d_vals, B->stream);
-    if (rc != GM_OK) {
-      free_batch(B);
-      delete B;
-      return rc;
-    }
+  B->fp64 = walkers[0]->fp64;
+  const int rc = set_members(B, walkers, count, pos4, force4);
+  if (rc != GM_OK) {
+    free_batch(B);
+    delete B;
+    return rc;
   }
   *out = B;
   return GM_OK;
+}
+
+int gm_batch_update(gm_batch* B, gm_ctx* const* walkers, int32_t count, const float* const* pos4,
+                    void* const* force4) {
+  if (!B || count < 0 || (count > 0 && (!walkers || !pos4 || !force4))) return GM_ERR_INVALID_ARG;
+  return set_members(B, walkers, count, pos4, force4);
 }
 
 int gm_batch_destroy(gm_batch* B) {
@@ -1343,9 +1362,48 @@ int gm_batch_step(gm_batch* B) {
 int gm_batch_deposit(gm_batch* B) {
   if (!B) return GM_ERR_INVALID_ARG;
   for (auto& g : B->groups) {
+    if (g.members.empty()) continue;
     GM_TRY(B->fp64 ? refresh_group<double>(B, g, false) : refresh_group<float>(B, g, false));
-    GM_TRY(hip_rc(launch_bias_batch(reinterpret_cast<const BiasArgs*>(g.d_dep), g.d_blk_bias,
+    GM_TRY(hip_rc(launch_bias_batch(reinterpret_cast<const BiasArgs*>(g.d_dep), static_cast<const int32_t*>(g.d_blk_bias),
                                     (int32_t)g.members.size(), g.blocks_bias, B->stream)));
+  }
+  return GM_OK;
+}
+
+int gm_batch_deposit_some(gm_batch* B, const int32_t* which, int32_t count) {
+  if (!B || count < 0 || (count > 0 && !which)) return GM_ERR_INVALID_ARG;
+  const int32_t W = (int32_t)B->walkers.size();
+  std::vector<char> seen(W, 0);
+  for (int32_t i = 0; i < count; i++) {
+    if (which[i] < 0 || which[i] >= W || seen[which[i]]) return GM_ERR_INVALID_ARG;
+    if (!B->walkers[which[i]]->fwd) return GM_ERR_STATE;
+    seen[which[i]] = 1;
+  }
+  for (auto& g : B->groups) {
+    bool any = false;
+    for (int m : g.members) any = any || seen[m];
+    if (any) GM_TRY(B->fp64 ? refresh_group<double>(B, g, false) : refresh_group<float>(B, g, false));
+  }
+  BiasSubset s;
+  s.k = 0;
+  s.blk[0] = 0;
+  for (int32_t i = 0; i < count; i++) {
+    const int m = which[i];
+    const gm_batch::Group* gp = nullptr;
+    int pos = -1;
+    for (const auto& g : B->groups)
+      for (size_t j = 0; j < g.members.size() && pos < 0; j++)
+        if (g.members[j] == m) {
+          gp = &g;
+          pos = (int)j;
+        }
+    if (!gp) return GM_ERR_INVALID_ARG;
+    s.tab[s.k] = reinterpret_cast<const BiasArgs*>(gp->d_dep) + pos;
+    s.blk[s.k + 1] = s.blk[s.k] + B->walkers[m]->bias_blocks;
+    if (++s.k == kSubsetMax || i == count - 1) {
+      GM_TRY(hip_rc(launch_bias_subset(s, B->stream)));
+      s.k = 0;
+    }
   }
   return GM_OK;
 }
@@ -1354,7 +1412,7 @@ int gm_batch_values(gm_batch* B, double* s_dev, double* V_dev, double* dVds_dev)
   if (!B) return GM_ERR_INVALID_ARG;
   if ((s_dev && !aligned(s_dev, 8)) || (V_dev && !aligned(V_dev, 8)) || (dVds_dev && !aligned(dVds_dev, 8)))
     return GM_ERR_INVALID_ARG;
-  if (!s_dev && !V_dev && !dVds_dev) return GM_OK;
+  if ((!s_dev && !V_dev && !dVds_dev) || B->walkers.empty()) return GM_OK;
   return hip_rc(launch_batch_values(reinterpret_cast<const double* const*>(B->d_vals), (int32_t)B->walkers.size(),
                                     s_dev, V_dev, dVds_dev, B->stream));
 }

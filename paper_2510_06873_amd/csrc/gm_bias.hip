@@ -108,6 +108,29 @@ hipError_t launch_bias_batch(const BiasArgs* tab, const int32_t* blk_start, int3
   return hipGetLastError();
 }
 
+// The same for a subset of a batch's walkers named by value.
+__global__ __launch_bounds__(kBlock) void k_bias_subset(BiasSubset s) {
+  const int32_t g = blockIdx.x;
+  int32_t lo = 0, hi = s.k;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (s.blk[mid] <= g) lo = mid; else hi = mid;
+  }
+  bias_body(*s.tab[lo], g - s.blk[lo], s.blk[lo + 1] - s.blk[lo]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bias_finish_subset(BiasSubset s) {
+  const int32_t w = blockIdx.x;
+  bias_finish_body(*s.tab[w], s.blk[w + 1] - s.blk[w]);
+}
+
+hipError_t launch_bias_subset(const BiasSubset& s, hipStream_t st) {
+  if (s.k < 1) return hipSuccess;
+  k_bias_subset<<<(unsigned)s.blk[s.k], kBlock, 0, st>>>(s);
+  k_bias_finish_subset<<<(unsigned)s.k, kBlock, 0, st>>>(s);
+  return hipGetLastError();
+}
+
 // CV, bias and dV/ds of every walker of a batch into dense arrays (second
 // columns hold the contexts' zero second entries for 1-D CVs).
 __global__ __launch_bounds__(kBlock) void k_batch_values(const double* const* __restrict__ tab, int32_t W, double* s,

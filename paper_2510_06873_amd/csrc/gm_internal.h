@@ -248,6 +248,15 @@ hipError_t launch_pass_batch(int pass, bool with_cn, bool fp_rows, const CvArgs<
                              int32_t W, int32_t blocks, int32_t cap, hipStream_t st);
 hipError_t launch_bias_batch(const BiasArgs* tab, const int32_t* blk_start, int32_t W, int32_t blocks,
                              hipStream_t st);
+// Some walkers of a batch in one launch pair: device pointers to their table
+// entries and the workgroup prefix, passed by value.
+constexpr int kSubsetMax = 64;
+struct BiasSubset {
+  const BiasArgs* tab[kSubsetMax];
+  int32_t blk[kSubsetMax + 1];
+  int32_t k;
+};
+hipError_t launch_bias_subset(const BiasSubset& s, hipStream_t st);
 hipError_t launch_sum_i32(const int32_t* v, int64_t n, unsigned long long* out, hipStream_t st);
 
 // LDS bytes of one staged halo slot: position only, or position + 16-wide row.

@@ -265,19 +265,25 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
                 continue
             ids = tuple(w.req.rid for w in active)
             if ids != members:
-                if batch is not None:
-                    batch.close()
-                batch = Batch([w.pipe for w in active], [w.pos for w in active], [w.F for w in active],
-                              stream=stream)
+                # one batch for the whole run: a change of members keeps its
+                # device tables (no allocation or free per change)
+                pipes, xs, fs = [w.pipe for w in active], [w.pos for w in active], [w.F for w in active]
+                if batch is None:
+                    batch = Batch(pipes, xs, fs, stream=stream)
+                else:
+                    batch.update(pipes, xs, fs)
                 members = ids
             # rebuilds due at each walker's own step count
             _rebuild_concurrently([w for w in active if w.done > 0 and w.done % w.req.pace == 0], stream, aux)
             batch.step()
             ticks += 1
-            for w in active:
+            due = []
+            for k, w in enumerate(active):
                 w.done += 1
                 if w.done % w.req.pace == 0:
-                    w.pipe.deposit_hill()
+                    due.append(k)
+            if due:
+                batch.deposit(due)  # one launch pair for the walkers due
             # prepare walkers for the next free slots while the step runs
             step_done = torch.cuda.Event()
             step_done.record(stream)
@@ -308,10 +314,12 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
                 retiring.append(_Retiring(ev, finished, s_h, V_h, [members.index(w.req.rid) for w in finished],
                                           forces))
                 active = [w for w in active if w.done < w.req.steps]
-                batch.close()
-                batch = None
-                members = None
+                # the finished walkers leave the batch before their contexts close
+                batch.update([w.pipe for w in active], [w.pos for w in active], [w.F for w in active])
+                members = tuple(w.req.rid for w in active)
         stream.synchronize()
+        if batch is not None:
+            batch.close()
     wall = time.perf_counter() - t0
     return results, _stats(results, wall, ticks=ticks, peak_bytes=peak_used)
 

@@ -153,3 +153,94 @@ def test_context_with_a_smaller_lds_budget_created_later():
     assert np.array_equal(pipe.s.cpu().numpy(), s_ref)
     assert np.array_equal(F.cpu().numpy(), F_ref)
     later.close()
+
+
+def test_batch_update_members_bitwise_equals_solo():
+    """One batch whose members change between steps (walkers join, finish and
+    leave, the member list ends empty): every walker's CV, bias, forces and
+    hills are bitwise those of stepping it alone, and contexts closed after
+    leaving the batch do not disturb the ones that stay."""
+    from paper_2510_06873_amd import Batch
+
+    dev = torch.device("cuda", 0)
+    ws = walkers()
+    solo = {}
+    for k, (wl, d) in enumerate(ws):
+        pipe, F = _run_solo(wl, d, dev, k, 3)
+        torch.cuda.synchronize()
+        solo[k] = (pipe.s.cpu().numpy().copy(), pipe.V.item(), F.cpu().numpy().copy(), pipe.hills_get())
+        pipe.close()
+    made = {k: setup(wl, d, dev, k) for k, (wl, d) in enumerate(ws)}
+    joins = {0: [0, 1, 2], 1: [3], 2: [4]}
+    active, done, batch = [], {}, None
+    for tick in range(8):
+        active += joins.get(tick, [])
+        if not active:
+            break
+        args = ([made[k][0] for k in active], [made[k][1] for k in active], [made[k][2] for k in active])
+        if batch is None:
+            batch = Batch(*args)
+        else:
+            batch.update(*args)
+        for k in active:
+            if done.get(k, 0) == 1:
+                made[k][0].deposit_hill()
+        batch.step()
+        s, V = batch.values()
+        s, V = s.cpu().numpy(), V.cpu().numpy()
+        for row, k in enumerate(active):
+            done[k] = done.get(k, 0) + 1
+        finished = [k for k in active if done[k] == 3]
+        for k in finished:
+            row = active.index(k)
+            pipe, p4, F = made[k]
+            assert pipe.status(True) == 0, k
+            s_solo, V_solo, F_solo, (c_solo, h_solo) = solo[k]
+            assert np.array_equal(s[row, :pipe.dims], s_solo[:pipe.dims]), (tick, k)
+            assert V[row] == V_solo, (tick, k)
+            assert np.array_equal(F.cpu().numpy(), F_solo), (tick, k)
+            c, h = pipe.hills_get()
+            assert np.array_equal(c, c_solo) and np.array_equal(h, h_solo), (tick, k)
+        active = [k for k in active if k not in finished]
+        batch.update([made[k][0] for k in active], [made[k][1] for k in active], [made[k][2] for k in active])
+        for k in finished:
+            made[k][0].close()
+    assert sorted(done) == list(range(len(ws))) and all(v == 3 for v in done.values())
+    batch.close()
+
+
+def test_batch_deposit_some_bitwise_equals_solo():
+    """Deposits for some members only (one launch pair): the depositing
+    walkers' hills are bitwise those of gm_deposit_hill on each alone, the
+    others get none; repeated or out-of-range indices are refused."""
+    from paper_2510_06873_amd import Batch
+    from paper_2510_06873_amd.binding import GmError
+
+    dev = torch.device("cuda", 0)
+    ws = walkers()
+    solo = {}
+    for k, (wl, d) in enumerate(ws):
+        pipe, p4, F = setup(wl, d, dev, k)
+        pipe.step(p4, F)
+        if k in (1, 3):
+            pipe.deposit_hill()
+        pipe.step(p4, F)
+        torch.cuda.synchronize()
+        solo[k] = (pipe.hills_get(), F.cpu().numpy().copy())
+        pipe.close()
+    made = [setup(wl, d, dev, k) for k, (wl, d) in enumerate(ws)]
+    batch = Batch([m[0] for m in made], [m[1] for m in made], [m[2] for m in made])
+    batch.step()
+    for bad in ([1, 1], [len(ws)], [-1]):
+        with pytest.raises(GmError):
+            batch.deposit(bad)
+    batch.deposit([3, 1])
+    batch.step()
+    torch.cuda.synchronize()
+    for k, (pipe, p4, F) in enumerate(made):
+        assert pipe.status(True) == 0
+        (c_solo, h_solo), F_solo = solo[k]
+        c, h = pipe.hills_get()
+        assert np.array_equal(c, c_solo) and np.array_equal(h, h_solo), k
+        assert np.array_equal(F.cpu().numpy(), F_solo), k
+    batch.close()
