@@ -404,7 +404,8 @@ template <int MODE, typename T>
 __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, const CellGeom& cg,
                                            const BrickGeom& g, const BrickIndex& bi, double rl2, uint16_t* nbr,
                                            int32_t kmax, int32_t* cnt, int32_t* err, const float4* hpos,
-                                           const int32_t* hp, int32_t hb, int32_t ob, int32_t k0, int32_t k1,
+                                           const int32_t* hp, int32_t hb, int32_t ob, int32_t O, int32_t k0,
+                                           int32_t k1,
                                            int32_t hx, int32_t hxy, int32_t& mymax, double& mysum) {
 #pragma clang fp contract(off)
   float Lf[3], iLf[3], Llo[3];
@@ -433,9 +434,11 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
       pi = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
     }
     int32_t count = 0;  // the same in every lane of the group
-    // entry e goes to sub-row e % TPA at e / TPA: 32-bit offsets from the
-    // atom's first sub-row
-    uint16_t* const row0 = nbr + subrow(g, ob, k, 0);
+    // entry e goes to sub-row e % TPA at index x = e / TPA: piece x / 8 of
+    // that sub-row, pieces pstride8 entries apart (32-bit offsets from the
+    // atom's first piece)
+    uint16_t* const row0 = nbr + row_first(g, ob, k, 0);
+    const int32_t pstride8 = piece_stride(g, O) * 8;
     for (int cz = -1; cz <= 1; cz++)
       for (int cy = -1; cy <= 1; cy++) {
         const int h = hc + cz * hxy + cy * hx;  // middle cell of the x-run
@@ -475,7 +478,10 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
           const uint64_t m = __ballot(in);
           if (in) {
             const int32_t e = count + __popcll(m & below);
-            if (e < kmax) row0[(e & (g.tpa - 1)) * g.kpart + (e >> tsh)] = (uint16_t)sl;
+            if (e < kmax) {
+              const int32_t x = e >> tsh;
+              row0[(e & (g.tpa - 1)) * 8 + (x >> 3) * pstride8 + (x & 7)] = (uint16_t)sl;
+            }
           }
           count += __popcll(m & gmask);
         }
@@ -485,7 +491,7 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
       const int32_t part = i >> 3;
       const int32_t np = stored > part ? ((stored - 1 - part) >> tsh) + 1 : 0;
       const int32_t at = np + (i & 7);
-      if (at < ((np + 7) & ~7)) nbr[subrow(g, ob, k, part) + at] = 0;
+      if (at < ((np + 7) & ~7)) nbr[row_entry(g, ob, O, k, part, at)] = 0;
     }
     if (lig == 0) {
       cnt[ob + k] = count;
@@ -513,7 +519,7 @@ __global__ __launch_bounds__(MAXT) void k_build_nbr(const vec4_t<T>* __restrict_
   const int64_t b = lb / g.build_split;
   const int32_t part = (int32_t)(lb - b * g.build_split);
   const bool live = b < g.nbricks;
-  int32_t hb = 0, H = 0, ob = 0, k0 = 0, k1 = 0, hx = 0, hxy = 0;
+  int32_t hb = 0, H = 0, ob = 0, O = 0, k0 = 0, k1 = 0, hx = 0, hxy = 0;
   int mode = 2;
   if (live) {
     const BrickShape s = brick_shape(b, g);
@@ -522,7 +528,7 @@ __global__ __launch_bounds__(MAXT) void k_build_nbr(const vec4_t<T>* __restrict_
     hb = bi.hb[b];
     H = bi.hb[b + 1] - hb;
     ob = bi.ob[b];
-    const int32_t O = bi.ob[b + 1] - ob;
+    O = bi.ob[b + 1] - ob;
     const int32_t share = (O + g.build_split - 1) / g.build_split;
     k0 = part * share < O ? part * share : O;
     k1 = k0 + share < O ? k0 + share : O;
@@ -539,13 +545,13 @@ __global__ __launch_bounds__(MAXT) void k_build_nbr(const vec4_t<T>* __restrict_
   int32_t mymax = 0;
   double mysum = 0.0;
   if (mode == 0)
-    build_rows<0, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, k0, k1, hx, hxy, mymax,
+    build_rows<0, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
                      mysum);
   else if (mode == 1)
-    build_rows<1, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, k0, k1, hx, hxy, mymax,
+    build_rows<1, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
                      mysum);
   else
-    build_rows<2, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, k0, k1, hx, hxy, mymax,
+    build_rows<2, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
                      mysum);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -575,7 +581,7 @@ __global__ __launch_bounds__(kBlock) void k_neighbor_ranks(const uint16_t* __res
     const int32_t c = cnt[ob + k];
     const int32_t m = c < kmax ? c : kmax;
     for (int32_t e = 0; e < m; e++)
-      nbr_out[(int64_t)r * kmax + e] = bi.halo_rank[hb + nbr[subrow(g, ob, k, e % g.tpa) + e / g.tpa]];
+      nbr_out[(int64_t)r * kmax + e] = bi.halo_rank[hb + nbr[row_entry(g, ob, O, k, e % g.tpa, e / g.tpa)]];
     cnt_out[r] = c;
   }
 }

@@ -225,7 +225,7 @@ __device__ __forceinline__ T group_sum(T v, int TPA) {
 // records.  Otherwise a fetch may go to global memory and stays guarded.
 template <bool ALL, typename T, class Body>
 __device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lr, const T* rows,
-                                             const uint16_t* crow, int32_t n, uint4 first, Body body) {
+                                             const uint16_t* crow, int32_t n, int32_t ps, uint4 first, Body body) {
   if (n <= 0) return;
   vec4_t<T> pa, pb;
   T va[16], vb[16];
@@ -238,7 +238,7 @@ __device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k,
     uint4 cur = first;
     fetch_rec<ALL>(a, k, lr, rows, (int32_t)(cur.x & 0xffffu), pa, va);
     for (int32_t b = 0; b < n; b += 8) {
-      const uint4 nxt = src[min((b >> 3) + 1, last)];
+      const uint4 nxt = src[min((b >> 3) + 1, last) * ps];
       const uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
 #pragma unroll
       for (int e = 0; e < 8; e += 2) {
@@ -252,7 +252,7 @@ __device__ __forceinline__ void walk_records(const CvArgs<T>& a, const Brick& k,
     }
   } else {
     SlotStream st;
-    st.init_first(crow, n, first);
+    st.init_first(crow, n, ps, first);
     fetch_rec<ALL>(a, k, lr, rows, st.pop(), pa, va);
     for (int32_t j = 0; j < n; j += 2) {
       const bool b_ok = j + 1 < n;
@@ -299,7 +299,7 @@ __device__ __forceinline__ void head_record(const CvArgs<T>& a, const Brick& k, 
 template <typename T>
 __device__ __forceinline__ void head_rows(const CvArgs<T>& a, const Brick& k, int32_t part, AtomHead& h) {
   h.nc = a.ccnt[(int64_t)(k.ob + h.o) * a.bg.tpa + part];
-  h.c0 = *reinterpret_cast<const uint4*>(a.cut + subrow(a.bg, k.ob, h.o, part));  // allocated even when nc = 0
+  h.c0 = *reinterpret_cast<const uint4*>(a.cut + row_first(a.bg, k.ob, h.o, part));  // allocated even when nc = 0
 }
 
 // Threads past the brick's atoms load the last atom's head (valid memory,
@@ -429,7 +429,7 @@ __device__ __forceinline__ void balance_pair(SlotWriter& wr) {
 #pragma unroll
     for (int q = 0; q < 8; q++)
       if (q >= r) w[q >> 1] &= (q & 1) ? 0x0000ffffu : 0xffff0000u;
-    wr.dst[keep >> 3] = make_uint4(w[0], w[1], w[2], w[3]);
+    wr.dst[(keep >> 3) * wr.ps] = make_uint4(w[0], w[1], w[2], w[3]);
   }
   wr.n = keep;
 }
@@ -448,11 +448,12 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
     const int32_t cp = c > part ? ((c - part - 1) >> TSH) + 1 : 0;
     // Phase 1: distance filter over the neighbour sub-row, writing this
     // step's in-cutoff slots (cheap, so divergence costs little).
-    uint16_t* crow = a.cut + subrow(a.bg, k.ob, o, part);
-    const uint16_t* nrow = a.nbr + subrow(a.bg, k.ob, o, part);
+    uint16_t* crow = a.cut + row_first(a.bg, k.ob, o, part);
+    const uint16_t* nrow = a.nbr + row_first(a.bg, k.ob, o, part);
+    const int32_t ps = piece_stride(a.bg, k.O);
     SlotWriter wr;
-    wr.init(crow);
-    for_slots<true>(nrow, cp, first_chunk(nrow, cp), [&](int32_t s) {
+    wr.init(crow, ps);
+    for_slots<true>(nrow, cp, ps, first_chunk(nrow, cp), [&](int32_t s) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
       if (pair_vec<WRAP>(pi, pj, a, dx, dy, dz) < a.rc2) wr.push(s);
@@ -478,7 +479,7 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
 #pragma unroll
     for (int m = 0; m < 13; m++) Q[m] = T(0);
     T fsum = T(0), cnsum = T(0);
-    for_slots<true>(crow, nc, first_chunk(crow, nc), [&](int32_t s) {
+    for_slots<true>(crow, nc, ps, first_chunk(crow, nc), [&](int32_t s) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
@@ -557,7 +558,7 @@ __device__ __forceinline__ double pass2_atoms(const CvArgs<T>& a, const Brick& k
     T qi[16];
     fetch_rec<ALL>(a, k, lr, a.qrow, si, pi, qi);
     T nbond = T(0);
-    walk_records<ALL>(a, k, lr, a.qrow, a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0, [&](const vec4_t<T>& pj, const T* qj) {
+    walk_records<ALL>(a, k, lr, a.qrow, a.cut + row_first(a.bg, k.ob, o, part), nc, piece_stride(a.bg, k.O), h.c0, [&](const vec4_t<T>& pj, const T* qj) {
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T r = r2 * g_rsqrt(r2);  // the same r as passes 3 and 4
@@ -612,7 +613,7 @@ __device__ __forceinline__ void pass3_atoms(const CvArgs<T>& a, const Brick& k, 
 #pragma unroll
     for (int m = 0; m < 13; m++) hs[m] = T(0);
     T rx = T(0), ry = T(0), rz = T(0);
-    walk_records<ALL>(a, k, lr, a.qrow, a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0, [&](const vec4_t<T>& pj, const T* qj) {
+    walk_records<ALL>(a, k, lr, a.qrow, a.cut + row_first(a.bg, k.ob, o, part), nc, piece_stride(a.bg, k.O), h.c0, [&](const vec4_t<T>& pj, const T* qj) {
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
@@ -685,7 +686,7 @@ __device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, 
     fetch_rec<ALL>(a, k, lr, a.grow, si, pi, gi);
     T ax = T(0), ay = T(0), az = T(0);
     T cx = T(0), cy = T(0), cz = T(0);
-    walk_records<ALL>(a, k, lr, a.grow, a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0, [&](const vec4_t<T>& pj, const T* gj) {
+    walk_records<ALL>(a, k, lr, a.grow, a.cut + row_first(a.bg, k.ob, o, part), nc, piece_stride(a.bg, k.O), h.c0, [&](const vec4_t<T>& pj, const T* gj) {
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       const T rinv = g_rsqrt(r2);
@@ -767,7 +768,7 @@ __device__ __forceinline__ void cn_force_atoms(const CvArgs<T>& a, const Brick& 
   GM_FOR_RANKED(a, k, h0) {
     const vec4_t<T> pi = fetch_pos<ALL>(a, k, lp, si);
     T cx = T(0), cy = T(0), cz = T(0);
-    for_slots<true>(a.cut + subrow(a.bg, k.ob, o, part), nc, h.c0, [&](int32_t s) {
+    for_slots<true>(a.cut + row_first(a.bg, k.ob, o, part), nc, piece_stride(a.bg, k.O), h.c0, [&](int32_t s) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);

@@ -305,11 +305,28 @@ __device__ __forceinline__ int64_t logical_brick(const BrickGeom& g) {
   return (b % kXcd) * per + b / kXcd;
 }
 
-// First entry of the sub-row of part `part` of owned atom `o` of a brick whose
-// owned atoms start at `ob`.  Entry e of an atom's row lives in sub-row
-// e % tpa at index e / tpa.
-__device__ __forceinline__ int64_t subrow(const BrickGeom& g, int32_t ob, int32_t o, int32_t part) {
-  return ((int64_t)(ob + o) * g.tpa + part) * g.kpart;
+// Rows of 16-bit halo slots (neighbour rows and this step's in-cutoff rows).
+// Entry e of an atom's row lives in sub-row e % tpa at index e / tpa, and a
+// sub-row is stored in pieces of 8 entries (16 bytes).  A brick's rows are
+// piece-major: piece q of sub-row `part` of owned atom `o` is piece
+// (q O + o) tpa + part of the brick's region, which starts at entry
+// ob tpa kpart (ob: the brick's first owned atom, O: its owned count).  Most
+// sub-rows end in their first or second piece, so the later pieces, which
+// few atoms reach, lie in cache lines of their own instead of between the
+// pieces every atom reads.
+//
+// First entry of a sub-row (its piece 0), and the distance in pieces from one
+// piece of a sub-row to the next.
+__device__ __forceinline__ int64_t row_first(const BrickGeom& g, int32_t ob, int32_t o, int32_t part) {
+  return (int64_t)ob * g.tpa * g.kpart + ((int64_t)o * g.tpa + part) * 8;
+}
+
+__device__ __forceinline__ int32_t piece_stride(const BrickGeom& g, int32_t O) { return O * g.tpa; }
+
+// Entry x of a sub-row.
+__device__ __forceinline__ int64_t row_entry(const BrickGeom& g, int32_t ob, int32_t O, int32_t o, int32_t part,
+                                             int32_t x) {
+  return row_first(g, ob, o, part) + (int64_t)(x >> 3) * piece_stride(g, O) * 8 + (x & 7);
 }
 
 // Sequential reader of one sub-row of 16-bit slots: 8 entries per 16-byte
@@ -321,10 +338,11 @@ __device__ __forceinline__ int64_t subrow(const BrickGeom& g, int32_t ob, int32_
 struct SlotStream {
   const uint4* src;
   uint4 cur, nxt;
-  int32_t n, j;
+  int32_t n, j, ps;
 
-  __device__ __forceinline__ void init(const uint16_t* row, int32_t count) {
+  __device__ __forceinline__ void init(const uint16_t* row, int32_t count, int32_t stride) {
     src = reinterpret_cast<const uint4*>(row);
+    ps = stride;
     n = count;
     j = 0;
     cur = make_uint4(0, 0, 0, 0);
@@ -333,8 +351,9 @@ struct SlotStream {
   }
 
   // The same, with the row's first 16 bytes already loaded.
-  __device__ __forceinline__ void init_first(const uint16_t* row, int32_t count, uint4 first) {
+  __device__ __forceinline__ void init_first(const uint16_t* row, int32_t count, int32_t stride, uint4 first) {
     src = reinterpret_cast<const uint4*>(row);
+    ps = stride;
     n = count;
     j = 0;
     cur = first;
@@ -348,13 +367,13 @@ struct SlotStream {
     cur.z = __builtin_amdgcn_alignbit(cur.w, cur.z, 16);
     cur.w = cur.w >> 16;
     j++;
-    if ((j & 7) == 4 && j + 4 < n) nxt = src[(j >> 3) + 1];
+    if ((j & 7) == 4 && j + 4 < n) nxt = src[((j >> 3) + 1) * ps];
     if ((j & 7) == 0) cur = nxt;
     return s;
   }
 };
 
-// Visits the first n slots of a sub-row in order, 8 to a block: the load of
+// Visits the first n slots of a sub-row (pieces ps apart) in order, 8 to a block: the load of
 // the next block's 16 bytes is issued before the current block is visited,
 // so its wait falls after 8 bodies.  The prefetch index is clamped to the
 // row's last used chunk, so the load is unconditional and in bounds.  `first`
@@ -364,12 +383,12 @@ struct SlotStream {
 // to memory, whereas a store inside the rolled inner loop (with no load
 // beside it) makes the compiler wait for the prefetch before that loop.
 template <bool UNROLL = false, class Body>
-__device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, uint4 first, Body body) {
+__device__ __forceinline__ void for_slots(const uint16_t* row, int32_t n, int32_t ps, uint4 first, Body body) {
   const uint4* src = reinterpret_cast<const uint4*>(row);
   const int32_t last = (n - 1) >> 3;
   uint4 cur = first;
   for (int32_t b = 0; b < n; b += 8) {
-    const uint4 nxt = src[min((b >> 3) + 1, last)];
+    const uint4 nxt = src[min((b >> 3) + 1, last) * ps];
     // Settle the wait for this block's 16 bytes here (in the first block
     // they are still in flight), so that no wait inside the block can also
     // drain the prefetch behind a store the body issued.
@@ -405,10 +424,11 @@ __device__ __forceinline__ uint4 first_chunk(const uint16_t* row, int32_t n) {
 struct SlotWriter {
   uint4* dst;
   uint4 buf;
-  int32_t n;
+  int32_t n, ps;
 
-  __device__ __forceinline__ void init(uint16_t* row) {
+  __device__ __forceinline__ void init(uint16_t* row, int32_t stride) {
     dst = reinterpret_cast<uint4*>(row);
+    ps = stride;
     buf = make_uint4(0, 0, 0, 0);
     n = 0;
   }
@@ -419,7 +439,7 @@ struct SlotWriter {
     buf.z = __builtin_amdgcn_alignbit(buf.w, buf.z, 16);
     buf.w = (buf.w >> 16) | ((uint32_t)s << 16);
     n++;
-    if ((n & 7) == 0) dst[(n >> 3) - 1] = buf;
+    if ((n & 7) == 0) dst[((n >> 3) - 1) * ps] = buf;
   }
 
   __device__ __forceinline__ void flush() {
@@ -434,7 +454,7 @@ struct SlotWriter {
         b.z = __builtin_amdgcn_alignbit(b.w, b.z, 16);
         b.w = b.w >> 16;
       }
-      dst[n >> 3] = b;
+      dst[(n >> 3) * ps] = b;
     }
   }
 };
