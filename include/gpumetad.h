@@ -305,6 +305,21 @@ int gm_batch_update(gm_batch* batch, gm_ctx* const* walkers, int32_t count, cons
 /* Rebuild every walker's cell and neighbour lists; boxes: host double[count][3]. */
 int gm_batch_build(gm_batch* batch, const double* boxes);
 
+/* Rebuild the lists of some members: which = host array of count distinct
+ * member indices (the order of the last create or update), boxes = host
+ * double[count][3] (row i is the box of walker which[i]).  Walkers whose cell
+ * grid and brick count each fit one workgroup's scan (at most 16,384) are
+ * rebuilt together, one launch per stage of the rebuild; the others as
+ * gm_build_neighbors does.  Lists and sorted order are bitwise those of
+ * gm_build_neighbors.  Enqueued on hip_stream (NULL: the batch's stream); on
+ * another stream the caller orders the work (that stream waits for the
+ * batch's stream before the call, and the batch's stream for it after).
+ * Buffers that must grow are allocated in the order of that stream.
+ * GM_ERR_INVALID_ARG for an index out of range or repeated; box errors as in
+ * gm_build_neighbors. */
+int gm_batch_build_some(gm_batch* batch, const int32_t* which, int32_t count, const double* boxes,
+                        void* hip_stream);
+
 /* One MD step of the bias pipeline for every walker: CV forward, bias,
  * adjoint and F -= dV/ds ds/dx, each pass one launch per CV kind.  V and dV/ds
  * stay in the walker's context.  GM_ERR_STATE if a walker was never built. */

@@ -31,12 +31,11 @@ EXPORTS = (
     "gm_cv_backward", "gm_apply_bias_forces", "gm_deposit_hill", "gm_hills_get", "gm_hills_set", "gm_status",
     "gm_strerror", "gm_neighbor_stats", "gm_release_rows", "gm_device_bytes", "gm_hills_set_device",
     "gm_status_copy", "gm_status_decode", "gm_reserve_neighbors",
-    "gm_copy_cell_list", "gm_copy_neighbors",
-    "gm_atom_values", "gm_version", "gm_batch_create", "gm_batch_destroy", "gm_batch_update", "gm_batch_build",
-    "gm_batch_step", "gm_batch_deposit", "gm_batch_deposit_some", "gm_batch_values", "gm_torsions",
-    "gm_torsion_forces", "gm_nearest_distance",
-    "gm_nearest_distance_forces", "gm_lattice_virial", "gm_fes_reweight", "gm_fes_reweight_noalloc",
-    "gm_fes_hills",
+    "gm_copy_cell_list", "gm_copy_neighbors", "gm_atom_values", "gm_version",
+    "gm_batch_create", "gm_batch_destroy", "gm_batch_update", "gm_batch_build", "gm_batch_build_some",
+    "gm_batch_step", "gm_batch_deposit", "gm_batch_deposit_some", "gm_batch_values",
+    "gm_torsions", "gm_torsion_forces", "gm_nearest_distance", "gm_nearest_distance_forces",
+    "gm_lattice_virial", "gm_fes_reweight", "gm_fes_reweight_noalloc", "gm_fes_hills",
 )
 
 
@@ -100,6 +99,7 @@ def _load() -> C.CDLL:
         "gm_batch_update": ([vp, C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)],
                             C.c_int),
         "gm_batch_build": ([vp, dp], C.c_int),
+        "gm_batch_build_some": ([vp, C.POINTER(C.c_int32), C.c_int32, dp, vp], C.c_int),
         "gm_batch_step": ([vp], C.c_int),
         "gm_batch_deposit": ([vp], C.c_int),
         "gm_batch_deposit_some": ([vp, C.POINTER(C.c_int32), C.c_int32], C.c_int),
@@ -491,6 +491,20 @@ class Batch:
 
         b = np.ascontiguousarray(boxes, dtype=np.float64).reshape(len(self.pipes), 3)
         _check(_lib.gm_batch_build(self.h, b.ctypes.data_as(C.POINTER(C.c_double))), "gm_batch_build")
+
+    def build_some(self, which, boxes, stream=None):
+        """Rebuild the lists of the member indices in `which` (boxes: one row
+        per listed walker), batched where the walkers allow; on `stream`
+        (default: the batch stream), ordered by the caller."""
+        import numpy as np
+
+        if not len(which):
+            return
+        b = np.ascontiguousarray(boxes, dtype=np.float64).reshape(len(which), 3)
+        idx = (C.c_int32 * len(which))(*[int(i) for i in which])
+        st = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(_lib.gm_batch_build_some(self.h, idx, len(which), b.ctypes.data_as(C.POINTER(C.c_double)), st),
+               "gm_batch_build_some")
 
     def step(self):
         _check(_lib.gm_batch_step(self.h), "gm_batch_step")

@@ -47,6 +47,9 @@ struct gm_ctx {
   double *part_a = nullptr, *part_b = nullptr, *s_int = nullptr, *V_int = nullptr, *dV_int = nullptr;
   double *centres = nullptr, *heights = nullptr, *bias_part = nullptr;
   int64_t* hill_count = nullptr;
+  BuildArgs* build_dev = nullptr;  // this context's rebuild arguments in device memory (batched rebuilds)
+  BuildArgs build_host;            // what build_dev holds (compared before re-uploading)
+  bool build_dev_ok = false;
 
   unsigned char* arena = nullptr;  // the fixed-size buffers below, carved from one allocation
   // buffers that grow or go together, one allocation each: the neighbour and
@@ -499,6 +502,8 @@ void free_all(gm_ctx* c) {
   c->nbr = c->cut = nullptr;
   c->count = c->start = c->fill = c->scan_tmp = nullptr;
   c->brick_H = c->brick_O = c->brick_hb = c->brick_ob = c->brick_hp = nullptr;
+  c->build_dev = nullptr;
+  c->build_dev_ok = false;
 }
 
 // The neighbour and in-cutoff rows (tpa sub-rows of kpart entries each).
@@ -628,6 +633,7 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
       {(void**)&c->order, n * 16},   {(void**)&c->pos_s, n * 4 * T},
       {(void**)&c->centres, cap * c->dims * 8}, {(void**)&c->heights, cap * 8},
       {(void**)&c->bias_part, (size_t)c->bias_blocks * 3 * 8},
+      {(void**)&c->build_dev, sizeof(BuildArgs)},
   };
   int rc = carve(c, &c->arena, pieces, (int)(sizeof(pieces) / sizeof(pieces[0])), 8);
   if (rc == GM_OK && !c->external) rc = alloc_rows(c);
@@ -683,7 +689,13 @@ static int reserve_bricks(gm_ctx* c) {
   return GM_OK;
 }
 
-int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
+}  // extern "C"
+
+namespace {
+
+// The host half of a rebuild: box checks, cell grid, bricks and the buffers
+// they need (allocated in stream order on the context's stream).
+int prepare_build(gm_ctx* c, const float* pos4, const double* box) {
   if (c && c->external) return GM_ERR_STATE;
   if (!c || !pos4 || !box || !aligned(pos4, 16)) return GM_ERR_INVALID_ARG;
   int32_t nc[3];
@@ -714,10 +726,16 @@ int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
   }
   choose_bricks(c, nc);
   GM_TRY(reserve_bricks(c));
-  hipStream_t st = c->stream;
-  const float4* p4 = reinterpret_cast<const float4*>(pos4);
   c->built = c->fwd = c->bwd = false;
-  // canonical cell list: counts, scan, scatter, per-cell sort by atom id
+  return GM_OK;
+}
+
+// The device half, one walker on stream st: canonical cell list (counts,
+// scan, scatter, per-cell sort by atom id), brick tables, sorted positions,
+// neighbour rows.
+int enqueue_build(gm_ctx* c, const float* pos4, hipStream_t st) {
+  const int64_t ncells = c->ncells;
+  const float4* p4 = reinterpret_cast<const float4*>(pos4);
   // cell counts, list statistics and the out-of-box flag (see the gather)
   GM_TRY(hip_rc(launch_reset_build(c->count, ncells, c->stats, c->err, st)));
   GM_TRY(hip_rc(launch_cell_ids(p4, c->n, c->geom, c->cell, c->count, c->err, st)));
@@ -743,6 +761,50 @@ int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
     GM_TRY(hip_rc(launch_build_nbr<float>(ps, c->geom, c->bg, bi, rl2, c->nbr, c->kmax, c->cnt, c->err, c->stats,
                                           st)));
   }
+  return GM_OK;
+}
+
+// Every buffer and parameter one rebuild of the context uses (after prepare_build).
+BuildArgs build_args(gm_ctx* c, const float* pos4) {
+  BuildArgs a;
+  memset(&a, 0, sizeof(a));
+  a.ga = gather_args(c, pos4);
+  a.cg = c->geom;
+  a.bg = c->bg;
+  a.bi = brick_index(c);
+  a.n = c->n;
+  a.ncells = c->ncells;
+  a.cell = c->cell;
+  a.count = c->count;
+  a.start = c->start;
+  a.fill = c->fill;
+  a.perm = c->perm;
+  a.scat = c->owned_rank;  // the scatter's output, rewritten by the brick fill
+  a.stats = c->stats;
+  a.err = c->err;
+  a.brick_H = c->brick_H;
+  a.brick_O = c->brick_O;
+  a.brick_hb = c->brick_hb;
+  a.brick_ob = c->brick_ob;
+  a.brick_hp = c->brick_hp;
+  a.halo_rank = c->halo_rank;
+  a.owned_slot = c->owned_slot;
+  a.owned_rank = c->owned_rank;
+  a.owned_hcell = c->owned_hcell;
+  a.nbr = c->nbr;
+  a.cnt = c->cnt;
+  a.kmax = c->kmax;
+  a.rl2 = c->r_list * c->r_list;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gm_build_neighbors(gm_ctx* c, const float* pos4, const double* box) {
+  GM_TRY(prepare_build(c, pos4, box));
+  GM_TRY(enqueue_build(c, pos4, c->stream));
   c->built = true;
   c->version++;
   return GM_OK;
@@ -1345,11 +1407,80 @@ int gm_batch_destroy(gm_batch* B) {
   return GM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Rebuild the listed members on stream st: host preparation for each, then
+// the batchable ones one launch per stage (kBuildSubsetMax at a time), the
+// rest alone.  The walkers' own streams are st meanwhile, so that buffers
+// grown here are allocated and released in the order of st.
+int batch_build(gm_batch* B, const int32_t* which, int32_t count, const double* boxes, hipStream_t st) {
+  const int32_t W = (int32_t)B->walkers.size();
+  std::vector<char> seen(W, 0);
+  for (int32_t i = 0; i < count; i++) {
+    if (which[i] < 0 || which[i] >= W || seen[which[i]]) return GM_ERR_INVALID_ARG;
+    seen[which[i]] = 1;
+  }
+  struct Restore {
+    gm_batch* B;
+    const int32_t* which;
+    int32_t count;
+    ~Restore() {
+      for (int32_t i = 0; i < count; i++) B->walkers[which[i]]->stream = B->stream;
+    }
+  } restore{B, which, count};
+  for (int32_t i = 0; i < count; i++) B->walkers[which[i]]->stream = st;
+  for (int32_t i = 0; i < count; i++) GM_TRY(prepare_build(B->walkers[which[i]], B->pos[which[i]], boxes + 3 * i));
+  std::vector<const BuildArgs*> dev;
+  std::vector<BuildArgs> host;
+  auto flush = [&]() -> int {
+    const int rc = hip_rc(launch_build_batch(dev.data(), host.data(), (int32_t)dev.size(), B->fp64, st));
+    dev.clear();
+    host.clear();
+    return rc;
+  };
+  for (int32_t i = 0; i < count; i++) {
+    gm_ctx* c = B->walkers[which[i]];
+    const float* pos4 = B->pos[which[i]];
+    const BuildArgs a = build_args(c, pos4);
+    if (!build_batchable(a)) {
+      GM_TRY(enqueue_build(c, pos4, st));
+      continue;
+    }
+    if (!c->build_dev_ok || memcmp(&a, &c->build_host, sizeof(a)) != 0) {
+      GM_TRY(hip_rc(launch_upload(c->build_dev, &a, sizeof(a), st)));
+      c->build_host = a;
+      c->build_dev_ok = true;
+    }
+    dev.push_back(c->build_dev);
+    host.push_back(a);
+    if ((int)dev.size() == kBuildSubsetMax) GM_TRY(flush());
+  }
+  if (!dev.empty()) GM_TRY(flush());
+  for (int32_t i = 0; i < count; i++) {
+    gm_ctx* c = B->walkers[which[i]];
+    c->built = true;
+    c->version++;
+  }
+  return GM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int gm_batch_build(gm_batch* B, const double* boxes) {
   if (!B || !boxes) return GM_ERR_INVALID_ARG;
-  for (size_t i = 0; i < B->walkers.size(); i++)
-    GM_TRY(gm_build_neighbors(B->walkers[i], B->pos[i], boxes + 3 * i));
-  return GM_OK;
+  std::vector<int32_t> all(B->walkers.size());
+  for (size_t i = 0; i < all.size(); i++) all[i] = (int32_t)i;
+  return batch_build(B, all.data(), (int32_t)all.size(), boxes, B->stream);
+}
+
+int gm_batch_build_some(gm_batch* B, const int32_t* which, int32_t count, const double* boxes, void* hip_stream) {
+  if (!B || count < 0 || (count > 0 && (!which || !boxes))) return GM_ERR_INVALID_ARG;
+  hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : B->stream;
+  return batch_build(B, which, count, boxes, st);
 }
 
 int gm_batch_step(gm_batch* B) {

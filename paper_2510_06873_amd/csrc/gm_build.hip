@@ -72,16 +72,21 @@ __device__ __forceinline__ int32_t wave_count_add(int32_t* base, int32_t key) {
   return __shfl(old, leader, 64) + rank;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cell_ids(const float4* __restrict__ pos, int64_t n,
-                                                     CellGeom g, int32_t* __restrict__ cell,
-                                                     int32_t* __restrict__ count, int32_t* err) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void cell_ids_body(const float4* __restrict__ pos, int64_t n, const CellGeom& g,
+                                              int32_t* __restrict__ cell, int32_t* __restrict__ count, int32_t* err,
+                                              int64_t i) {
   if (i >= n) return;
   int32_t c[3];
   if (!cell_coords(pos[i], g, c)) atomicOr(err, kErrNonFinite);
   int32_t id = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
   cell[i] = id;
   (void)wave_count_add(count, id);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_ids(const float4* __restrict__ pos, int64_t n,
+                                                     CellGeom g, int32_t* __restrict__ cell,
+                                                     int32_t* __restrict__ count, int32_t* err) {
+  cell_ids_body(pos, n, g, cell, count, err, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Exclusive prefix sum of n int32 values, out[n] = total, in three launches:
@@ -188,22 +193,31 @@ __global__ __launch_bounds__(kScanTile) void k_scan_small(const int32_t* __restr
 
 // Clears what a rebuild accumulates into: the cell counts, the list
 // statistics and the out-of-box flag.
-__global__ __launch_bounds__(kBlock) void k_reset_build(int32_t* __restrict__ count, int64_t ncells,
-                                                        int32_t* __restrict__ stats, int32_t* __restrict__ err) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void reset_build_body(int32_t* __restrict__ count, int64_t ncells,
+                                                 int32_t* __restrict__ stats, int32_t* __restrict__ err, int64_t i) {
   if (i < ncells) count[i] = 0;
   if (i < 4) stats[i] = 0;
   if (i == 0) err[1] = 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ cell, int64_t n,
-                                                    const int32_t* __restrict__ start,
-                                                    int32_t* __restrict__ fill, int32_t* __restrict__ perm) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_reset_build(int32_t* __restrict__ count, int64_t ncells,
+                                                        int32_t* __restrict__ stats, int32_t* __restrict__ err) {
+  reset_build_body(count, ncells, stats, err, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__device__ __forceinline__ void scatter_body(const int32_t* __restrict__ cell, int64_t n,
+                                             const int32_t* __restrict__ start, int32_t* __restrict__ fill,
+                                             int32_t* __restrict__ perm, int64_t i) {
   if (i >= n) return;
   const int32_t c = cell[i];
   const int32_t slot = wave_count_add(fill, c);
   perm[start[c] + slot] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ cell, int64_t n,
+                                                    const int32_t* __restrict__ start,
+                                                    int32_t* __restrict__ fill, int32_t* __restrict__ perm) {
+  scatter_body(cell, n, start, fill, perm, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // The atomic scatter leaves each cell's atoms in arbitrary order; placing each
@@ -211,11 +225,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ 
 // unique stable order.  One thread per atom counts the smaller ids of its
 // segment (the segment's reads are shared by its atoms and cached), so dense
 // cells cost linear time per atom instead of a quadratic sort per cell.
-__global__ __launch_bounds__(kBlock) void k_rank_cells(const int32_t* __restrict__ cell,
-                                                       const int32_t* __restrict__ start,
-                                                       const int32_t* __restrict__ scattered, int64_t n,
-                                                       int32_t* __restrict__ perm) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rank_cells_body(const int32_t* __restrict__ cell, const int32_t* __restrict__ start,
+                                                const int32_t* __restrict__ scattered, int64_t n,
+                                                int32_t* __restrict__ perm, int64_t t) {
   if (t >= n) return;
   const int32_t v = scattered[t];
   const int32_t c = cell[v];
@@ -223,6 +235,13 @@ __global__ __launch_bounds__(kBlock) void k_rank_cells(const int32_t* __restrict
   int32_t r = 0;
   for (int32_t k = b; k < e; k++) r += scattered[k] < v ? 1 : 0;
   perm[b + r] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank_cells(const int32_t* __restrict__ cell,
+                                                       const int32_t* __restrict__ start,
+                                                       const int32_t* __restrict__ scattered, int64_t n,
+                                                       int32_t* __restrict__ perm) {
+  rank_cells_body(cell, start, scattered, n, perm, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <typename T>
@@ -285,9 +304,9 @@ __device__ __forceinline__ int32_t block_scan_incl_wave(int32_t v, int32_t* wsum
 // --------------------------------------------------------------------------
 // One wave per brick: lanes over the halo cells, wave sums of the halo and
 // owned atom counts.
-__global__ __launch_bounds__(kBlock) void k_brick_count(const int32_t* __restrict__ start, BrickGeom g,
-                                                        int32_t* __restrict__ H, int32_t* __restrict__ O) {
-  const int64_t b = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+__device__ __forceinline__ void brick_count_body(const int32_t* __restrict__ start, const BrickGeom& g,
+                                                 int32_t* __restrict__ H, int32_t* __restrict__ O, int64_t blk) {
+  const int64_t b = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (b >= g.nbricks) return;
   const BrickShape s = brick_shape(b, g);
@@ -311,18 +330,23 @@ __global__ __launch_bounds__(kBlock) void k_brick_count(const int32_t* __restric
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_brick_count(const int32_t* __restrict__ start, BrickGeom g,
+                                                        int32_t* __restrict__ H, int32_t* __restrict__ O) {
+  brick_count_body(start, g, H, O, blockIdx.x);
+}
+
 // One workgroup per brick: slot prefix over the halo cells, the sorted
 // position of every halo slot, and for every owned atom its slot, sorted
 // position and own halo cell.
-__global__ __launch_bounds__(kBlock) void k_brick_fill(const int32_t* __restrict__ start, BrickGeom g, BrickIndex bi,
-                                                       int32_t* __restrict__ hp_out, int32_t* __restrict__ halo_rank,
-                                                       int32_t* __restrict__ owned_slot, int32_t* __restrict__ owned_rank,
-                                                       int32_t* __restrict__ owned_hcell, int32_t* err) {
+__device__ __forceinline__ void brick_fill_body(const int32_t* __restrict__ start, const BrickGeom& g,
+                                                const BrickIndex& bi, int32_t* __restrict__ hp_out,
+                                                int32_t* __restrict__ halo_rank, int32_t* __restrict__ owned_slot,
+                                                int32_t* __restrict__ owned_rank, int32_t* __restrict__ owned_hcell,
+                                                int32_t* err, int64_t b) {
   static_assert(kHaloCells <= kBlock && kOwnCells <= kBlock, "one thread per halo cell");
   __shared__ int32_t hcell[kHaloCells], hpre[kHaloCells + 1];
   __shared__ int32_t oh[kOwnCells], opre[kOwnCells + 1];
   __shared__ int32_t wsum[kBlock / 64];
-  const int64_t b = blockIdx.x;
   const BrickShape s = brick_shape(b, g);
   const int nh = s.h[0] * s.h[1] * s.h[2];
   const int no = s.e[0] * s.e[1] * s.e[2];
@@ -375,6 +399,13 @@ __global__ __launch_bounds__(kBlock) void k_brick_fill(const int32_t* __restrict
     owned_rank[ob + k] = start[hcell[h]] + idx;
     owned_hcell[ob + k] = h;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_brick_fill(const int32_t* __restrict__ start, BrickGeom g, BrickIndex bi,
+                                                       int32_t* __restrict__ hp_out, int32_t* __restrict__ halo_rank,
+                                                       int32_t* __restrict__ owned_slot, int32_t* __restrict__ owned_rank,
+                                                       int32_t* __restrict__ owned_hcell, int32_t* err) {
+  brick_fill_body(start, g, bi, hp_out, halo_rank, owned_slot, owned_rank, owned_hcell, err, blockIdx.x);
 }
 
 // Full neighbour rows as halo slots.  The decision is the FP64 test on the
@@ -502,11 +533,13 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
   }
 }
 
+// lb: the workgroup's logical index among the build_split x blocks of this
+// system's launch.
 template <typename T, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_build_nbr(const vec4_t<T>* __restrict__ pos_s, CellGeom cg, BrickGeom g,
-                                                      BrickIndex bi, double rl2, uint16_t* __restrict__ nbr,
-                                                      int32_t kmax, int32_t* __restrict__ cnt, int32_t* err,
-                                                      int32_t* stats) {
+__device__ __forceinline__ void build_nbr_body(const vec4_t<T>* __restrict__ pos_s, const CellGeom& cg,
+                                               const BrickGeom& g, const BrickIndex& bi, double rl2,
+                                               uint16_t* __restrict__ nbr, int32_t kmax, int32_t* __restrict__ cnt,
+                                               int32_t* err, int32_t* stats, int64_t lb) {
   extern __shared__ __align__(16) unsigned char smem[];
   float4* hpos = reinterpret_cast<float4*>(smem);
   __shared__ int32_t hp[kHaloCells + 1];
@@ -515,7 +548,6 @@ __global__ __launch_bounds__(MAXT) void k_build_nbr(const vec4_t<T>* __restrict_
   // build_split workgroups share a brick (consecutive logical indices, so on
   // one XCD): each stages the brick's halo and builds the rows of a
   // contiguous share of its owned atoms.
-  const int64_t lb = logical_brick(g);
   const int64_t b = lb / g.build_split;
   const int32_t part = (int32_t)(lb - b * g.build_split);
   const bool live = b < g.nbricks;
@@ -567,6 +599,101 @@ __global__ __launch_bounds__(MAXT) void k_build_nbr(const vec4_t<T>* __restrict_
     atomicMax(&stats[0], bm);
     atomicAdd(reinterpret_cast<unsigned long long*>(stats + 2), (unsigned long long)bsum);
   }
+}
+
+template <typename T, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_build_nbr(const vec4_t<T>* __restrict__ pos_s, CellGeom cg, BrickGeom g,
+                                                      BrickIndex bi, double rl2, uint16_t* __restrict__ nbr,
+                                                      int32_t kmax, int32_t* __restrict__ cnt, int32_t* err,
+                                                      int32_t* stats) {
+  build_nbr_body<T, MAXT>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, stats, logical_brick(g));
+}
+
+// --------------------------------------------------------------------------
+// Rebuilds of several systems, one launch per stage: workgroup g of a stage
+// serves walker w with blk[w] <= g < blk[w+1] (the stage's own prefix of
+// workgroups per walker), as workgroup g - blk[w] of that walker's own launch.
+// --------------------------------------------------------------------------
+struct BuildSubset {
+  const BuildArgs* tab[kBuildSubsetMax];
+  int32_t blk[kBuildSubsetMax + 1];
+  int32_t k;
+};
+
+__device__ __forceinline__ int32_t subset_walker(const BuildSubset& s, int64_t g) {
+  int32_t lo = 0, hi = s.k;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (s.blk[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+#define GM_SUBSET_BEGIN(s, gidx)                 \
+  const int64_t g_ = (gidx);                      \
+  const int32_t w_ = subset_walker((s), g_);      \
+  const BuildArgs& A = *(s).tab[w_];              \
+  const int64_t blk = g_ - (s).blk[w_];           \
+  (void)blk;
+
+__global__ __launch_bounds__(kBlock) void k_reset_build_b(BuildSubset s) {
+  GM_SUBSET_BEGIN(s, blockIdx.x)
+  reset_build_body(A.count, A.ncells, A.stats, A.err, blk * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_ids_b(BuildSubset s) {
+  GM_SUBSET_BEGIN(s, blockIdx.x)
+  cell_ids_body(A.ga.pos, A.n, A.cg, A.cell, A.count, A.err, blk * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(kScanTile) void k_scan_cells_b(BuildSubset s) {
+  __shared__ int32_t lds[kScanTile];
+  GM_SUBSET_BEGIN(s, blockIdx.x)
+  scan_small_one(A.count, A.ncells, A.start, A.fill, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_b(BuildSubset s) {
+  GM_SUBSET_BEGIN(s, blockIdx.x)
+  scatter_body(A.cell, A.n, A.start, A.fill, A.scat, blk * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank_cells_b(BuildSubset s) {
+  GM_SUBSET_BEGIN(s, blockIdx.x)
+  rank_cells_body(A.cell, A.start, A.scat, A.n, A.perm, blk * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_brick_count_b(BuildSubset s) {
+  GM_SUBSET_BEGIN(s, blockIdx.x)
+  brick_count_body(A.start, A.bg, A.brick_H, A.brick_O, blk);
+}
+
+__global__ __launch_bounds__(kScanTile) void k_scan_bricks_b(BuildSubset s) {
+  __shared__ int32_t lds[kScanTile];
+  GM_SUBSET_BEGIN(s, blockIdx.x)
+  scan_small_one(A.brick_H, A.bg.nbricks, A.brick_hb, nullptr, lds);
+  scan_small_one(A.brick_O, A.bg.nbricks, A.brick_ob, nullptr, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_brick_fill_b(BuildSubset s) {
+  GM_SUBSET_BEGIN(s, blockIdx.x)
+  brick_fill_body(A.start, A.bg, A.bi, A.brick_hp, A.halo_rank, A.owned_slot, A.owned_rank, A.owned_hcell, A.err,
+                  blk);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_b(BuildSubset s) {
+  GM_SUBSET_BEGIN(s, blockIdx.x)
+  gather_body<T>(A.ga, blk * blockDim.x + threadIdx.x);
+}
+
+// The whole grid is a multiple of the XCD count (each walker's share is), so
+// the XCD remap keeps a walker's bricks on few XCDs as in its own launch.
+template <typename T, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_build_nbr_b(BuildSubset s) {
+  const int64_t per = gridDim.x / kXcd;
+  GM_SUBSET_BEGIN(s, ((int64_t)blockIdx.x % kXcd) * per + (int64_t)blockIdx.x / kXcd)
+  build_nbr_body<T, MAXT>(reinterpret_cast<const vec4_t<T>*>(A.ga.pos_s), A.cg, A.bg, A.bi, A.rl2, A.nbr, A.kmax,
+                          A.cnt, A.err, A.stats, blk);
 }
 
 // Neighbour rows as sorted positions (for inspection and tests).
@@ -731,12 +858,83 @@ hipError_t launch_neighbor_ranks(const uint16_t* nbr, const int32_t* cnt, const 
   return hipGetLastError();
 }
 
+bool build_batchable(const BuildArgs& a) { return a.ncells <= kScanSmall && a.bg.nbricks <= kScanSmall; }
+
+hipError_t launch_build_batch(const BuildArgs* const* dev, const BuildArgs* host, int32_t k, bool fp64,
+                              hipStream_t st) {
+  if (k < 1) return hipSuccess;
+  if (k > kBuildSubsetMax) return hipErrorInvalidValue;
+  BuildSubset s;
+  s.k = k;
+  for (int32_t w = 0; w < k; w++) s.tab[w] = dev[w];
+  // workgroups per walker for a stage -> the subset's prefix; false if none
+  auto prefix = [&](auto per) {
+    s.blk[0] = 0;
+    for (int32_t w = 0; w < k; w++) s.blk[w + 1] = s.blk[w] + (int32_t)per(host[w]);
+    return s.blk[k] > 0;
+  };
+  const unsigned bw = kBlock / 64;  // bricks per workgroup of the brick count
+  if (prefix([](const BuildArgs& a) { return grid_of(a.ncells > 4 ? a.ncells : 4, kBlock); }))
+    k_reset_build_b<<<(unsigned)s.blk[k], kBlock, 0, st>>>(s);
+  if (prefix([](const BuildArgs& a) { return grid_of(a.n, kBlock); })) k_cell_ids_b<<<(unsigned)s.blk[k], kBlock, 0, st>>>(s);
+  if (prefix([](const BuildArgs&) { return 1; })) k_scan_cells_b<<<(unsigned)s.blk[k], kScanTile, 0, st>>>(s);
+  if (prefix([](const BuildArgs& a) { return grid_of(a.n, kBlock); })) {
+    k_scatter_b<<<(unsigned)s.blk[k], kBlock, 0, st>>>(s);
+    k_rank_cells_b<<<(unsigned)s.blk[k], kBlock, 0, st>>>(s);
+  }
+  if (prefix([&](const BuildArgs& a) { return grid_of(a.bg.nbricks, (int)bw); }))
+    k_brick_count_b<<<(unsigned)s.blk[k], kBlock, 0, st>>>(s);
+  if (prefix([](const BuildArgs&) { return 1; })) k_scan_bricks_b<<<(unsigned)s.blk[k], kScanTile, 0, st>>>(s);
+  if (prefix([](const BuildArgs& a) { return a.bg.nbricks; })) k_brick_fill_b<<<(unsigned)s.blk[k], kBlock, 0, st>>>(s);
+  if (prefix([](const BuildArgs& a) { return grid_of(a.n, kBlock); })) {
+    if (fp64)
+      k_gather_b<double><<<(unsigned)s.blk[k], kBlock, 0, st>>>(s);
+    else
+      k_gather_b<float><<<(unsigned)s.blk[k], kBlock, 0, st>>>(s);
+  }
+  // the neighbour rows: one launch per workgroup size, with the largest
+  // staging any of its walkers asks for
+  for (int wide = 0; wide < 2; wide++) {
+    BuildSubset u;
+    u.k = 0;
+    u.blk[0] = 0;
+    size_t lds = 0;
+    for (int32_t w = 0; w < k; w++) {
+      const BrickGeom& g = host[w].bg;
+      if ((g.build_threads > kBlock) != (wide == 1)) continue;
+      u.tab[u.k] = dev[w];
+      u.blk[u.k + 1] = u.blk[u.k] + g.blocks * g.build_split;
+      u.k++;
+      const size_t b = (size_t)g.build_cap * sizeof(float4);
+      lds = b > lds ? b : lds;
+    }
+    if (u.k == 0) continue;
+    const unsigned grid = (unsigned)u.blk[u.k];
+    if (fp64) {
+      if (wide)
+        k_build_nbr_b<double, kBuildMaxThreads><<<grid, kBuildMaxThreads, lds, st>>>(u);
+      else
+        k_build_nbr_b<double, kBlock><<<grid, kBlock, lds, st>>>(u);
+    } else {
+      if (wide)
+        k_build_nbr_b<float, kBuildMaxThreads><<<grid, kBuildMaxThreads, lds, st>>>(u);
+      else
+        k_build_nbr_b<float, kBlock><<<grid, kBlock, lds, st>>>(u);
+    }
+  }
+  return hipGetLastError();
+}
+
 void allow_build_lds(int bytes) {
   const hipFuncAttribute A = hipFuncAttributeMaxDynamicSharedMemorySize;
   (void)hipFuncSetAttribute((const void*)k_build_nbr<float, kBlock>, A, bytes);
   (void)hipFuncSetAttribute((const void*)k_build_nbr<float, kBuildMaxThreads>, A, bytes);
   (void)hipFuncSetAttribute((const void*)k_build_nbr<double, kBlock>, A, bytes);
   (void)hipFuncSetAttribute((const void*)k_build_nbr<double, kBuildMaxThreads>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_build_nbr_b<float, kBlock>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_build_nbr_b<float, kBuildMaxThreads>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_build_nbr_b<double, kBlock>, A, bytes);
+  (void)hipFuncSetAttribute((const void*)k_build_nbr_b<double, kBuildMaxThreads>, A, bytes);
   (void)hipGetLastError();
 }
 

@@ -171,6 +171,30 @@ struct GatherArgs {
   float L[3];    // box lengths
 };
 
+// Everything one walker's neighbour rebuild reads and writes, kept in device
+// memory per context so that rebuilds of several walkers run as one launch per
+// stage (the table entries are named by value in the launch).
+struct BuildArgs {
+  GatherArgs ga;  // caller positions -> sorted positions
+  CellGeom cg;
+  BrickGeom bg;
+  BrickIndex bi;
+  int64_t n, ncells;
+  int32_t *cell, *count, *start, *fill, *perm, *scat, *stats, *err;
+  int32_t *brick_H, *brick_O, *brick_hb, *brick_ob, *brick_hp, *halo_rank, *owned_slot, *owned_rank, *owned_hcell;
+  uint16_t* nbr;
+  int32_t* cnt;
+  int32_t kmax;
+  double rl2;
+};
+constexpr int kBuildSubsetMax = 64;
+// Rebuilds that fit the one-workgroup scans (cells and bricks) can be batched.
+bool build_batchable(const BuildArgs& a);
+// Rebuild k walkers (k <= kBuildSubsetMax): dev[i] is walker i's BuildArgs in
+// device memory, host[i] the same values on the host (for the grids).
+hipError_t launch_build_batch(const BuildArgs* const* dev, const BuildArgs* host, int32_t k, bool fp64,
+                              hipStream_t st);
+
 // ---- launchers -------------------------------------------------------------
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 // Copy bytes of host memory to dst (device, at least bytes rounded up to a

@@ -6,7 +6,10 @@ rebuild and a hill deposit every ``pace`` steps of its own.  The server keeps
 each admitted walker's lists and hills on the device, admits new requests at
 tick boundaries while a slot and HBM budget are free, and advances every
 active walker by one step per tick with one launch per pass for all of them
-(``Batch``).  Finished walkers free their slot and memory for the queue.
+(one ``Batch`` for the whole run, whose members change in place); the walkers
+due for a neighbour rebuild or a hill deposit at a tick get them in one
+launch per stage as well.  Finished walkers free their slot and memory for
+the queue.
 
 Nothing in the loop waits for the device while walkers run.  A request's
 arrays are page-locked before the run (the server receives them into pinned
@@ -152,25 +155,6 @@ class _Retiring:
     forces: list                # pinned force copies (keep_forces) or None
 
 
-def _rebuild_concurrently(walkers, stream, aux):
-    """Neighbour rebuilds of several walkers, spread over the auxiliary streams
-    so that their chains of small kernels overlap on the device.  Each rebuild
-    starts after the work already on the main stream (which reads the old
-    lists) and the main stream waits for all of them."""
-    if not walkers:
-        return
-    used = aux[:len(walkers)]
-    for s in used:
-        s.wait_stream(stream)
-    for k, w in enumerate(walkers):
-        s = used[k % len(used)]
-        w.pipe.set_stream(s)
-        w.pipe.build_neighbors(w.pos, w.req.box)
-        w.pipe.set_stream(stream)
-    for s in used:
-        stream.wait_stream(s)
-
-
 def _wider(req: Request) -> Request:
     """The same request with neighbour rows twice as wide."""
     from dataclasses import replace
@@ -179,7 +163,7 @@ def _wider(req: Request) -> Request:
 
 
 def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64, keep_forces: bool = False,
-                  device=None, rebuild_streams: int = 3, stage_ahead: Optional[int] = None):
+                  device=None, stage_ahead: Optional[int] = None):
     """Run the requests with continuous batching; returns (results, stats).
 
     stage_ahead: most walkers prepared ahead of a free slot (default max_slots;
@@ -198,7 +182,6 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
         r.pin(torch)
     stream = torch.cuda.Stream(device=dev)
     adm = torch.cuda.Stream(device=dev)
-    aux = [torch.cuda.Stream(device=dev) for _ in range(rebuild_streams)]
     pending = sorted(requests, key=lambda r: r.arrival)
     active: List[_Walker] = []
     staged: List[_Walker] = []
@@ -273,8 +256,11 @@ def serve_batched(requests: List[Request], hbm_budget: int, max_slots: int = 64,
                 else:
                     batch.update(pipes, xs, fs)
                 members = ids
-            # rebuilds due at each walker's own step count
-            _rebuild_concurrently([w for w in active if w.done > 0 and w.done % w.req.pace == 0], stream, aux)
+            # rebuilds due at each walker's own step count, one launch per
+            # stage of the rebuild for all of them
+            due = [k for k, w in enumerate(active) if w.done > 0 and w.done % w.req.pace == 0]
+            if due:
+                batch.build_some(due, [active[k].req.box for k in due])
             batch.step()
             ticks += 1
             due = []

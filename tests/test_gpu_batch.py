@@ -244,3 +244,62 @@ def test_batch_deposit_some_bitwise_equals_solo():
         assert np.array_equal(c, c_solo) and np.array_equal(h, h_solo), k
         assert np.array_equal(F.cpu().numpy(), F_solo), k
     batch.close()
+
+
+def test_batch_build_some_bitwise_equals_solo():
+    """Rebuilds of some members in one launch per stage (and a system too
+    large for the one-workgroup scans, rebuilt alone in the same call, on a
+    second stream): cell lists, neighbour rows and the step that follows are
+    bitwise those of gm_build_neighbors; bad indices are refused."""
+    from paper_2510_06873_amd import Batch, Pipeline
+    from paper_2510_06873_amd.binding import GmError
+
+    dev = torch.device("cuda", 0)
+    ws = walkers()
+    big = W.walker_structure("wz", 120000, seed=77)
+    big_wl = dict(Q6, cv="q6")
+    ws.append((big_wl, dict(pos=big[0], species=big[1], box=big[2])))
+    solo = []
+    for k, (wl, d) in enumerate(ws):
+        pipe, p4, F = setup(wl, d, dev, k)
+        pipe.step(p4, F)
+        torch.cuda.synchronize()
+        _, perm, start = pipe.cell_list()
+        nbr, cnt = pipe.neighbor_lists()
+        solo.append((perm.cpu().numpy(), start.cpu().numpy(), nbr.cpu().numpy(), cnt.cpu().numpy(),
+                     pipe.s.cpu().numpy().copy(), F.cpu().numpy().copy()))
+        pipe.close()
+    made = [setup(wl, d, dev, k) for k, (wl, d) in enumerate(ws)]
+    # lists built from shifted positions first, so that the batched rebuild
+    # has to replace every table
+    for k, (pipe, p4, F) in enumerate(made):
+        box = torch.tensor(np.asarray(ws[k][1]["box"], np.float64), device=dev)
+        shifted = p4.clone()
+        shifted[:, :3] = torch.remainder(p4[:, :3].double() + 1.37, box).float()
+        pipe.build_neighbors_checked(shifted, ws[k][1]["box"])
+        torch.cuda.synchronize()
+    batch = Batch([m[0] for m in made], [m[1] for m in made], [m[2] for m in made])
+    for bad in ([0, 0], [len(ws)]):
+        with pytest.raises(GmError):
+            batch.build_some(bad, [ws[0][1]["box"]] * len(bad))
+    side = torch.cuda.Stream(device=dev)
+    order = [5, 0, 3, 1, 4, 2]
+    side.wait_stream(batch.stream)
+    batch.build_some(order, [ws[k][1]["box"] for k in order], stream=side)
+    batch.stream.wait_stream(side)
+    batch.step()
+    torch.cuda.synchronize()
+    for k, (pipe, p4, F) in enumerate(made):
+        assert pipe.status(True) == 0, k
+        perm0, start0, nbr0, cnt0, s0, F0 = solo[k]
+        _, perm, start = pipe.cell_list()
+        nbr, cnt = pipe.neighbor_lists()
+        assert np.array_equal(perm.cpu().numpy(), perm0) and np.array_equal(start.cpu().numpy(), start0), k
+        cnt, nbr = cnt.cpu().numpy(), nbr.cpu().numpy()
+        assert np.array_equal(cnt, cnt0), k
+        # entries past a row's count are not written by the copy
+        used = np.arange(nbr.shape[1])[None, :] < np.minimum(cnt, nbr.shape[1])[:, None]
+        assert np.array_equal(nbr[used], nbr0[used]), k
+        assert np.array_equal(pipe.s.cpu().numpy()[:pipe.dims], s0[:pipe.dims]), k
+        assert np.array_equal(F.cpu().numpy(), F0), k
+    batch.close()
