@@ -105,8 +105,9 @@ def cache_key(n_atoms: int, box: Sequence[float], params: Params) -> str:
 
 
 def autotune(pos4, box, params: Params, steps: int = 3, cache: Optional[str] = None,
-             limit: int = 10) -> Tuple[Params, Dict[str, float]]:
-    """Return params with the fastest (brick, lds_kb, tpa) and the timings (ms/step)."""
+             limit: int = 10, lds_kb: Sequence[int] = (40, 48, 56, 64)) -> Tuple[Params, Dict[str, float]]:
+    """Return params with the fastest (brick, lds_kb, tpa) and the timings
+    (ms/step); lds_kb: the staging budgets (KiB) the candidates may use."""
     n = pos4.shape[0]
     key = cache_key(n, box, params)
     if cache and os.path.exists(cache):
@@ -122,7 +123,7 @@ def autotune(pos4, box, params: Params, steps: int = 3, cache: Optional[str] = N
     force4 = torch.zeros((n, 4), dtype=torch.float64 if params.precision == 1 else torch.float32,
                          device=pos4.device)
     # the library's own choice (brick (0, 0, 0), default LDS budget and lanes) is always timed
-    trials = [((0, 0, 0), 0, 0)] + [c for c in candidates(n, box, params, limit=limit)
+    trials = [((0, 0, 0), 0, 0)] + [c for c in candidates(n, box, params, lds_kb=lds_kb, limit=limit)
                                     if c != (tuple(params.brick), params.lds_kb, params.tpa)]
     for b, kb, tpa in trials:
         trial = replace(params, brick=b, lds_kb=kb, tpa=tpa)

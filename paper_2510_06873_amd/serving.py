@@ -37,7 +37,7 @@ from __future__ import annotations
 
 import time
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -153,6 +153,44 @@ class _Retiring:
     V: object                   # pinned (W,) biases
     rows: list                  # row of each walker in s / V
     forces: list                # pinned force copies (keep_forces) or None
+
+
+def tune_requests(requests: List[Request], cache: Optional[str] = None, steps: int = 5, limit: int = 6,
+                  device=None) -> Tuple[List[Request], dict]:
+    """The autotuner's brick shape and lanes per atom, chosen once per tuning
+    class (CV kind, precision, cutoff, walker size class and atoms per cell
+    rounded to an integer) on the largest request of the class and given to
+    every request of the class.  The LDS budget stays the library's: a batched
+    pass runs every walker of a CV kind with the largest staging any of them
+    asks for, so a smaller budget for one walker would not take effect.
+    Returns the tuned requests and the choice per class."""
+    from dataclasses import replace
+
+    import torch
+
+    from .autotune import autotune, cells_per_axis, size_class
+
+    def key_of(r):
+        p = r.params
+        rho = r.n / float(np.prod(cells_per_axis(r.box, p.r_c + p.skin)))
+        return f"kind{p.cv_kind}-p{p.precision}-rc{p.r_c:g}-size{size_class(r.n)}-rho{round(rho)}"
+
+    dev = device or torch.device("cuda", 0)
+    largest = {}
+    for r in requests:
+        k = key_of(r)
+        if k not in largest or r.n > largest[k].n:
+            largest[k] = r
+    chosen = {}
+    for k, r in largest.items():
+        pos4 = torch.from_numpy(np.ascontiguousarray(r.pos, np.float32)).to(dev)
+        tuned, _ = autotune(pos4, r.box, r.params, steps=steps, cache=cache, limit=limit, lds_kb=(80,))
+        chosen[k] = (tuple(tuned.brick), tuned.tpa)
+    out = []
+    for r in requests:
+        b, tpa = chosen[key_of(r)]
+        out.append(replace(r, params=replace(r.params, brick=b, tpa=tpa), pinned=None))
+    return out, chosen
 
 
 def _wider(req: Request) -> Request:

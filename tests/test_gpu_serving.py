@@ -67,3 +67,30 @@ def test_overflowing_walker_is_run_again_with_wider_rows():
         a = alone[r.rid]
         assert np.array_equal(r.s, a.s) and r.V == a.V, r.rid
         assert np.array_equal(r.forces, a.forces), r.rid
+
+
+def test_tuned_requests_match_untuned_and_serve_bitwise_alone():
+    """Requests tuned per class (brick shape and lanes per atom): served in
+    the mix they equal their own sequential run bitwise, and they agree with
+    the library's default geometry within the FP32 bars (the geometry only
+    reorders the sums)."""
+    from paper_2510_06873_amd.serving import serve_batched, serve_sequential, tune_requests
+
+    reqs = requests(8)
+    for r in reqs:
+        r.steps = 12
+    tuned, chosen = tune_requests(reqs, steps=2, limit=3)
+    assert len(tuned) == len(reqs) and chosen
+    for r, t in zip(reqs, tuned):
+        assert t.rid == r.rid and t.params.cv_kind == r.params.cv_kind and t.params.lds_kb == r.params.lds_kb
+    rt, _ = serve_batched(tuned, hbm_budget=64 << 30, max_slots=4, keep_forces=True)
+    ra, _ = serve_sequential(tuned, keep_forces=True)
+    rd, _ = serve_batched(reqs, hbm_budget=64 << 30, max_slots=4, keep_forces=True)
+    alone = {r.rid: r for r in ra}
+    default = {r.rid: r for r in rd}
+    for r in rt:
+        a, d = alone[r.rid], default[r.rid]
+        assert np.array_equal(r.s, a.s) and r.V == a.V and np.array_equal(r.forces, a.forces), r.rid
+        assert np.allclose(r.s, d.s, rtol=1e-5, atol=1e-6), r.rid
+        f, fd = r.forces[:, :3].astype(np.float64), d.forces[:, :3].astype(np.float64)
+        assert np.max(np.abs(f - fd)) <= 1e-4 * max(np.max(np.abs(fd)), 1.0), r.rid
