@@ -112,6 +112,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="wz1m")
     ap.add_argument("--graph", action="store_true", help="replay each window as a captured HIP graph")
+    ap.add_argument("--no-graph-too", dest="graph_too", action="store_false",
+                    help="skip the graph-replayed windows timed after the eager ones")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving workload")
     ap.add_argument("--autograd", action="store_true",
@@ -188,8 +190,20 @@ def setup(wl_name, args=None):
     return dict(wl=wl, d=d, n=n, pipe=pipe, pos4=pos4, F=F, stream=stream, cen=cen, box=d["box"], tuned=tuned)
 
 
-def window(S, ev=None):
-    """One window; ev collects (name, start, end) event pairs."""
+CALLS_PER_WINDOW = 2 + 4 * MD_STEPS_PER_WINDOW
+
+
+def event_pool(count):
+    """Timing events created ahead of the timed region (creating an event
+    costs host time that would otherwise sit between the launches)."""
+    import torch
+
+    return [torch.cuda.Event(enable_timing=True) for _ in range(count)]
+
+
+def window(S, ev=None, pool=None):
+    """One window; ev collects (name, start, end) event pairs, taken from
+    pool (a list, consumed from the end) when given."""
     import torch
 
     pipe, pos4, F, box = S["pipe"], S["pos4"], S["F"], S["box"]
@@ -198,8 +212,11 @@ def window(S, ev=None):
         if ev is None:
             fn(*a)
             return
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        if pool:
+            e0, e1 = pool.pop(), pool.pop()
+        else:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
         e0.record(S["stream"])
         fn(*a)
         e1.record(S["stream"])
@@ -501,22 +518,53 @@ def main():
         S["pipe"].check()
         log(f"[bench] warmup done ({args.warmup} windows)")
         ev = [] if graph is None else None
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        pool = event_pool(2 * CALLS_PER_WINDOW * args.steps) if graph is None else None
+        e_win = event_pool(args.steps)  # an event at every window boundary (per-window spread)
         e_start = torch.cuda.Event(enable_timing=True)
         e_stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         e_start.record(stream)
-        for _ in range(args.steps):
+        for i in range(args.steps):
             if graph is not None:
                 graph.replay()
             else:
-                window(S, ev)
+                window(S, ev, pool)
+            e_win[i].record(stream)
         e_stop.record(stream)
         stream.synchronize()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
     S["pipe"].check()
     gpu_ms = e_start.elapsed_time(e_stop)
+    win_ms = [e_start.elapsed_time(e_win[0])] + [a.elapsed_time(b) for a, b in zip(e_win, e_win[1:])]
+    spread = {"median": round(float(np.median(win_ms)), 4), "p10": round(float(np.percentile(win_ms, 10)), 4),
+              "p90": round(float(np.percentile(win_ms, 90)), 4)}
+    graph_line = None
+    if graph is None and args.graph_too:
+        # the same window captured once as a HIP graph and replayed (no
+        # per-call events can be recorded inside a graph on this runtime)
+        with torch.cuda.stream(stream):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                window(S)
+            for _ in range(2):
+                g.replay()
+            stream.synchronize()
+            ge = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+            ge[0].record(stream)
+            for i in range(args.steps):
+                g.replay()
+                ge[i + 1].record(stream)
+            stream.synchronize()
+        S["pipe"].check()
+        gw = [a.elapsed_time(b) for a, b in zip(ge, ge[1:])]
+        gmean = ge[0].elapsed_time(ge[-1]) / args.steps
+        graph_line = {"ms_per_step": round(gmean, 4), "value": n * MD_STEPS_PER_WINDOW / (gmean * 1e-3),
+                      "window_ms": {"median": round(float(np.median(gw)), 4),
+                                    "p10": round(float(np.percentile(gw, 10)), 4),
+                                    "p90": round(float(np.percentile(gw, 90)), 4)}}
+        log(f"[bench] graph-replayed windows: {gmean:.3f} ms each")
     ms_per_window = gpu_ms / args.steps
     atom_steps = n * MD_STEPS_PER_WINDOW * args.steps
     value = atom_steps / (gpu_ms / 1e3)
@@ -571,6 +619,8 @@ def main():
                                f"apply_bias_forces) + 1 deposit",
                    "atoms": n, "md_steps_per_step": MD_STEPS_PER_WINDOW, "graph": bool(args.graph),
                    "neighbor_entries": int(total_entries), "autotuned": S["tuned"]},
+        "window_ms": spread,
+        "graph_replay": graph_line,
         "per_call_us": {k: round(v, 2) for k, v in per_call_us.items()},
         "roofline": roofline,
         "step_hbm": {"achieved_gbs": round(step_hbm, 1), "peak_gbs": HBM_PEAK_GBS,
