@@ -297,8 +297,9 @@ int gm_batch_destroy(gm_batch* batch);
  * stay, so a serving loop whose active set changes every few steps neither
  * frees nor reallocates device memory per change.  A context must be removed
  * by an update (or the batch destroyed) before the context is destroyed.
- * On GM_ERR_INVALID_ARG the batch keeps its previous members.  Every member
- * must have the batch's precision; new members are bound to its stream. */
+ * On GM_ERR_INVALID_ARG the batch keeps its previous members; on GM_ERR_OOM
+ * or GM_ERR_HIP it is left with none.  Every member must have the batch's
+ * precision; new members are bound to its stream. */
 int gm_batch_update(gm_batch* batch, gm_ctx* const* walkers, int32_t count, const float* const* pos4,
                     void* const* force4);
 

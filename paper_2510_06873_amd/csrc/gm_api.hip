@@ -1368,7 +1368,18 @@ int set_members(gm_batch* B, gm_ctx* const* walkers, int32_t count, const float*
     append(vals, c->V_int);
     append(vals, c->dV_int);
   }
-  return upload_into(vals, &B->d_vals, &B->c_vals, B->stream);
+  const int rc = upload_into(vals, &B->d_vals, &B->c_vals, B->stream);
+  if (rc != GM_OK) {
+    // no table of value pointers for these members: leave the batch empty
+    B->walkers.clear();
+    B->pos.clear();
+    B->force.clear();
+    for (auto& g : B->groups) {
+      g.members.clear();
+      g.dirty = true;
+    }
+  }
+  return rc;
 }
 
 }  // namespace

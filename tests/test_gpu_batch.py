@@ -288,6 +288,7 @@ def test_batch_build_some_bitwise_equals_solo():
     batch.build_some(order, [ws[k][1]["box"] for k in order], stream=side)
     batch.stream.wait_stream(side)
     batch.step()
+    s_b = batch.values()[0].cpu().numpy()
     torch.cuda.synchronize()
     for k, (pipe, p4, F) in enumerate(made):
         assert pipe.status(True) == 0, k
@@ -300,6 +301,59 @@ def test_batch_build_some_bitwise_equals_solo():
         # entries past a row's count are not written by the copy
         used = np.arange(nbr.shape[1])[None, :] < np.minimum(cnt, nbr.shape[1])[:, None]
         assert np.array_equal(nbr[used], nbr0[used]), k
-        assert np.array_equal(pipe.s.cpu().numpy()[:pipe.dims], s0[:pipe.dims]), k
+        assert np.array_equal(s_b[k, :pipe.dims], s0[:pipe.dims]), k
+        assert np.array_equal(F.cpu().numpy(), F0), k
+    batch.close()
+
+
+def test_batch_build_some_fp64_and_changed_box():
+    """The batched rebuild in FP64 (its gather and neighbour rows in double),
+    and a walker rebuilt with a different box (new cell geometry: its device
+    argument block is rewritten), both bitwise equal to gm_build_neighbors."""
+    from paper_2510_06873_amd import Batch
+
+    dev = torch.device("cuda", 0)
+    wl = W.WORKLOADS["fcc864"]
+    ds = [W.fcc_jittered(n=6, a=3.615, jitter=0.1, seed=s) for s in (1, 2, 3)]
+    # the same atoms in a box 6% larger on x: other cells, same pairs
+    big = dict(ds[2])
+    big["box"] = np.asarray(big["box"], np.float64) * np.array([1.06, 1.0, 1.0])
+
+    def lists(pipe):
+        _, perm, start = pipe.cell_list()
+        nbr, cnt = pipe.neighbor_lists()
+        cnt, nbr = cnt.cpu().numpy(), nbr.cpu().numpy()
+        used = np.arange(nbr.shape[1])[None, :] < np.minimum(cnt, nbr.shape[1])[:, None]
+        return perm.cpu().numpy(), start.cpu().numpy(), cnt, nbr[used]
+
+    def setup64(d, k):
+        pipe, p4, F = setup(wl, d, dev, k)
+        return pipe, p4, F.to(pipe.fdtype)
+
+    solo, hills = [], []
+    for k, d in enumerate(ds[:2] + [big]):
+        pipe, p4, F = setup64(d, k)
+        hills.append(pipe.hills_get())
+        pipe.step(p4, F)
+        torch.cuda.synchronize()
+        solo.append((lists(pipe), pipe.s.cpu().numpy().copy(), F.cpu().numpy().copy()))
+        pipe.close()
+    made = [setup64(d, k) for k, d in enumerate(ds)]
+    for (pipe, _, _), (cen, hts) in zip(made, hills):
+        pipe.hills_set(cen, hts)  # walker 2's hills were placed around its CV in the larger box
+    assert all(m[0].fdtype == torch.float64 for m in made)
+    batch = Batch([m[0] for m in made], [m[1] for m in made], [m[2] for m in made])
+    batch.build_some([0, 1, 2], [ds[0]["box"], ds[1]["box"], ds[2]["box"]])  # argument blocks uploaded
+    batch.build_some([2, 0, 1], [big["box"], ds[0]["box"], ds[1]["box"]])  # walker 2: new grid
+    batch.step()
+    s_b = batch.values()[0].cpu().numpy()
+    torch.cuda.synchronize()
+    for k, (pipe, p4, F) in enumerate(made):
+        assert pipe.status(True) == 0, k
+        (perm0, start0, cnt0, nbr0), s0, F0 = solo[k]
+        perm, start, cnt, nbr = lists(pipe)
+        assert np.array_equal(perm, perm0) and np.array_equal(start, start0), k
+        assert np.array_equal(cnt, cnt0) and np.array_equal(nbr, nbr0), k
+        assert np.array_equal(s_b[k, :1], s0), k
         assert np.array_equal(F.cpu().numpy(), F0), k
     batch.close()
