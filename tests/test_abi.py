@@ -72,6 +72,24 @@ def test_null_context_calls():
         assert getattr(lib, name)(*args) == -1, name
 
 
+def test_null_batch_calls():
+    """Every batch entry point refuses a null batch (and a null output
+    handle) on the host."""
+    import paper_2510_06873_amd as P
+
+    lib = P.lib()
+    one = (C.c_int32 * 1)(0)
+    box = (C.c_double * 3)(10.0, 10.0, 10.0)
+    assert lib.gm_batch_create(None, None, 1, None, None, None) == -1
+    for name, args in [("gm_batch_destroy", [None]), ("gm_batch_update", [None, None, 0, None, None]),
+                       ("gm_batch_build", [None, box]), ("gm_batch_build_some", [None, one, 1, box, None]),
+                       ("gm_batch_step", [None]), ("gm_batch_deposit", [None]),
+                       ("gm_batch_deposit_some", [None, one, 1]), ("gm_batch_values", [None, None, None, None])]:
+        assert getattr(lib, name)(*args) == -1, name
+    h = C.c_void_p()
+    assert lib.gm_batch_create(C.byref(h), None, 1, None, None, None) == -1 and not h.value
+
+
 def test_small_cv_calls_reject_bad_arguments_on_host():
     """Argument checks of the context-free calls run before any device work."""
     import ctypes as C
