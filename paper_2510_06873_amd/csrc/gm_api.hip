@@ -342,7 +342,7 @@ CvArgs<T> make_args(gm_ctx* c) {
   a.inv_bond_w = (T)(c->p.bond_w > 0 ? 1.0 / c->p.bond_w : 0.0);
   a.count_n0 = (T)c->p.count_n0;
   a.inv_count_w = (T)(c->p.count_w > 0 ? 1.0 / c->p.count_w : 0.0);
-  a.cn_r0inv = (T)(c->p.cn_r0 > 0 ? 1.0 / c->p.cn_r0 : 0.0);
+  a.cn_r0inv2 = (T)(c->p.cn_r0 > 0 ? 1.0 / (c->p.cn_r0 * c->p.cn_r0) : 0.0);
   a.inv_n = 1.0 / (double)c->n;
   if constexpr (sizeof(T) == 4)
     a.yc = c->ycf;

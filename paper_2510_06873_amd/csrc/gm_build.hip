@@ -449,8 +449,8 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
   const float lo2 = (float)(rl2 * (1.0 - 4e-6)), hi2 = (float)(rl2 * (1.0 + 4e-6));
   const int lane = (int)(threadIdx.x & 63);
   const int lig = lane & (kBuildGroup - 1);
-  const uint64_t gmask = ((1ull << kBuildGroup) - 1) << (lane - lig);
-  const uint64_t below = gmask & ((1ull << lane) - 1);
+  const int gshift = lane - lig;                  // the group's first lane
+  const uint32_t below = (1u << lig) - 1u;        // lanes of the group before this one
   const int32_t groups = (int32_t)(blockDim.x / kBuildGroup);
   const int32_t tsh = g.tpa == 4 ? 2 : (g.tpa == 2 ? 1 : 0);
   const int32_t cap = g.build_cap;
@@ -467,9 +467,11 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
     int32_t count = 0;  // the same in every lane of the group
     // entry e goes to sub-row e % TPA at index x = e / TPA: piece x / 8 of
     // that sub-row, pieces pstride8 entries apart (32-bit offsets from the
-    // atom's first piece)
-    uint16_t* const row0 = nbr + row_first(g, ob, k, 0);
-    const int32_t pstride8 = piece_stride(g, O) * 8;
+    // brick's first piece)
+    uint16_t* const brow = nbr + row_first(g, ob, 0, 0);
+    const uint32_t row0 = (uint32_t)(k * g.tpa * 8);
+    const uint32_t pstride8 = (uint32_t)(piece_stride(g, O) * 8);
+    const uint32_t pmask = (uint32_t)(g.tpa - 1);
     for (int cz = -1; cz <= 1; cz++)
       for (int cy = -1; cy <= 1; cy++) {
         const int h = hc + cz * hxy + cy * hx;  // middle cell of the x-run
@@ -506,15 +508,16 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
               in = d0 * d0 + d1 * d1 + d2 * d2 < rl2;
             }
           }
-          const uint64_t m = __ballot(in);
+          // the group's ballot bits
+          const uint32_t m8 = (uint32_t)(__ballot(in) >> gshift) & ((1u << kBuildGroup) - 1u);
           if (in) {
-            const int32_t e = count + __popcll(m & below);
+            const int32_t e = count + __popc(m8 & below);
             if (e < kmax) {
-              const int32_t x = e >> tsh;
-              row0[(e & (g.tpa - 1)) * 8 + (x >> 3) * pstride8 + (x & 7)] = (uint16_t)sl;
+              const uint32_t x = (uint32_t)e >> tsh;
+              brow[row0 + ((uint32_t)e & pmask) * 8u + (x >> 3) * pstride8 + (x & 7u)] = (uint16_t)sl;
             }
           }
-          count += __popcll(m & gmask);
+          count += __popc(m8);
         }
       }
     const int32_t stored = count < kmax ? count : kmax;

@@ -451,12 +451,22 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
     uint16_t* crow = a.cut + row_first(a.bg, k.ob, o, part);
     const uint16_t* nrow = a.nbr + row_first(a.bg, k.ob, o, part);
     const int32_t ps = piece_stride(a.bg, k.O);
+    // The coordination terms are summed here, on the in-cutoff pairs as they
+    // are found: 1/(1 + u^3) with u = (r/r0)^2 needs r^2 only.
     SlotWriter wr;
     wr.init(crow, ps);
+    T cnsum = T(0);
     for_slots<true>(nrow, cp, ps, first_chunk(nrow, cp), [&](int32_t s) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
-      if (pair_vec<WRAP>(pi, pj, a, dx, dy, dz) < a.rc2) wr.push(s);
+      const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
+      if (r2 < a.rc2) {
+        wr.push(s);
+        if (CN) {
+          const T u = r2 * a.cn_r0inv2;
+          cnsum += g_rcp(T(1) + u * u * u);
+        }
+      }
     });
     if (TPA == 2)
       balance_pair(wr);
@@ -478,25 +488,19 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
     T Q[13];
 #pragma unroll
     for (int m = 0; m < 13; m++) Q[m] = T(0);
-    T fsum = T(0), cnsum = T(0);
-    for_slots<true>(crow, nc, ps, first_chunk(crow, nc), [&](int32_t s) {
-      const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
-      T dx, dy, dz;
-      const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
-      const T rinv = g_rsqrt(r2);
-      const T r = r2 * rinv;
-      if (Q6) {
+    T fsum = T(0);
+    if (Q6)
+      for_slots<true>(crow, nc, ps, first_chunk(crow, nc), [&](int32_t s) {
+        const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
+        T dx, dy, dz;
+        const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
+        const T rinv = g_rsqrt(r2);
+        const T r = r2 * rinv;
         T df;
         const T f = taper_w(r, a, df);
         accumulate_y(a.yc, dx * rinv, dy * rinv, dz * rinv, f, Q);
         fsum += f;
-      }
-      if (CN) {
-        const T x = r * a.cn_r0inv;
-        const T x2 = x * x;
-        cnsum += g_rcp(T(1) + x2 * x2 * x2);
-      }
-    });
+      });
     if (Q6) {
 #pragma unroll
       for (int m = 0; m < 13; m++) Q[m] = group_sum(Q[m], TPA);
@@ -712,14 +716,14 @@ __device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, 
       ay += py;
       az += pz;
       if (CN) {
-        const T x = r * a.cn_r0inv;
-        const T x2 = x * x;
-        const T x5 = x2 * x2 * x;
-        const T den = T(1) + x5 * x;
-        const T swp = T(-6) * x5 * a.cn_r0inv * g_rcp(den * den);
-        cx += swp * ux;
-        cy += swp * uy;
-        cz += swp * uz;
+        // d/dr of 1/(1 + u^3), u = (r/r0)^2: -6 u^2 / (r0^2 (1 + u^3)^2) times r
+        const T u = r2 * a.cn_r0inv2;
+        const T u2 = u * u;
+        const T den = T(1) + u2 * u;
+        const T swp = T(-6) * a.cn_r0inv2 * u2 * g_rcp(den * den);
+        cx += swp * dx;
+        cy += swp * dy;
+        cz += swp * dz;
       }
     });
     ax = group_sum(ax, TPA);
@@ -772,12 +776,10 @@ __device__ __forceinline__ void cn_force_atoms(const CvArgs<T>& a, const Brick& 
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
-      const T rinv = g_rsqrt(r2);
-      const T x = r2 * rinv * a.cn_r0inv;
-      const T x2 = x * x;
-      const T x5 = x2 * x2 * x;
-      const T den = T(1) + x5 * x;
-      const T swp = T(-6) * x5 * a.cn_r0inv * g_rcp(den * den) * rinv;
+      const T u = r2 * a.cn_r0inv2;
+      const T u2 = u * u;
+      const T den = T(1) + u2 * u;
+      const T swp = T(-6) * a.cn_r0inv2 * u2 * g_rcp(den * den);
       cx += swp * dx;
       cy += swp * dy;
       cz += swp * dz;

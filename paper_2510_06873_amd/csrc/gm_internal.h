@@ -127,7 +127,7 @@ struct CvArgs {
   T L[3], invL[3], Llo[3];  // box, 1/box, and the low part of box in T
   T rc2, taper_lo, pi_over_D, half_pi_over_D;
   T bond_d0, inv_bond_w, count_n0, inv_count_w;
-  T cn_r0inv;
+  T cn_r0inv2;  // 1/r0^2 of the coordination switch
   double inv_n;
   YCoef<T> yc;
   T* qrow;          // [N][16] by sorted position: qhat(13), |Q|, c', sum f
