@@ -43,7 +43,7 @@ struct gm_ctx {
   uint16_t *nbr = nullptr, *cut = nullptr;
   int32_t *cnt = nullptr, *ccnt = nullptr, *err = nullptr, *stats = nullptr;
   int4* order = nullptr;  // per brick, by rank: (atom, halo slot, sorted position, 0)
-  void *pos_s = nullptr, *qrow = nullptr, *grow = nullptr, *nb = nullptr, *cn_atom = nullptr;
+  void *pos_s = nullptr, *qrow = nullptr, *grow = nullptr, *nb = nullptr, *cn_atom = nullptr, *cn_grad = nullptr;
   double *part_a = nullptr, *part_b = nullptr, *s_int = nullptr, *V_int = nullptr, *dV_int = nullptr;
   double *centres = nullptr, *heights = nullptr, *bias_part = nullptr;
   int64_t* hill_count = nullptr;
@@ -352,6 +352,7 @@ CvArgs<T> make_args(gm_ctx* c) {
   a.grow = reinterpret_cast<T*>(c->grow);
   a.nb = reinterpret_cast<T*>(c->nb);
   a.cn_atom = reinterpret_cast<T*>(c->cn_atom);
+  a.cn_grad = reinterpret_cast<T*>(c->cn_grad);
   a.part_a = c->part_a;
   a.part_b = c->part_b;
   a.s_int = c->s_int;
@@ -495,7 +496,7 @@ void free_all(gm_ctx* c) {
   c->cell = c->perm = c->owned_slot = c->owned_rank = c->owned_hcell = c->cnt = c->ccnt = nullptr;
   c->err = c->stats = nullptr;
   c->order = nullptr;
-  c->pos_s = c->nb = c->cn_atom = c->qrow = c->grow = nullptr;
+  c->pos_s = c->nb = c->cn_atom = c->cn_grad = c->qrow = c->grow = nullptr;
   c->s_int = c->V_int = c->dV_int = c->centres = c->heights = c->bias_part = nullptr;
   c->part_a = c->part_b = nullptr;
   c->hill_count = nullptr;
@@ -631,6 +632,7 @@ int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_
       {(void**)&c->owned_rank, n * 4}, {(void**)&c->owned_hcell, n * 4}, {(void**)&c->cnt, n * 4},
       {(void**)&c->ccnt, n * 4 * 4},  // up to 4 parts per atom
       {(void**)&c->order, n * 16},   {(void**)&c->pos_s, n * 4 * T},
+      {(void**)&c->cn_grad, c->has_cn ? n * 4 * T : 16},
       {(void**)&c->centres, cap * c->dims * 8}, {(void**)&c->heights, cap * 8},
       {(void**)&c->bias_part, (size_t)c->bias_blocks * 3 * 8},
       {(void**)&c->build_dev, sizeof(BuildArgs)},

@@ -452,10 +452,13 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
     const uint16_t* nrow = a.nbr + row_first(a.bg, k.ob, o, part);
     const int32_t ps = piece_stride(a.bg, k.O);
     // The coordination terms are summed here, on the in-cutoff pairs as they
-    // are found: 1/(1 + u^3) with u = (r/r0)^2 needs r^2 only.
+    // are found: 1/(1 + u^3) with u = (r/r0)^2 needs r^2 only, and so does
+    // its gradient, which does not depend on the bias and is kept for the
+    // force pass: sum_j -6/r0^2 u^2/(1 + u^3)^2 (x_j - x_i).
     SlotWriter wr;
     wr.init(crow, ps);
-    T cnsum = T(0);
+    T cnsum = T(0), gx = T(0), gy = T(0), gz = T(0);
+    const T gscale = T(-6) * a.cn_r0inv2;
     for_slots<true>(nrow, cp, ps, first_chunk(nrow, cp), [&](int32_t s) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
@@ -464,7 +467,13 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
         wr.push(s);
         if (CN) {
           const T u = r2 * a.cn_r0inv2;
-          cnsum += g_rcp(T(1) + u * u * u);
+          const T f = g_rcp(T(1) + u * u * u);
+          cnsum += f;
+          const T w = u * f;
+          const T swp = gscale * w * w;
+          gx += swp * dx;
+          gy += swp * dy;
+          gz += swp * dz;
         }
       }
     });
@@ -506,7 +515,12 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
       for (int m = 0; m < 13; m++) Q[m] = group_sum(Q[m], TPA);
       fsum = group_sum(fsum, TPA);
     }
-    if (CN) cnsum = group_sum(cnsum, TPA);
+    if (CN) {
+      cnsum = group_sum(cnsum, TPA);
+      gx = group_sum(gx, TPA);
+      gy = group_sum(gy, TPA);
+      gz = group_sum(gz, TPA);
+    }
     if (part == 0) {
       if (Q6) {
         T qq = T(0);
@@ -524,6 +538,12 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
       }
       if (CN) {
         a.cn_atom[ri] = cnsum;
+        vec4_t<T> gv;
+        gv.x = gx;
+        gv.y = gy;
+        gv.z = gz;
+        gv.w = T(0);
+        reinterpret_cast<vec4_t<T>*>(a.cn_grad)[ri] = gv;
         cn_part += (double)cnsum;
       }
     }
@@ -689,7 +709,6 @@ __device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, 
     T gi[16];
     fetch_rec<ALL>(a, k, lr, a.grow, si, pi, gi);
     T ax = T(0), ay = T(0), az = T(0);
-    T cx = T(0), cy = T(0), cz = T(0);
     walk_records<ALL>(a, k, lr, a.grow, a.cut + row_first(a.bg, k.ob, o, part), nc, piece_stride(a.bg, k.O), h.c0, [&](const vec4_t<T>& pj, const T* gj) {
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
@@ -715,25 +734,10 @@ __device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, 
       ax += px;
       ay += py;
       az += pz;
-      if (CN) {
-        // d/dr of 1/(1 + u^3), u = (r/r0)^2: -6 u^2 / (r0^2 (1 + u^3)^2) times r
-        const T u = r2 * a.cn_r0inv2;
-        const T u2 = u * u;
-        const T den = T(1) + u2 * u;
-        const T swp = T(-6) * a.cn_r0inv2 * u2 * g_rcp(den * den);
-        cx += swp * dx;
-        cy += swp * dy;
-        cz += swp * dz;
-      }
     });
     ax = group_sum(ax, TPA);
     ay = group_sum(ay, TPA);
     az = group_sum(az, TPA);
-    if (CN) {
-      cx = group_sum(cx, TPA);
-      cy = group_sum(cy, TPA);
-      cz = group_sum(cz, TPA);
-    }
     if (part == 0) {
       // the taper radial sum: the last lanes of the atom's own record, read
       // again here rather than held through the walk
@@ -743,7 +747,12 @@ __device__ __forceinline__ void pass4_atoms(const CvArgs<T>& a, const Brick& k, 
       ax += go[13];
       ay += go[14];
       az += go[15];
-      write_out(a, ri, -(seed_q * ax + seed_cn * cx), -(seed_q * ay + seed_cn * cy), -(seed_q * az + seed_cn * cz));
+      // the coordination gradient, kept by the forward pass
+      vec4_t<T> cg;
+      cg.x = cg.y = cg.z = cg.w = T(0);
+      if (CN) cg = reinterpret_cast<const vec4_t<T>*>(a.cn_grad)[ri];
+      write_out(a, ri, -(seed_q * ax + seed_cn * cg.x), -(seed_q * ay + seed_cn * cg.y),
+                -(seed_q * az + seed_cn * cg.z));
     }
   }
 }
@@ -763,46 +772,21 @@ __device__ __forceinline__ void pass4_body(const CvArgs<T>& a, int64_t brick, in
 }
 
 // --------------------------------------------------------------------------
-// Coordination number alone: forces over the in-cutoff slots of pass 1.
+// Coordination number alone: the forces are the seed times the gradient that
+// pass 1 kept per atom (ds/dx_i = (2/N) sum_j f'(r_ij) (x_i - x_j)/r_ij, both
+// orders of each pair), one thread per owned atom of the brick.
 // --------------------------------------------------------------------------
-template <typename T, bool ALL, bool WRAP>
-__device__ __forceinline__ void cn_force_atoms(const CvArgs<T>& a, const Brick& k, const vec4_t<T>* lp,
-                                               const AtomHead& h0) {
-  const T seed = (T)((a.seed ? a.seed[0] : 1.0) * 2.0 * a.inv_n);
-  GM_FOR_RANKED(a, k, h0) {
-    const vec4_t<T> pi = fetch_pos<ALL>(a, k, lp, si);
-    T cx = T(0), cy = T(0), cz = T(0);
-    for_slots<true>(a.cut + row_first(a.bg, k.ob, o, part), nc, piece_stride(a.bg, k.O), h.c0, [&](int32_t s) {
-      const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
-      T dx, dy, dz;
-      const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
-      const T u = r2 * a.cn_r0inv2;
-      const T u2 = u * u;
-      const T den = T(1) + u2 * u;
-      const T swp = T(-6) * a.cn_r0inv2 * u2 * g_rcp(den * den);
-      cx += swp * dx;
-      cy += swp * dy;
-      cz += swp * dz;
-    });
-    cx = group_sum(cx, TPA);
-    cy = group_sum(cy, TPA);
-    cz = group_sum(cz, TPA);
-    if (part == 0) write_out(a, ri, -seed * cx, -seed * cy, -seed * cz);
-  }
-}
-
 template <typename T>
 __device__ __forceinline__ void cn_force_body(const CvArgs<T>& a, int64_t brick, int32_t blk, int32_t nblk) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  vec4_t<T>* lp = reinterpret_cast<vec4_t<T>*>(smem);
-  const Brick k = brick_begin(a, brick);
-  AtomHead h0 = head_begin(a, k);
-  stage_pos(a, k, lp);
-  head_end(a, k, h0);
-  __syncthreads();
-  brick_variant(a, k, [&](auto all, auto wrap) {
-    cn_force_atoms<T, decltype(all)::value, decltype(wrap)::value>(a, k, lp, h0);
-  });
+  if (brick >= a.bg.nbricks) return;
+  const int32_t ob = a.bi.ob[brick], O = a.bi.ob[brick + 1] - ob;
+  const T seed = (T)((a.seed ? a.seed[0] : 1.0) * 2.0 * a.inv_n);
+  const vec4_t<T>* g = reinterpret_cast<const vec4_t<T>*>(a.cn_grad);
+  for (int32_t o = (int32_t)threadIdx.x; o < O; o += (int32_t)blockDim.x) {
+    const int32_t ri = a.bi.owned_rank[ob + o];
+    const vec4_t<T> v = g[ri];
+    write_out(a, ri, -seed * v.x, -seed * v.y, -seed * v.z);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -922,7 +906,7 @@ hipError_t launch_cn_forward(const CvArgs<T>& a, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_cn_force(const CvArgs<T>& a, hipStream_t st) {
-  k_cn_force<T><<<(unsigned)a.bg.blocks, BrickBlock<T>::value, lds_bytes(a, false), st>>>(a);
+  k_cn_force<T><<<(unsigned)a.bg.blocks, BrickBlock<T>::value, 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -969,7 +953,7 @@ hipError_t launch_pass_batch(int pass, bool with_cn, bool fp_rows, const CvArgs<
       k_finish_batch<T, false, true><<<(unsigned)W, kBlock, 0, st>>>(tab);
       break;
     case 6:  // coordination alone: forces
-      k_cn_force_batch<T><<<g, BrickBlock<T>::value, lds_pos, st>>>(tab, blk_start, W);
+      k_cn_force_batch<T><<<g, BrickBlock<T>::value, 0, st>>>(tab, blk_start, W);
       break;
     default:
       return hipErrorInvalidValue;

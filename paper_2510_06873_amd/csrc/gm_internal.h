@@ -134,6 +134,7 @@ struct CvArgs {
   T* grow;          // [N][16]: g(13), then the sum over taper pairs of (c'_i + c'_j) b_ij f'(r) r_hat (3)
   T* nb;            // [N] bond counts
   T* cn_atom;       // [N] per-atom coordination sums
+  T* cn_grad;       // [N][4] per-atom coordination gradient sum_j f'(r) r_hat (w = 0)
   double* part_a;   // per-workgroup FP64 partial sums (count / coordination)
   double* part_b;
   double* s_out;    // caller's s (dev), may be NULL
