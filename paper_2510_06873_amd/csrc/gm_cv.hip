@@ -455,8 +455,11 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
     // are found: 1/(1 + u^3) with u = (r/r0)^2 needs r^2 only, and so does
     // its gradient, which does not depend on the bias and is kept for the
     // force pass: sum_j -6/r0^2 u^2/(1 + u^3)^2 (x_j - x_i).
+    // The in-cutoff rows (and the ranking below) serve the q6 passes 2-4
+    // only; the coordination CV alone keeps just their lengths.
     SlotWriter wr;
     wr.init(crow, ps);
+    int32_t ncut = 0;
     T cnsum = T(0), gx = T(0), gy = T(0), gz = T(0);
     const T gscale = T(-6) * a.cn_r0inv2;
     for_slots<true>(nrow, cp, ps, first_chunk(nrow, cp), [&](int32_t s) {
@@ -464,7 +467,10 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
       T dx, dy, dz;
       const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       if (r2 < a.rc2) {
-        wr.push(s);
+        if (Q6)
+          wr.push(s);
+        else
+          ncut++;
         if (CN) {
           const T u = r2 * a.cn_r0inv2;
           const T f = g_rcp(T(1) + u * u * u);
@@ -477,16 +483,18 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
         }
       }
     });
-    if (TPA == 2)
-      balance_pair(wr);
-    else
-      wr.flush();
-    const int32_t nc = wr.n;
+    if (Q6) {
+      if (TPA == 2)
+        balance_pair(wr);
+      else
+        wr.flush();
+    }
+    const int32_t nc = Q6 ? wr.n : ncut;
     a.ccnt[(int64_t)(k.ob + o) * TPA + part] = nc;
     int32_t longest = nc;
     if (TPA >= 2) longest = max(longest, quad_xor<kQuadXor1>(longest));
     if (TPA >= 4) longest = max(longest, quad_xor<kQuadXor2>(longest));
-    if (part == 0 && o < BrickBlock<T>::value) {
+    if (Q6 && part == 0 && o < BrickBlock<T>::value) {
       keys[o] = longest;
       int32_t* sr = keys + BrickBlock<T>::value * (1 + kRankBins / 64) + kRankBins;
       sr[2 * o] = si;
@@ -567,7 +575,7 @@ __device__ __forceinline__ void pass1_body(const CvArgs<T>& a, int64_t brick, in
     const double b = block_sum(cn_part, red);
     if (threadIdx.x == 0) (Q6 ? a.part_b : a.part_a)[blk] = b;
   }
-  rank_owned(a, k, keys);
+  if (Q6) rank_owned(a, k, keys);
 }
 
 // --------------------------------------------------------------------------
