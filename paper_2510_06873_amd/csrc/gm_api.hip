@@ -106,29 +106,146 @@ hipMemPool_t device_pool() {
   return g_pool[dev];
 }
 
+// Freed blocks are kept by the library, per device, in size classes (four per
+// power of two, at least 64 KiB): a free records an event on its stream and
+// files the block; an allocation of the same class takes a filed block that
+// was freed on its own stream (stream order covers it) or whose event has
+// completed, so neither side blocks the host and no stream waits on another.
+// (The pool's own free can wait on the host for several milliseconds when the
+// pool hands a block out again, tens of milliseconds under load: in a server
+// that retires and admits many walkers at once that idled the device.)  At
+// most kCacheKeepBytes stay filed; beyond that the oldest go back to the pool,
+// on a library stream that first waits for their events.
+constexpr size_t kCacheKeepBytes = 16ull << 30;
+
+struct Filed {
+  void* p;
+  size_t cls;
+  hipStream_t st;  // the stream the block was freed on
+  hipEvent_t ev;   // recorded there at the free
+};
+
+struct BlockCache {
+  std::vector<Filed> filed;       // oldest first
+  std::vector<hipEvent_t> spare;  // events free for the next free
+  size_t filed_bytes = 0;
+  hipStream_t trim = nullptr;
+};
+
+struct HandedOut {
+  size_t cls;
+  int dev;
+};
+
+std::mutex g_cache_mu;
+BlockCache g_cache[kMaxDevices];
+std::unordered_map<void*, HandedOut> g_handed;  // every block handed out
+
+size_t size_class(size_t bytes) {
+  size_t g = 64 << 10;
+  if (bytes > (256u << 10)) {
+    const int top = 63 - __builtin_clzll((unsigned long long)bytes);
+    g = (size_t)1 << (top - 2);
+  }
+  return (bytes + g - 1) / g * g;
+}
+
+// A filed block of class cls for st, or null: first one freed on st (the
+// wait for its event then costs nothing on the device, and covers a stream
+// handle that was destroyed and created again), then one whose event has
+// completed.
+void* take_filed(BlockCache& bc, size_t cls, hipStream_t st) {
+  for (int pass = 0; pass < 2; pass++)
+    for (size_t i = 0; i < bc.filed.size(); i++) {
+      const Filed& f = bc.filed[i];
+      if (f.cls != cls) continue;
+      if (pass == 0 ? (f.st != st || hipStreamWaitEvent(st, f.ev, 0) != hipSuccess)
+                    : hipEventQuery(f.ev) != hipSuccess)
+        continue;
+      void* q = f.p;
+      bc.spare.push_back(f.ev);
+      bc.filed_bytes -= cls;
+      bc.filed.erase(bc.filed.begin() + (std::ptrdiff_t)i);
+      return q;
+    }
+  (void)hipGetLastError();  // hipEventQuery's not-ready status
+  return nullptr;
+}
+
 // Allocate in stream order on st: usable by work enqueued on st after this
 // call, and by other streams once ordered after that point.
 template <typename P>
 int dalloc(hipStream_t st, P** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GM_ERR_HIP;
+  const size_t cls = size_class(bytes);
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    if (void* q = take_filed(g_cache[dev], cls, st)) {
+      g_handed[q] = {cls, dev};
+      *p = reinterpret_cast<P*>(q);
+      return GM_OK;
+    }
+  }
   hipMemPool_t pool = device_pool();
   if (!pool) return GM_ERR_HIP;
   void* q = nullptr;
-  if (hipMallocFromPoolAsync(&q, bytes, pool, st) != hipSuccess) {
+  if (hipMallocFromPoolAsync(&q, cls, pool, st) != hipSuccess) {
     (void)hipGetLastError();
     return GM_ERR_OOM;
   }
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  g_handed[q] = {cls, dev};
   *p = reinterpret_cast<P*>(q);
   return GM_OK;
 }
 
-// Free in stream order on st: the memory returns to the pool after the work
-// already enqueued on st, which must include every use of it.
+// Free in stream order on st: the block can be handed out again once the work
+// already enqueued on st, which must include every use of it, is done.
 template <typename P>
 void dfree(hipStream_t st, P*& p) {
-  if (p) (void)hipFreeAsync(reinterpret_cast<void*>(p), st);
+  if (!p) return;
+  void* q = reinterpret_cast<void*>(p);
   p = nullptr;
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  auto it = g_handed.find(q);
+  if (it == g_handed.end()) {
+    (void)hipFreeAsync(q, st);
+    return;
+  }
+  const HandedOut h = it->second;
+  g_handed.erase(it);
+  BlockCache& bc = g_cache[h.dev];
+  hipEvent_t ev = nullptr;
+  if (!bc.spare.empty()) {
+    ev = bc.spare.back();
+    bc.spare.pop_back();
+  } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    ev = nullptr;
+  }
+  if (!ev || hipEventRecord(ev, st) != hipSuccess) {  // not filed: back to the pool
+    (void)hipGetLastError();
+    if (ev) bc.spare.push_back(ev);
+    (void)hipFreeAsync(q, st);
+    return;
+  }
+  bc.filed.push_back({q, h.cls, st, ev});
+  bc.filed_bytes += h.cls;
+  while (bc.filed_bytes > kCacheKeepBytes && !bc.filed.empty()) {
+    if (!bc.trim && hipStreamCreateWithFlags(&bc.trim, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      bc.trim = nullptr;
+      break;
+    }
+    const Filed f = bc.filed.front();
+    bc.filed.erase(bc.filed.begin());
+    bc.filed_bytes -= f.cls;
+    (void)hipStreamWaitEvent(bc.trim, f.ev, 0);
+    (void)hipFreeAsync(f.p, bc.trim);
+    bc.spare.push_back(f.ev);
+  }
 }
 
 // The same for a context's own buffers, which it counts (gm_device_bytes).
