@@ -23,7 +23,11 @@
  * be captured in a HIP graph.
  *
  * Memory: the library's device buffers come from a stream-ordered pool of its
- * own (one per device, keeping up to 4 GiB cached between uses).  Allocation
+ * own (one per device, keeping up to 4 GiB cached between uses).  A released
+ * buffer stays with the library (up to 16 GiB per device, in size classes of
+ * four per power of two; beyond that the oldest go back to the pool): it is
+ * handed out again to an allocation on the stream it was released on, or on
+ * another stream once the work before its release has completed.  Allocation
  * and release are operations on the stream the context or batch is bound to
  * at that moment, so creating and destroying them never waits for the device.
  *
@@ -124,10 +128,11 @@ typedef struct gm_ctx gm_ctx;
  * hip_stream (no wait).  *out is set to NULL on failure. */
 int gm_create(gm_ctx** out, const gm_params* params, int64_t n_atoms, void* hip_stream);
 
-/* Free everything the context owns, in stream order on the context's stream
- * (no wait): work already enqueued there may still use the buffers, and work
- * on other streams that uses them must be ordered before this call.  The
- * stream must still exist. */
+/* Release everything the context owns, in stream order on the context's
+ * stream (no wait): work already enqueued there may still use the buffers, and
+ * work on other streams that uses them must be ordered before this call.  The
+ * stream must still exist.  The buffers go back to the library's cache of
+ * released device memory (see Memory above), not to the system. */
 int gm_destroy(gm_ctx* ctx);
 
 /* Re-bind the context to another stream (e.g. a capture stream).  The caller

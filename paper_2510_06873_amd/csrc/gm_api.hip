@@ -217,6 +217,12 @@ void dfree(hipStream_t st, P*& p) {
   }
   const HandedOut h = it->second;
   g_handed.erase(it);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != h.dev) {  // filed and trimmed on its own device only
+    (void)hipGetLastError();
+    (void)hipFreeAsync(q, st);
+    return;
+  }
   BlockCache& bc = g_cache[h.dev];
   hipEvent_t ev = nullptr;
   if (!bc.spare.empty()) {
