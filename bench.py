@@ -7,7 +7,9 @@ forces N(0, 1 eV/A)):
     10 x (cv_forward, bias_eval, cv_backward, apply_bias_forces)
     1 x deposit_hill
 i.e. 10 MD steps = 10 N atom-steps.  Inputs are resident in HBM before the
-timed region.  Prints one JSON line.
+timed region.  Inside it, HIP events bracket only the force calls (their
+kernel is the roofline's); the time of every call comes from a few more
+windows timed call by call afterwards.  Prints one JSON line.
 
 The line also carries the walker-serving workload (256 requests of 1k-200k
 atoms, continuous batching against sequential launches: p50/p99 latency and
@@ -114,6 +116,8 @@ def parse():
     ap.add_argument("--graph", action="store_true", help="replay each window as a captured HIP graph")
     ap.add_argument("--no-graph-too", dest="graph_too", action="store_false",
                     help="skip the graph-replayed windows timed after the eager ones")
+    ap.add_argument("--call-windows", type=int, default=5,
+                    help="windows after the timed region with an event pair around every call (per_call_us)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving workload")
     ap.add_argument("--autograd", action="store_true",
@@ -201,15 +205,16 @@ def event_pool(count):
     return [torch.cuda.Event(enable_timing=True) for _ in range(count)]
 
 
-def window(S, ev=None, pool=None):
-    """One window; ev collects (name, start, end) event pairs, taken from
-    pool (a list, consumed from the end) when given."""
+def window(S, ev=None, pool=None, only=None):
+    """One window; ev collects (name, start, end) event pairs around the calls
+    (only those named in `only`, when given), taken from pool (a list,
+    consumed from the end) when given."""
     import torch
 
     pipe, pos4, F, box = S["pipe"], S["pos4"], S["F"], S["box"]
 
     def timed(name, fn, *a):
-        if ev is None:
+        if ev is None or (only is not None and name not in only):
             fn(*a)
             return
         if pool:
@@ -517,8 +522,12 @@ def main():
         stream.synchronize()
         S["pipe"].check()
         log(f"[bench] warmup done ({args.warmup} windows)")
+        # Inside the timed region only the force calls are bracketed by events
+        # (the roofline's k_pass4 launches): an event pair around every call
+        # adds about 0.3 ms to a 5 ms window.  The other calls are timed in
+        # instrumented windows after it.
         ev = [] if graph is None else None
-        pool = event_pool(2 * CALLS_PER_WINDOW * args.steps) if graph is None else None
+        pool = event_pool(2 * MD_STEPS_PER_WINDOW * args.steps) if graph is None else None
         e_win = event_pool(args.steps)  # an event at every window boundary (per-window spread)
         e_start = torch.cuda.Event(enable_timing=True)
         e_stop = torch.cuda.Event(enable_timing=True)
@@ -529,7 +538,7 @@ def main():
             if graph is not None:
                 graph.replay()
             else:
-                window(S, ev, pool)
+                window(S, ev, pool, only=("apply_bias_forces",))
             e_win[i].record(stream)
         e_stop.record(stream)
         stream.synchronize()
@@ -574,15 +583,30 @@ def main():
     if ev:
         for name, e0, e1 in ev:
             per_call.setdefault(name, []).append(e0.elapsed_time(e1))
-    per_call_us = {k: 1e3 * float(np.mean(v)) for k, v in per_call.items()}
+    timed_us = {k: 1e3 * float(np.mean(v)) for k, v in per_call.items()}
+    # every call of a few more windows, each bracketed by events (not part of
+    # the throughput figure)
+    per_call_us = {}
+    if graph is None and args.call_windows > 0:
+        ev2, pool2 = [], event_pool(2 * CALLS_PER_WINDOW * args.call_windows)
+        with torch.cuda.stream(stream):
+            for _ in range(args.call_windows):
+                window(S, ev2, pool2)
+            stream.synchronize()
+        S["pipe"].check()
+        calls = {}
+        for name, e0, e1 in ev2:
+            calls.setdefault(name, []).append(e0.elapsed_time(e1))
+        per_call_us = {k: round(1e3 * float(np.mean(v)), 2) for k, v in calls.items()}
 
     mx, total_entries, cut_pairs = S["pipe"].neighbor_stats(cutoff_pairs=True)
     roofline = None
-    if "apply_bias_forces" in per_call_us:
+    if "apply_bias_forces" in timed_us:
         # Dominant launch: k_pass4 (apply_bias_forces, one launch per call), bound
         # by FP32 VALU work: the fraction of the published FP32 peak, and of the
-        # ceiling without packed FP32 (which these kernels do not use).
-        t_us = per_call_us["apply_bias_forces"]
+        # ceiling without packed FP32 (which these kernels do not use).  Its
+        # average over every launch of the timed region.
+        t_us = timed_us["apply_bias_forces"]
         flops = FLOPS_PER_PAIR_P4 * cut_pairs
         achieved = flops / (t_us * 1e-6) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -621,7 +645,9 @@ def main():
                    "neighbor_entries": int(total_entries), "autotuned": S["tuned"]},
         "window_ms": spread,
         "graph_replay": graph_line,
-        "per_call_us": {k: round(v, 2) for k, v in per_call_us.items()},
+        "per_call_us": per_call_us,
+        "per_call_from": (f"{args.call_windows} windows after the timed region, an event pair around every call "
+                          f"(inside the timed region only apply_bias_forces is bracketed)"),
         "roofline": roofline,
         "step_hbm": {"achieved_gbs": round(step_hbm, 1), "peak_gbs": HBM_PEAK_GBS,
                      "frac": round(step_hbm / HBM_PEAK_GBS, 4), "bytes_per_atom_step": round(bpas, 1),
