@@ -150,25 +150,30 @@ size_t size_class(size_t bytes) {
   return (bytes + g - 1) / g * g;
 }
 
-// A filed block of class cls for st, or null: first one freed on st (the
-// wait for its event then costs nothing on the device, and covers a stream
-// handle that was destroyed and created again), then one whose event has
-// completed.
+// A filed block of class cls for st, or null: first one freed on st, then one
+// freed on another stream whose free event has completed.  A block freed on st
+// whose event is still pending comes with a wait for that event on st (a no-op
+// on the device in stream order, and correct if st is a new stream that took
+// over the handle of a destroyed one); that event is then destroyed rather than
+// recorded again, so that no later record can change what the wait refers to.
 void* take_filed(BlockCache& bc, size_t cls, hipStream_t st) {
   for (int pass = 0; pass < 2; pass++)
     for (size_t i = 0; i < bc.filed.size(); i++) {
       const Filed& f = bc.filed[i];
-      if (f.cls != cls) continue;
-      if (pass == 0 ? (f.st != st || hipStreamWaitEvent(st, f.ev, 0) != hipSuccess)
-                    : hipEventQuery(f.ev) != hipSuccess)
-        continue;
+      if (f.cls != cls || (pass == 0 && f.st != st)) continue;
+      const bool done = hipEventQuery(f.ev) == hipSuccess;
+      if (!done) {
+        (void)hipGetLastError();  // not ready is not an error here
+        if (pass == 1 || hipStreamWaitEvent(st, f.ev, 0) != hipSuccess) continue;
+        (void)hipEventDestroy(f.ev);
+      } else {
+        bc.spare.push_back(f.ev);
+      }
       void* q = f.p;
-      bc.spare.push_back(f.ev);
       bc.filed_bytes -= cls;
       bc.filed.erase(bc.filed.begin() + (std::ptrdiff_t)i);
       return q;
     }
-  (void)hipGetLastError();  // hipEventQuery's not-ready status
   return nullptr;
 }
 
@@ -250,7 +255,7 @@ void dfree(hipStream_t st, P*& p) {
     bc.filed_bytes -= f.cls;
     (void)hipStreamWaitEvent(bc.trim, f.ev, 0);
     (void)hipFreeAsync(f.p, bc.trim);
-    bc.spare.push_back(f.ev);
+    (void)hipEventDestroy(f.ev);
   }
 }
 
