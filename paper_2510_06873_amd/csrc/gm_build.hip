@@ -430,8 +430,9 @@ __global__ __launch_bounds__(kBlock) void k_brick_fill(const int32_t* __restrict
 // index e / tpa; the rest of each sub-row's last 16-byte piece is zeroed,
 // since the CV passes read rows in whole pieces.
 // MODE 0: FP32 plain differences (halo off the faces), 1: FP32 minimum image,
-// 2: FP64 only (coordinates outside the box).
-template <int MODE, typename T>
+// 2: FP64 only (coordinates outside the box).  STAGED: every halo slot of the
+// brick is in LDS (no per-candidate check for slots read from global memory).
+template <int MODE, bool STAGED, typename T>
 __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, const CellGeom& cg,
                                            const BrickGeom& g, const BrickIndex& bi, double rl2, uint16_t* nbr,
                                            int32_t kmax, int32_t* cnt, int32_t* err, const float4* hpos,
@@ -481,10 +482,15 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
           bool in = false;
           if (sl < se && sl != si) {
             // staged slots (nearly all) read LDS; the rest global memory
-            float4 pj = hpos[min(sl, cap - 1)];
-            if (sl >= cap) {
-              const vec4_t<T> p = pos_s[bi.halo_rank[hb + sl]];
-              pj = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
+            float4 pj;
+            if constexpr (STAGED) {
+              pj = hpos[sl];
+            } else {
+              pj = hpos[min(sl, cap - 1)];
+              if (sl >= cap) {
+                const vec4_t<T> p = pos_s[bi.halo_rank[hb + sl]];
+                pj = make_float4((float)p.x, (float)p.y, (float)p.z, 0.f);
+              }
             }
             float ex, ey, ez;
             if constexpr (MODE == 1) {
@@ -514,7 +520,9 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
             const int32_t e = count + __popc(m8 & below);
             if (e < kmax) {
               const uint32_t x = (uint32_t)e >> tsh;
-              brow[row0 + ((uint32_t)e & pmask) * 8u + (x >> 3) * pstride8 + (x & 7u)] = (uint16_t)sl;
+              // piece index and stride below 2^24: the full-rate 24-bit multiply
+              brow[row0 + ((uint32_t)e & pmask) * 8u + __umul24(x >> 3, pstride8) + (x & 7u)] =
+                  (uint16_t)sl;
             }
           }
           count += __popc(m8);
@@ -579,15 +587,22 @@ __device__ __forceinline__ void build_nbr_body(const vec4_t<T>* __restrict__ pos
   __syncthreads();
   int32_t mymax = 0;
   double mysum = 0.0;
-  if (mode == 0)
-    build_rows<0, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
-                     mysum);
+  const bool staged = H <= g.build_cap;  // every halo slot in LDS
+  if (mode == 0 && staged)
+    build_rows<0, true, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
+                           mysum);
+  else if (mode == 0)
+    build_rows<0, false, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
+                            mysum);
+  else if (mode == 1 && staged)
+    build_rows<1, true, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
+                           mysum);
   else if (mode == 1)
-    build_rows<1, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
-                     mysum);
+    build_rows<1, false, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
+                            mysum);
   else
-    build_rows<2, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
-                     mysum);
+    build_rows<2, false, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
+                            mysum);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const int32_t v = __shfl_down(mymax, o, 64);
