@@ -438,7 +438,7 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
                                            int32_t kmax, int32_t* cnt, int32_t* err, const float4* hpos,
                                            const int32_t* hp, int32_t hb, int32_t ob, int32_t O, int32_t k0,
                                            int32_t k1,
-                                           int32_t hx, int32_t hxy, int32_t& mymax, double& mysum) {
+                                           int32_t hx, int32_t hxy, uint32_t wmask, int32_t& mymax, double& mysum) {
 #pragma clang fp contract(off)
   float Lf[3], iLf[3], Llo[3];
 #pragma unroll
@@ -494,9 +494,11 @@ __device__ __forceinline__ void build_rows(const vec4_t<T>* __restrict__ pos_s, 
             }
             float ex, ey, ez;
             if constexpr (MODE == 1) {
-              ex = mic(pj.x, pi.x, Lf[0], iLf[0], Llo[0]);
-              ey = mic(pj.y, pi.y, Lf[1], iLf[1], Llo[1]);
-              ez = mic(pj.z, pi.z, Lf[2], iLf[2], Llo[2]);
+              // the minimum image on the axes whose halo reaches a face; on
+              // the others it is the plain difference (k = 0 in mic)
+              ex = (wmask & 1u) ? mic(pj.x, pi.x, Lf[0], iLf[0], Llo[0]) : pj.x - pi.x;
+              ey = (wmask & 2u) ? mic(pj.y, pi.y, Lf[1], iLf[1], Llo[1]) : pj.y - pi.y;
+              ez = (wmask & 4u) ? mic(pj.z, pi.z, Lf[2], iLf[2], Llo[2]) : pj.z - pi.z;
             } else {
               ex = pj.x - pi.x;
               ey = pj.y - pi.y;
@@ -564,6 +566,7 @@ __device__ __forceinline__ void build_nbr_body(const vec4_t<T>* __restrict__ pos
   const bool live = b < g.nbricks;
   int32_t hb = 0, H = 0, ob = 0, O = 0, k0 = 0, k1 = 0, hx = 0, hxy = 0;
   int mode = 2;
+  uint32_t wmask = 0;  // axes on which the halo reaches a periodic face
   if (live) {
     const BrickShape s = brick_shape(b, g);
     hx = s.h[0];
@@ -576,6 +579,8 @@ __device__ __forceinline__ void build_nbr_body(const vec4_t<T>* __restrict__ pos
     k0 = part * share < O ? part * share : O;
     k1 = k0 + share < O ? k0 + share : O;
     mode = err[1] != 0 ? 2 : (halo_touches_face(s, g) ? 1 : 0);
+    for (int d = 0; d < 3; d++)
+      if (s.o[d] < 2 || s.o[d] + s.e[d] > g.nc[d] - 2) wmask |= 1u << d;
     const int nh = s.h[0] * s.h[1] * s.h[2];
     for (int h = threadIdx.x; h <= nh; h += blockDim.x) hp[h] = bi.hp[b * (kHaloCells + 1) + h];
     const int32_t ns = H < g.build_cap ? H : g.build_cap;
@@ -589,19 +594,19 @@ __device__ __forceinline__ void build_nbr_body(const vec4_t<T>* __restrict__ pos
   double mysum = 0.0;
   const bool staged = H <= g.build_cap;  // every halo slot in LDS
   if (mode == 0 && staged)
-    build_rows<0, true, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
+    build_rows<0, true, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, wmask, mymax,
                            mysum);
   else if (mode == 0)
-    build_rows<0, false, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
+    build_rows<0, false, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, wmask, mymax,
                             mysum);
   else if (mode == 1 && staged)
-    build_rows<1, true, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
+    build_rows<1, true, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, wmask, mymax,
                            mysum);
   else if (mode == 1)
-    build_rows<1, false, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
+    build_rows<1, false, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, wmask, mymax,
                             mysum);
   else
-    build_rows<2, false, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, mymax,
+    build_rows<2, false, T>(pos_s, cg, g, bi, rl2, nbr, kmax, cnt, err, hpos, hp, hb, ob, O, k0, k1, hx, hxy, wmask, mymax,
                             mysum);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
