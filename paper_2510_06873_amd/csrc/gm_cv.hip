@@ -19,8 +19,7 @@ namespace gm {
 struct Brick {
   int64_t b;
   int32_t hb, H, ob, O, ns;
-  bool wrap;     // pairs may cross a periodic face: minimum image needed
-  uint32_t axes;  // with wrap: the axes (bit d) on which they may
+  bool wrap;  // pairs may cross a periodic face: minimum image needed
 };
 
 template <typename T>
@@ -29,7 +28,6 @@ __device__ __forceinline__ Brick brick_begin(const CvArgs<T>& a, int64_t brick) 
   k.b = brick;
   k.hb = k.H = k.ob = k.O = k.ns = 0;
   k.wrap = true;
-  k.axes = 7u;
   if (k.b < a.bg.nbricks) {
     k.hb = a.bi.hb[k.b];
     k.H = a.bi.hb[k.b + 1] - k.hb;
@@ -38,13 +36,7 @@ __device__ __forceinline__ Brick brick_begin(const CvArgs<T>& a, int64_t brick) 
     k.ns = k.H < a.bg.cap ? k.H : a.bg.cap;
     // plain pair differences unless the halo touches a face or the gather
     // flagged a coordinate outside the box
-    const BrickShape sh = brick_shape(k.b, a.bg);
-    k.wrap = halo_touches_face(sh, a.bg) || a.err[1] != 0;
-    if (a.err[1] == 0) {
-      k.axes = 0u;
-      for (int d = 0; d < 3; d++)
-        if (sh.o[d] < 2 || sh.o[d] + sh.e[d] > a.bg.nc[d] - 2) k.axes |= 1u << d;
-    }
+    k.wrap = halo_touches_face(brick_shape(k.b, a.bg), a.bg) || a.err[1] != 0;
   }
   return k;
 }
@@ -473,7 +465,7 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
     for_slots<true>(nrow, cp, ps, first_chunk(nrow, cp), [&](int32_t s) {
       const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
       T dx, dy, dz;
-      const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz, k.axes);
+      const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
       if (r2 < a.rc2) {
         if (Q6)
           wr.push(s);
@@ -518,7 +510,7 @@ __device__ __forceinline__ double pass1_atoms(const CvArgs<T>& a, const Brick& k
       for_slots<true>(crow, nc, ps, first_chunk(crow, nc), [&](int32_t s) {
         const vec4_t<T> pj = fetch_pos<ALL>(a, k, lp, s);
         T dx, dy, dz;
-        const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz, k.axes);
+        const T r2 = pair_vec<WRAP>(pi, pj, a, dx, dy, dz);
         const T rinv = g_rsqrt(r2);
         const T r = r2 * rinv;
         T df;

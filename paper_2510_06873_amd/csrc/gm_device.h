@@ -74,15 +74,13 @@ __device__ __forceinline__ T mic(T xj, T xi, T L, T invL, T Llo) {
 // holds no cell on a periodic face while every coordinate lies in [0, L): no
 // listed pair can then cross a face, and the plain difference is the minimum
 // image.
-// With WRAP, `axes` (bit d for axis d, the same in every lane) names the axes
-// that take the minimum image; on the others it is the plain difference.
 template <bool WRAP, typename T>
 __device__ __forceinline__ T pair_vec(const vec4_t<T>& pi, const vec4_t<T>& pj, const CvArgs<T>& a,
-                                      T& dx, T& dy, T& dz, uint32_t axes = 7u) {
+                                      T& dx, T& dy, T& dz) {
   if constexpr (WRAP) {
-    dx = (axes & 1u) ? mic(pj.x, pi.x, a.L[0], a.invL[0], a.Llo[0]) : pj.x - pi.x;
-    dy = (axes & 2u) ? mic(pj.y, pi.y, a.L[1], a.invL[1], a.Llo[1]) : pj.y - pi.y;
-    dz = (axes & 4u) ? mic(pj.z, pi.z, a.L[2], a.invL[2], a.Llo[2]) : pj.z - pi.z;
+    dx = mic(pj.x, pi.x, a.L[0], a.invL[0], a.Llo[0]);
+    dy = mic(pj.y, pi.y, a.L[1], a.invL[1], a.Llo[1]);
+    dz = mic(pj.z, pi.z, a.L[2], a.invL[2], a.Llo[2]);
   } else {
     dx = pj.x - pi.x;
     dy = pj.y - pi.y;
