@@ -34,7 +34,7 @@ struct gm_ctx {
   int bias_blocks = 0;
 
   // cell list (canonical sorted order)
-  int32_t *cell = nullptr, *count = nullptr, *start = nullptr, *fill = nullptr, *perm = nullptr;
+  int32_t *cell = nullptr, *count = nullptr, *start = nullptr, *perm = nullptr;
   int32_t* scan_tmp = nullptr;  // tile sums of the prefix scans
   // bricks
   int32_t *brick_H = nullptr, *brick_O = nullptr, *brick_hb = nullptr, *brick_ob = nullptr, *brick_hp = nullptr;
@@ -54,7 +54,7 @@ struct gm_ctx {
   unsigned char* arena = nullptr;  // the fixed-size buffers below, carved from one allocation
   // buffers that grow or go together, one allocation each: the neighbour and
   // in-cutoff rows; the q-hat and adjoint rows; the cell tables (counts,
-  // starts, fill, scan tiles); the brick tables and per-workgroup partials
+  // starts, scan tiles); the brick tables and per-workgroup partials
   unsigned char *rows_blk = nullptr, *qg_blk = nullptr, *cells_blk = nullptr, *bricks_blk = nullptr;
   std::unordered_map<void*, size_t> held;  // device allocations of the context and their sizes
   size_t held_bytes = 0;
@@ -629,7 +629,7 @@ void free_all(gm_ctx* c) {
   c->part_a = c->part_b = nullptr;
   c->hill_count = nullptr;
   c->nbr = c->cut = nullptr;
-  c->count = c->start = c->fill = c->scan_tmp = nullptr;
+  c->count = c->start = c->scan_tmp = nullptr;
   c->brick_H = c->brick_O = c->brick_hb = c->brick_ob = c->brick_hp = nullptr;
   c->build_dev = nullptr;
   c->build_dev_ok = false;
@@ -842,8 +842,8 @@ int prepare_build(gm_ctx* c, const float* pos4, const double* box) {
     c->ncells_cap = 0;
     const int64_t tiles = (ncells + 1023) / 1024 + 1;  // tile sums of the prefix scans
     const Piece pieces[] = {{(void**)&c->count, (size_t)ncells * 4}, {(void**)&c->start, (size_t)(ncells + 1) * 4},
-                            {(void**)&c->fill, (size_t)ncells * 4}, {(void**)&c->scan_tmp, (size_t)tiles * 4}};
-    GM_TRY(carve(c, &c->cells_blk, pieces, 4));
+                            {(void**)&c->scan_tmp, (size_t)tiles * 4}};
+    GM_TRY(carve(c, &c->cells_blk, pieces, 3));
     c->ncells_cap = ncells;
   }
   c->ncells = ncells;
@@ -868,10 +868,11 @@ int enqueue_build(gm_ctx* c, const float* pos4, hipStream_t st) {
   const float4* p4 = reinterpret_cast<const float4*>(pos4);
   // cell counts, list statistics and the out-of-box flag (see the gather)
   GM_TRY(hip_rc(launch_reset_build(c->count, ncells, c->stats, c->err, st)));
-  GM_TRY(hip_rc(launch_cell_ids(p4, c->n, c->geom, c->cell, c->count, c->err, st)));
-  GM_TRY(hip_rc(launch_scan(c->count, ncells, c->start, c->fill, c->scan_tmp, st)));
-  // scatter into owned_rank (rewritten by the brick fill below), then rank
-  GM_TRY(hip_rc(launch_scatter(c->cell, c->n, c->start, c->fill, c->owned_rank, st)));
+  // each atom's slot in its cell goes to owned_slot and the scatter to
+  // owned_rank (both rewritten by the brick fill below), then the rank by id
+  GM_TRY(hip_rc(launch_cell_ids(p4, c->n, c->geom, c->cell, c->count, c->owned_slot, c->err, st)));
+  GM_TRY(hip_rc(launch_scan(c->count, ncells, c->start, nullptr, c->scan_tmp, st)));
+  GM_TRY(hip_rc(launch_scatter(c->cell, c->n, c->start, c->owned_slot, c->owned_rank, st)));
   GM_TRY(hip_rc(launch_rank_cells(c->cell, c->start, c->owned_rank, c->n, c->perm, st)));
   // bricks: halo and owned sizes, their prefix sums, the slot tables
   GM_TRY(hip_rc(launch_brick_count(c->start, c->bg, c->brick_H, c->brick_O, st)));
@@ -907,7 +908,7 @@ BuildArgs build_args(gm_ctx* c, const float* pos4) {
   a.cell = c->cell;
   a.count = c->count;
   a.start = c->start;
-  a.fill = c->fill;
+  a.slot = c->owned_slot;  // each atom's slot in its cell, rewritten by the brick fill
   a.perm = c->perm;
   a.scat = c->owned_rank;  // the scatter's output, rewritten by the brick fill
   a.stats = c->stats;

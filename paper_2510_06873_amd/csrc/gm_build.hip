@@ -72,21 +72,24 @@ __device__ __forceinline__ int32_t wave_count_add(int32_t* base, int32_t key) {
   return __shfl(old, leader, 64) + rank;
 }
 
+// Cell of atom i, its count, and its slot within the cell (the count it saw:
+// unique per atom, in arrival order), which the scatter uses after the scan.
 __device__ __forceinline__ void cell_ids_body(const float4* __restrict__ pos, int64_t n, const CellGeom& g,
-                                              int32_t* __restrict__ cell, int32_t* __restrict__ count, int32_t* err,
-                                              int64_t i) {
+                                              int32_t* __restrict__ cell, int32_t* __restrict__ count,
+                                              int32_t* __restrict__ slot, int32_t* err, int64_t i) {
   if (i >= n) return;
   int32_t c[3];
   if (!cell_coords(pos[i], g, c)) atomicOr(err, kErrNonFinite);
   int32_t id = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
   cell[i] = id;
-  (void)wave_count_add(count, id);
+  slot[i] = wave_count_add(count, id);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_ids(const float4* __restrict__ pos, int64_t n,
                                                      CellGeom g, int32_t* __restrict__ cell,
-                                                     int32_t* __restrict__ count, int32_t* err) {
-  cell_ids_body(pos, n, g, cell, count, err, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                                                     int32_t* __restrict__ count, int32_t* __restrict__ slot,
+                                                     int32_t* err) {
+  cell_ids_body(pos, n, g, cell, count, slot, err, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Exclusive prefix sum of n int32 values, out[n] = total, in three launches:
@@ -206,21 +209,19 @@ __global__ __launch_bounds__(kBlock) void k_reset_build(int32_t* __restrict__ co
 }
 
 __device__ __forceinline__ void scatter_body(const int32_t* __restrict__ cell, int64_t n,
-                                             const int32_t* __restrict__ start, int32_t* __restrict__ fill,
-                                             int32_t* __restrict__ perm, int64_t i) {
+                                             const int32_t* __restrict__ start, const int32_t* __restrict__ slot,
+                                             int32_t* __restrict__ scat, int64_t i) {
   if (i >= n) return;
-  const int32_t c = cell[i];
-  const int32_t slot = wave_count_add(fill, c);
-  perm[start[c] + slot] = (int32_t)i;
+  scat[start[cell[i]] + slot[i]] = (int32_t)i;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(const int32_t* __restrict__ cell, int64_t n,
                                                     const int32_t* __restrict__ start,
-                                                    int32_t* __restrict__ fill, int32_t* __restrict__ perm) {
-  scatter_body(cell, n, start, fill, perm, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                                                    const int32_t* __restrict__ slot, int32_t* __restrict__ scat) {
+  scatter_body(cell, n, start, slot, scat, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// The atomic scatter leaves each cell's atoms in arbitrary order; placing each
+// The scatter leaves each cell's atoms in arrival order; placing each
 // atom at its rank by id within its cell's segment makes the permutation the
 // unique stable order.  One thread per atom counts the smaller ids of its
 // segment (the segment's reads are shared by its atoms and cached), so dense
@@ -666,18 +667,18 @@ __global__ __launch_bounds__(kBlock) void k_reset_build_b(BuildSubset s) {
 
 __global__ __launch_bounds__(kBlock) void k_cell_ids_b(BuildSubset s) {
   GM_SUBSET_BEGIN(s, blockIdx.x)
-  cell_ids_body(A.ga.pos, A.n, A.cg, A.cell, A.count, A.err, blk * blockDim.x + threadIdx.x);
+  cell_ids_body(A.ga.pos, A.n, A.cg, A.cell, A.count, A.slot, A.err, blk * blockDim.x + threadIdx.x);
 }
 
 __global__ __launch_bounds__(kScanTile) void k_scan_cells_b(BuildSubset s) {
   __shared__ int32_t lds[kScanTile];
   GM_SUBSET_BEGIN(s, blockIdx.x)
-  scan_small_one(A.count, A.ncells, A.start, A.fill, lds);
+  scan_small_one(A.count, A.ncells, A.start, nullptr, lds);
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter_b(BuildSubset s) {
   GM_SUBSET_BEGIN(s, blockIdx.x)
-  scatter_body(A.cell, A.n, A.start, A.fill, A.scat, blk * blockDim.x + threadIdx.x);
+  scatter_body(A.cell, A.n, A.start, A.slot, A.scat, blk * blockDim.x + threadIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_rank_cells_b(BuildSubset s) {
@@ -795,8 +796,8 @@ hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s
 }
 
 hipError_t launch_cell_ids(const float4* pos, int64_t n, const CellGeom& g, int32_t* cell, int32_t* count,
-                           int32_t* err, hipStream_t st) {
-  k_cell_ids<<<grid_of(n, kBlock), kBlock, 0, st>>>(pos, n, g, cell, count, err);
+                           int32_t* slot, int32_t* err, hipStream_t st) {
+  k_cell_ids<<<grid_of(n, kBlock), kBlock, 0, st>>>(pos, n, g, cell, count, slot, err);
   return hipGetLastError();
 }
 
@@ -829,9 +830,9 @@ hipError_t launch_reset_build(int32_t* count, int64_t ncells, int32_t* stats, in
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const int32_t* cell, int64_t n, const int32_t* start, int32_t* fill, int32_t* perm,
+hipError_t launch_scatter(const int32_t* cell, int64_t n, const int32_t* start, const int32_t* slot, int32_t* scat,
                           hipStream_t st) {
-  k_scatter<<<grid_of(n, kBlock), kBlock, 0, st>>>(cell, n, start, fill, perm);
+  k_scatter<<<grid_of(n, kBlock), kBlock, 0, st>>>(cell, n, start, slot, scat);
   return hipGetLastError();
 }
 

@@ -181,7 +181,7 @@ struct BuildArgs {
   BrickGeom bg;
   BrickIndex bi;
   int64_t n, ncells;
-  int32_t *cell, *count, *start, *fill, *perm, *scat, *stats, *err;
+  int32_t *cell, *count, *start, *slot, *perm, *scat, *stats, *err;
   int32_t *brick_H, *brick_O, *brick_hb, *brick_ob, *brick_hp, *halo_rank, *owned_slot, *owned_rank, *owned_hcell;
   uint16_t* nbr;
   int32_t* cnt;
@@ -202,14 +202,14 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 // multiple of 4) through kernel arguments; src may be freed on return.
 hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t st);
 hipError_t launch_cell_ids(const float4* pos, int64_t n, const CellGeom& g, int32_t* cell,
-                           int32_t* count, int32_t* err, hipStream_t st);
+                           int32_t* count, int32_t* slot, int32_t* err, hipStream_t st);
 // tmp: device int32[(n + 1023)/1024] scratch for the tile sums
 hipError_t launch_scan(const int32_t* in, int64_t n, int32_t* out, int32_t* zero, int32_t* tmp, hipStream_t st);
 hipError_t launch_scan2(const int32_t* in0, int32_t* out0, const int32_t* in1, int32_t* out1, int64_t n,
                         int32_t* tmp, hipStream_t st);
 hipError_t launch_reset_build(int32_t* count, int64_t ncells, int32_t* stats, int32_t* err, hipStream_t st);
-hipError_t launch_scatter(const int32_t* cell, int64_t n, const int32_t* start, int32_t* fill,
-                          int32_t* perm, hipStream_t st);
+hipError_t launch_scatter(const int32_t* cell, int64_t n, const int32_t* start, const int32_t* slot,
+                          int32_t* scat, hipStream_t st);
 // perm[start[c] + rank] = atom: each cell's atoms of `scattered` in id order.
 hipError_t launch_rank_cells(const int32_t* cell, const int32_t* start, const int32_t* scattered, int64_t n,
                              int32_t* perm, hipStream_t st);
