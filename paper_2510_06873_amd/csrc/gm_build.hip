@@ -378,27 +378,22 @@ __device__ __forceinline__ void brick_fill_body(const int32_t* __restrict__ star
   __syncthreads();
   int32_t* hp = hp_out + b * (kHaloCells + 1);
   for (int h = threadIdx.x; h <= nh; h += blockDim.x) hp[h] = hpre[h];
-  const int32_t hb = bi.hb[b], H = bi.hb[b + 1] - hb;
-  for (int32_t sl = threadIdx.x; sl < H; sl += blockDim.x) {
-    int lo = 0, hi = nh;  // find h with hpre[h] <= sl < hpre[h+1]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (hpre[mid] <= sl) lo = mid; else hi = mid;
-    }
-    halo_rank[hb + sl] = start[hcell[lo]] + (sl - hpre[lo]);
+  // thread t writes the slots of halo cell t, then of owned cell t (each cell's
+  // atoms are consecutive in sorted order from start[cell])
+  const int32_t hb = bi.hb[b];
+  if (t < nh) {
+    const int32_t s0 = start[hcell[t]], base = hb + hpre[t];
+    for (int32_t j = 0; j < ch; j++) halo_rank[base + j] = s0 + j;
   }
-  const int32_t ob = bi.ob[b], O = bi.ob[b + 1] - ob;
-  for (int32_t k = threadIdx.x; k < O; k += blockDim.x) {
-    int lo = 0, hi = no;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (opre[mid] <= k) lo = mid; else hi = mid;
+  const int32_t ob = bi.ob[b];
+  if (t < no) {
+    const int h = oh[t];
+    const int32_t s0 = start[hcell[h]], slot0 = hpre[h], base = ob + opre[t];
+    for (int32_t j = 0; j < co; j++) {
+      owned_slot[base + j] = slot0 + j;
+      owned_rank[base + j] = s0 + j;
+      owned_hcell[base + j] = h;
     }
-    const int h = oh[lo];
-    const int32_t idx = k - opre[lo];
-    owned_slot[ob + k] = hpre[h] + idx;
-    owned_rank[ob + k] = start[hcell[h]] + idx;
-    owned_hcell[ob + k] = h;
   }
 }
 
